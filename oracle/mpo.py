@@ -1,0 +1,398 @@
+"""Dense Vidal-form MPO of a lossy GBS state (oracle, FP64, no charge blocking).
+
+Test infrastructure only (see ``oracle/__init__``).
+
+Representation (Sec. II, Eq. MPS and the vectorisation map; App. D):
+the vectorised density operator |rho>> = sum rho[k, k'] |k, k'> is written as
+
+    Psi[alpha_0; (m_1, m'_1), ..., (m_M, m'_M)] =
+        lam_0 G_0 lam_1 G_1 ... G_{M-1} lam_M
+
+with site tensors G_j[a, m, m', b] (a on bond j, b on bond j+1, ket m, bra m')
+and Schmidt values lam_b on bonds b = 0..M.  Bond 0 is an auxiliary left leg
+whose index carries the total photon numbers, because "the left-most charge is
+the sum of all photons" (App. A); the physical state is the sum over that leg.
+Charges c_b = (photons, photons') to the right of bond b (App. D) are carried
+only as labels: every tensor here is dense and every contraction and SVD runs
+on the full dense matrices.
+
+Two-site update (App. D, Eq. Theta and the SVD that follows):
+Theta = lam_{j} G_j lam_{j+1} G_{j+1} lam_{j+2}, the Fock beam splitter
+U (x) conj(U) acts on the four local indices (Sec. II, vectorised unitary),
+the dense SVD is truncated to chi, and G~_j = V / lam_j, G~_{j+1} = W^dag /
+lam_{j+2}.
+
+Truncation rule (the paper only says "keep the chi largest"; readings):
+* singular values below 1e-14 of the largest are dropped (rank cut-off);
+* Hermiticity makes the spectra of mirror charges (n, n') and (n', n)
+  identical, so the i-th value of a sector and the i-th value of its mirror
+  form one unit of size 2; a self-mirror sector gives units of size 1;
+* units are taken by decreasing value (ties: canonical charge, then rank)
+  while the running size stays <= chi; the first unit that does not fit ends
+  the selection;
+* the new bond is ordered by charge (lexicographic) then by decreasing value.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import fock
+
+RANK_CUT = 1e-14
+
+
+# --------------------------------------------------------------------------
+# truncation rule
+# --------------------------------------------------------------------------
+def select(charges: np.ndarray, vals: np.ndarray, chi: int) -> np.ndarray:
+    """Indices kept by the mirror-pair rule, ordered by (charge, -value)."""
+    vals = np.asarray(vals, dtype=float)
+    if len(vals) == 0:
+        return np.zeros(0, dtype=int)
+    vmax = vals.max()
+    groups: dict[tuple, list[int]] = {}
+    for idx in range(len(vals)):
+        if vals[idx] >= RANK_CUT * vmax and vals[idx] > 0:
+            groups.setdefault((int(charges[idx][0]), int(charges[idx][1])), []).append(idx)
+    for q in groups:
+        groups[q].sort(key=lambda i: (-vals[i], i))
+    units = []
+    for q, members in groups.items():
+        qb = (q[1], q[0])
+        if q == qb:
+            for i, idx in enumerate(members):
+                units.append((vals[idx], q, i, [idx]))
+        elif q < qb:
+            partner = groups.get(qb, [])
+            for i in range(max(len(members), len(partner))):
+                mem = ([members[i]] if i < len(members) else []) + \
+                      ([partner[i]] if i < len(partner) else [])
+                units.append((max(vals[m] for m in mem), q, i, mem))
+        elif qb not in groups:
+            for i, idx in enumerate(members):
+                units.append((vals[idx], qb, i, [idx]))
+    units.sort(key=lambda u: (-u[0], u[1], u[2]))
+    kept: list[int] = []
+    for u in units:
+        if len(kept) + len(u[3]) > chi:
+            break
+        kept.extend(u[3])
+    kept.sort(key=lambda i: (int(charges[i][0]), int(charges[i][1]), -vals[i], i))
+    return np.array(kept, dtype=int)
+
+
+# --------------------------------------------------------------------------
+# charge labels of dense singular vectors
+# --------------------------------------------------------------------------
+def _label_rows(Wh: np.ndarray, S: np.ndarray, col_charge: np.ndarray, V: np.ndarray):
+    """Give every right singular vector (row of Wh) a definite charge.
+
+    The dense SVD of a charge-block-diagonal matrix returns charge-definite
+    vectors for non-degenerate values; inside a (near-)degenerate cluster it
+    may return any rotation.  Inside each cluster the vectors are rotated to
+    diagonalise the charge operator, which is exactly diagonal on the
+    column basis.  Returns (labels, V, Wh) with V and Wh rotated consistently.
+    """
+    k = len(S)
+    if k == 0:
+        return np.zeros((0, 2), dtype=int), V, Wh
+    keys = col_charge[:, 0].astype(np.int64) * 100003 + col_charge[:, 1].astype(np.int64)
+    tol = 1e-11 * S[0]
+    start = 0
+    V = V.copy()
+    Wh = Wh.copy()
+    while start < k:
+        end = start + 1
+        while end < k and S[end - 1] - S[end] <= tol:
+            end += 1
+        if end - start > 1:
+            blk = Wh[start:end]
+            w = np.abs(blk) ** 2
+            support = np.unique(keys[w.sum(axis=0) > 1e-12])
+            f = np.zeros(len(keys))
+            for rank, key in enumerate(support):
+                f[keys == key] = rank + 1.0
+            H = (blk * f[None, :]) @ blk.conj().T
+            _, R = np.linalg.eigh(H)
+            Wh[start:end] = R.conj().T @ blk
+            V[:, start:end] = V[:, start:end] @ R
+        start = end
+    labels = np.zeros((k, 2), dtype=int)
+    for i in range(k):
+        w = np.abs(Wh[i]) ** 2
+        tot = w.sum()
+        uk, inv = np.unique(keys, return_inverse=True)
+        acc = np.bincount(inv, weights=w, minlength=len(uk))
+        best = int(np.argmax(acc))
+        if acc[best] < (1 - 1e-6) * tot:
+            raise RuntimeError("charge labelling failed: vector is not charge-definite")
+        col = np.nonzero(inv == best)[0][0]
+        labels[i] = col_charge[col]
+    return labels, V, Wh
+
+
+# --------------------------------------------------------------------------
+# the MPO
+# --------------------------------------------------------------------------
+class DenseMPO:
+    """Dense Vidal MPO with an auxiliary total-charge leg on bond 0."""
+
+    def __init__(self, G, lam, charge, d):
+        self.G = G            # list of M arrays (Dl, d, d, Dr), complex
+        self.lam = lam        # list of M+1 real arrays
+        self.charge = charge  # list of M+1 int arrays (D, 2)
+        self.d = d
+
+    @property
+    def M(self):
+        return len(self.G)
+
+    # ---------------- initial state ----------------
+    @classmethod
+    def product(cls, rhos, chi: int):
+        """Initial state by its definition: the exact Vidal form of the product
+        rho_1 (x) ... (x) rho_M with the auxiliary total-charge leg, written
+        out from the Schmidt decomposition of a product state on every bond
+        (one Schmidt vector per right charge q), then the top-chi
+        (mirror-pair rule) charges kept on every bond without re-canonicalising.
+
+        With A_b = prod_{i<b} ||rho_i||_F and w_b(q) the weight of charge q in
+        (x)_{i>=b} rho_i (2-D convolution of |rho_i|^2):
+        lam_b[q] = A_b sqrt(w_b(q)) and
+        G_j[q', m, m', q] = rho_j[m, m'] delta(q' = q + (m, m')) / (A_{j+1} sqrt(w_j(q'))).
+        ``product_by_sweeps`` obtains the same state by dense SVD sweeps.
+        """
+        M = len(rhos)
+        d = rhos[0].shape[0]
+        lam_d = product_lambdas(rhos)
+        A = [1.0]
+        for j in range(M):
+            A.append(A[-1] * float(np.linalg.norm(rhos[j])))
+        charge = [np.array(sorted(ld.keys()), dtype=int).reshape(-1, 2) for ld in lam_d]
+        lam = [np.array([lam_d[b][tuple(q)] for q in charge[b]]) for b in range(M + 1)]
+        G = []
+        for j in range(M):
+            idx = {tuple(q): i for i, q in enumerate(charge[j])}
+            T = np.zeros((len(charge[j]), d, d, len(charge[j + 1])), dtype=complex)
+            for qi, q in enumerate(charge[j + 1]):
+                for m in range(d):
+                    for mp in range(d):
+                        key = (int(q[0]) + m, int(q[1]) + mp)
+                        if rhos[j][m, mp] != 0 and key in idx:
+                            a = idx[key]
+                            wq = (lam[j][a] / A[j]) ** 2
+                            T[a, m, mp, qi] = rhos[j][m, mp] / (A[j + 1] * math.sqrt(wq))
+            G.append(T)
+        mpo = cls(G, lam, charge, d)
+        mpo.truncate_all(chi)
+        return mpo
+
+    @classmethod
+    def product_by_sweeps(cls, rhos, chi: int):
+        """Vidal form of rho_1 (x) ... (x) rho_M by dense sweeps, then the top-chi
+        (mirror-pair rule) charges kept on every bond, without re-canonicalising.
+        Small sizes only: the dense SVD cannot resolve the vectors of Schmidt
+        values far below the largest one.
+
+        The charge-bond tensor B_j[q', m, m', q] = rho_j[m, m'] delta(q' = q + (m, m'))
+        is the U(1) product MPO (App. D, the delta form of the MPS); the
+        sweeps (QR left to right, SVD right to left) bring it to Vidal form
+        exactly as for any MPS (App. D, Eq. MPS in Vidal form).
+        """
+        M = len(rhos)
+        d = rhos[0].shape[0]
+        # reachable charges, counted from the right
+        ch = [None] * (M + 1)
+        ch[M] = [(0, 0)]
+        for b in range(M - 1, -1, -1):
+            s = set()
+            nz = np.argwhere(rhos[b] != 0)
+            for q in ch[b + 1]:
+                for (m, mp) in nz:
+                    s.add((q[0] + int(m), q[1] + int(mp)))
+            ch[b] = sorted(s)
+        index = [{q: i for i, q in enumerate(c)} for c in ch]
+        B = []
+        for j in range(M):
+            T = np.zeros((len(ch[j]), d, d, len(ch[j + 1])), dtype=complex)
+            for qi, q in enumerate(ch[j + 1]):
+                for m in range(d):
+                    for mp in range(d):
+                        if rhos[j][m, mp] != 0:
+                            T[index[j][(q[0] + m, q[1] + mp)], m, mp, qi] = rhos[j][m, mp]
+            B.append(T)
+        # left-canonicalise; bond 0 is an open leg (the auxiliary total charge)
+        A = [t.copy() for t in B]
+        for j in range(M - 1):
+            Dl, _, _, Dr = A[j].shape
+            Q, R = np.linalg.qr(A[j].reshape(Dl * d * d, Dr))
+            A[j] = Q.reshape(Dl, d, d, Q.shape[1])
+            A[j + 1] = np.tensordot(R, A[j + 1], axes=(1, 0))
+        norm = np.linalg.norm(A[M - 1])
+        lam = [None] * (M + 1)
+        charge = [None] * (M + 1)
+        Bright = [None] * M
+        lam[M] = np.array([norm])
+        charge[M] = np.array([[0, 0]])
+        C = A[M - 1]
+        aux_charge = np.array(ch[0])
+        for j in range(M - 1, -1, -1):
+            Dl, _, _, Dr = C.shape
+            X = C.reshape(Dl, d * d * Dr)
+            U_, S, Vh = np.linalg.svd(X, full_matrices=False)
+            keep = S >= RANK_CUT * S[0]
+            U_, S, Vh = U_[:, keep], S[keep], Vh[keep]
+            col_charge = np.zeros((d, d, Dr, 2), dtype=int)
+            for m in range(d):
+                for mp in range(d):
+                    col_charge[m, mp, :, 0] = charge[j + 1][:, 0] + m
+                    col_charge[m, mp, :, 1] = charge[j + 1][:, 1] + mp
+            labels, U_, Vh = _label_rows(Vh, S, col_charge.reshape(-1, 2), U_)
+            Bright[j] = Vh.reshape(len(S), d, d, Dr)
+            lam[j] = S
+            charge[j] = labels
+            if j > 0:
+                C = np.tensordot(A[j - 1], U_ * S[None, :], axes=(3, 0))
+            else:
+                # bond 0: the left Schmidt vectors are aux basis states |Q>;
+                # absorb their phases so that index alpha_0 is exactly |Q>.
+                for a in range(len(S)):
+                    qa = int(np.argmax(np.abs(U_[:, a])))
+                    if abs(abs(U_[qa, a]) - 1) > 1e-8 or tuple(aux_charge[qa]) != tuple(labels[a]):
+                        raise RuntimeError("bond-0 Schmidt vector is not an aux basis state")
+                    Bright[0][a] *= U_[qa, a]
+        G = []
+        for j in range(M):
+            G.append(Bright[j] / lam[j + 1][None, None, None, :])
+        mpo = cls(G, lam, charge, d)
+        mpo.truncate_all(chi)
+        return mpo
+
+    def truncate_all(self, chi: int):
+        """Keep the top-chi (mirror-pair rule) indices on every bond, no
+        re-canonicalisation (initial-state truncation)."""
+        keep = [select(self.charge[b], self.lam[b], chi) for b in range(self.M + 1)]
+        for b in range(self.M + 1):
+            self.lam[b] = self.lam[b][keep[b]]
+            self.charge[b] = self.charge[b][keep[b]]
+        for j in range(self.M):
+            self.G[j] = self.G[j][keep[j]][:, :, :, keep[j + 1]]
+
+    # ---------------- gates ----------------
+    def apply_gate(self, m: int, theta: float, phi: float, chi: int):
+        """Beam splitter T(theta, phi) on modes (m, m+1): App. D two-site update."""
+        d = self.d
+        j = m
+        A, B = self.G[j], self.G[j + 1]
+        lL, lC, lR = self.lam[j], self.lam[j + 1], self.lam[j + 2]
+        Theta = np.einsum('a,aikc,c,cjlb,b->aikjlb', lL, A, lC, B, lR, optimize=True)
+        Uf = fock.fock_bs(fock.bs_matrix(theta, phi), d)        # [I, J, i, j]
+        # vectorised unitary U (x) conj(U) on (ket, bra) of both modes
+        Theta = np.einsum('IJij,KLkl,aikjlb->aIKJLb', Uf, Uf.conj(), Theta, optimize=True)
+        Dl, Dr = len(lL), len(lR)
+        X = Theta.reshape(Dl * d * d, d * d * Dr)
+        V, S, Wh = np.linalg.svd(X, full_matrices=False)
+        keep = S >= RANK_CUT * S[0] if len(S) and S[0] > 0 else np.zeros(len(S), bool)
+        V, S, Wh = V[:, keep], S[keep], Wh[keep]
+        col_charge = np.zeros((d, d, Dr, 2), dtype=int)
+        cR = self.charge[j + 2]
+        for J in range(d):
+            for L in range(d):
+                col_charge[J, L, :, 0] = cR[:, 0] + J
+                col_charge[J, L, :, 1] = cR[:, 1] + L
+        labels, V, Wh = _label_rows(Wh, S, col_charge.reshape(-1, 2), V)
+        kept = select(labels, S, chi)
+        S = S[kept]
+        V = V[:, kept].reshape(Dl, d, d, len(kept))
+        Wh = Wh[kept].reshape(len(kept), d, d, Dr)
+        self.G[j] = V / lL[:, None, None, None]
+        self.G[j + 1] = Wh / lR[None, None, None, :]
+        self.lam[j + 1] = S
+        self.charge[j + 1] = labels[kept]
+
+    def apply_phases(self, phases):
+        """Output phase screen D: |n> -> e^{i n phi}|n> on every mode, i.e.
+        rho[m, m'] -> e^{i phi (m - m')} rho[m, m'] (Sec. II, vectorised unitary)."""
+        d = self.d
+        n = np.arange(d)
+        for j, ph in enumerate(phases):
+            f = np.exp(1j * ph * (n[:, None] - n[None, :]))
+            self.G[j] = self.G[j] * f[None, :, :, None]
+
+    # ---------------- readouts ----------------
+    def entropies(self):
+        """Operator EE on bonds 1..M-1, in bits, with p = lam^2 / sum lam^2
+        (Sec. II EE definition; App. B normalisation and log base 2)."""
+        out = []
+        for b in range(1, self.M):
+            p = self.lam[b] ** 2
+            p = p / p.sum()
+            p = p[p > 0]
+            out.append(float(-(p * np.log2(p)).sum()))
+        return np.array(out)
+
+    def marginals(self):
+        """(P[j, n] = Tr(rho Pi_{j,n}) / Tr rho, Tr rho, raw Tr(rho Pi)).
+
+        The trace contracts every site with the identity (local m = m') and
+        the auxiliary leg with the all-ones vector; 1 - Tr rho is the paper's
+        error proxy (Sec. I, Sec. III, App. A)."""
+        M, d = self.M, self.d
+        diag = [np.einsum('ammb->amb', g) for g in self.G]     # (Dl, d, Dr)
+        E = [None] * (M + 1)
+        E[M] = np.ones(1, dtype=complex)
+        for j in range(M - 1, -1, -1):
+            E[j] = np.einsum('amb,b,b->a', diag[j], self.lam[j + 1], E[j + 1])
+        L = [None] * (M + 1)
+        L[0] = np.ones(len(self.lam[0]), dtype=complex)
+        for j in range(M):
+            L[j + 1] = np.einsum('a,a,amb->b', L[j], self.lam[j], diag[j])
+        raw = np.zeros((M, d))
+        for j in range(M):
+            v = np.einsum('a,a,amb,b,b->m', L[j], self.lam[j], diag[j],
+                          self.lam[j + 1], E[j + 1])
+            raw[j] = v.real
+        tr = float(np.sum(L[0] * self.lam[0] * E[0]).real)
+        return raw / tr, tr, raw
+
+    def to_dense(self):
+        """Full rho as a tensor [m_1..m_M, m'_1..m'_M] (sums the aux leg)."""
+        M, d = self.M, self.d
+        T = np.diag(self.lam[0]).astype(complex)   # (aux, bond 0)
+        for j in range(M):
+            g = self.G[j] * self.lam[j + 1][None, None, None, :]
+            T = np.tensordot(T, g, axes=(T.ndim - 1, 0))
+        T = T.sum(axis=0)                          # sum over the aux leg
+        T = T[..., 0]                              # bond M has one index
+        perm = [2 * i for i in range(M)] + [2 * i + 1 for i in range(M)]
+        return np.transpose(T, perm)
+
+
+def product_lambdas(rhos):
+    """Closed form of the untruncated product-state Schmidt values with the
+    auxiliary leg: lam_b[q]^2 = (prod_{j<b} ||rho_j||_F^2) * w_b(q) where w_b is
+    the 2-D convolution of |rho_j|^2 over modes j >= b (App. D charges;
+    derivation in the design notes).  Returns per bond a dict {q: lam}."""
+    M = len(rhos)
+    d = rhos[0].shape[0]
+    w = [None] * (M + 1)
+    w[M] = {(0, 0): 1.0}
+    for b in range(M - 1, -1, -1):
+        acc: dict[tuple, float] = {}
+        a2 = np.abs(rhos[b]) ** 2
+        for q, v in w[b + 1].items():
+            for m in range(d):
+                for mp in range(d):
+                    if a2[m, mp] != 0:
+                        key = (q[0] + m, q[1] + mp)
+                        acc[key] = acc.get(key, 0.0) + v * a2[m, mp]
+        w[b] = acc
+    out = []
+    A2 = 1.0
+    for b in range(M + 1):
+        out.append({q: math.sqrt(A2 * v) for q, v in w[b].items() if v > 0})
+        if b < M:
+            A2 *= float((np.abs(rhos[b]) ** 2).sum())
+    return out
