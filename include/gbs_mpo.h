@@ -1,0 +1,183 @@
+/*
+ * gbs_mpo.h -- C ABI of the MI355X (gfx950) lossy Gaussian boson sampling
+ * matrix-product-operator simulator.
+ *
+ * Method: Liu, Oh, Liu, Jiang, Alexeev, "Simulating lossy Gaussian boson
+ * sampling with matrix product operators" (arXiv 2301.12814).
+ *
+ * State.  The vectorised density operator |rho>> (Sec. II, vectorisation map)
+ * of M optical modes is held in U(1)-symmetric Vidal form (App. D, charged
+ * MPS): site matrices Gamma_j (mode j, no physical index), Schmidt values
+ * lam_b and photon-number charges c_b = (n, n') on bonds b = 0..M, where
+ * c_b counts the ket and bra photons in modes b..M-1 (App. D, "particles to
+ * the right").  Bond 0 is an auxiliary leg that carries the total photon
+ * numbers ("the left-most charge is the sum of all photons", App. A).
+ * Each mode has a per-mode Fock cutoff d (local index [0, d)^2, ket x bra).
+ *
+ * Conventions.
+ *   * Modes are 0-based.  A gate "on left_site k" acts on modes (k, k+1).
+ *   * Beam splitter T(theta, phi) = [[e^{i phi} cos t, -sin t],
+ *                                    [e^{i phi} sin t,  cos t]],
+ *     acting on creation operators as a^dag_j -> sum_i T[i][j] a^dag_i
+ *     (App. B, creation-operator transform); rho -> U rho U^dag.
+ *   * Truncation: singular values below 1e-14 of the largest are dropped;
+ *     the i-th values of mirror charges (n, n') and (n', n) form one unit of
+ *     size 2 (Hermiticity makes the spectra equal), self-mirror charges give
+ *     units of size 1; units are kept by decreasing value (ties: charge, then
+ *     rank) while the running size stays <= chi.  New bonds are ordered by
+ *     charge, then by decreasing value.
+ *
+ * Ownership.  The caller owns every host buffer: inputs are read before the
+ * call returns, outputs are written to caller memory.  A handle owns all its
+ * device memory until mpo_free.  A handle is not thread-safe; distinct handles
+ * may be used from distinct threads on distinct streams.
+ *
+ * Errors.  Every call returns MPO_OK or a negative code and sets a
+ * thread-local message (mpo_last_error).  Argument errors leave the state
+ * unchanged.  mpo_apply_bs_layer only enqueues device work; a numerical
+ * failure found on the device (non-converged SVD, non-finite values,
+ * workspace overflow) is latched and returned by the next synchronising call
+ * (mpo_entropy, mpo_photon_marginals, mpo_sync, mpo_get_bond).
+ */
+#ifndef GBS_MPO_H
+#define GBS_MPO_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gbs_mpo gbs_mpo;
+
+enum {
+  MPO_OK = 0,
+  MPO_EINVAL = -1,   /* invalid argument; state unchanged                    */
+  MPO_ENOMEM = -2,   /* projected device memory exceeds the budget / alloc   */
+  MPO_EDEVICE = -3,  /* HIP runtime error                                    */
+  MPO_ENUMERIC = -4, /* latched device-side numerical failure                */
+  MPO_EBUSY = -5
+};
+
+enum { MPO_FP64 = 0, MPO_MIXED = 1 };
+
+/*
+ * Initial lossy squeezed product state (Sec. II: uniform loss commutes with
+ * the interferometer and is applied to the input; App. C: squeezed-vacuum
+ * wavefunction; App. B: pure-loss Kraus operators).
+ *   M        number of modes, M >= 2
+ *   r        host array [M], squeezing per mode, r >= 0 (0 = vacuum input)
+ *   eta      uniform transmission, 0 < eta <= 1
+ *   d        per-mode Fock cutoff, 2 <= d <= 16
+ *   chi      bond dimension, 1 <= chi <= 4096
+ *   precision MPO_FP64 or MPO_MIXED (split-bf16 sector contractions)
+ *   hip_stream  hipStream_t to run on, or NULL for a stream owned by the handle
+ *   out      receives the new handle
+ * Each mode's state is built in a large internal Fock space, lossy, then
+ * cropped to [0, d)^2 (no renormalisation).  The exact product Vidal form is
+ * truncated to the top-chi charges of every bond by the rule above.
+ */
+int mpo_init_lossy_squeezed(int M, const double *r, double eta, int d, int chi,
+                            int precision, void *hip_stream, gbs_mpo **out);
+
+/*
+ * One layer of disjoint nearest-neighbour beam splitters (App. D two-site
+ * update with charge-blocked Theta(c), Eq. theta; per-sector SVD truncated to
+ * chi; App. D.5 block SVD).  Gates must be disjoint: no two share a mode.
+ *   left_site[g] in [0, M-2]; theta[g], phi[g] as in T(theta, phi).
+ * Enqueues device work only.  Also updates the operator EE of each updated
+ * bond and the running maximum.
+ */
+int mpo_apply_bs_layer(gbs_mpo *h, int n_gates, const int *left_site,
+                       const double *theta, const double *phi);
+
+/* Output phase screen D: |n> -> e^{i n phase[j]} |n> on every mode j (any local
+ * unitary of the vectorised map, Sec. II).  Leaves lam, charges, EE unchanged. */
+int mpo_apply_phases(gbs_mpo *h, const double *phase);
+
+/*
+ * Operator entanglement entropy S_b = -sum p log2 p, p = lam^2 / sum lam^2
+ * (Sec. II EE definition; App. B explicit normalisation, log base 2) on the
+ * internal bonds b = 1..M-1.  S: host array [M-1]; S_max_so_far (nullable)
+ * receives the maximum over bonds and over every layer applied so far.
+ * Synchronises the handle's stream.
+ */
+int mpo_entropy(gbs_mpo *h, double *S, double *S_max_so_far);
+
+/*
+ * Photon-number marginals P[j*d + n] = Tr(rho Pi_{j,n}) / Tr rho and the trace
+ * Tr rho (nullable), whose deficit 1 - Tr rho is the paper's error proxy
+ * (Sec. III; App. A).  The trace contracts every site with the identity and
+ * the auxiliary leg with the all-ones vector.  P: host array [M*d].
+ * Synchronises the handle's stream.
+ */
+int mpo_photon_marginals(gbs_mpo *h, double *P, double *trace);
+
+/* Waits for the handle's queued work; returns a latched device error if any. */
+int mpo_sync(gbs_mpo *h);
+
+/*
+ * Inspection of bond b in 0..M (synchronises).  dim receives the bond size D;
+ * lam [chi] and charges [2*chi] (n, n' pairs, nullable) receive the first D
+ * entries, ordered by charge then decreasing value.
+ */
+int mpo_get_bond(gbs_mpo *h, int b, int *dim, double *lam, int *charges);
+
+/*
+ * Copy of site matrix Gamma_j (j in 0..M-1), D_j x D_{j+1}, row-major,
+ * interleaved (re, im) doubles, into host buffer G [2 * chi * chi]
+ * (leading dimension D_{j+1}).  Synchronises.
+ */
+int mpo_get_site(gbs_mpo *h, int j, double *G);
+
+/*
+ * Per-layer statistics of the last applied layer (synchronises):
+ * stats[0] = number of sector blocks, stats[1] = sum over blocks of r*s,
+ * stats[2] = sum of candidate singular values, stats[3] = largest block rows,
+ * stats[4] = largest block cols, stats[5] = Jacobi sweeps of the slowest block.
+ */
+int mpo_layer_stats(gbs_mpo *h, long long *stats);
+
+/*
+ * Phase profiling (tracing).  mpo_set_profiling(h, 1) enables HIP events
+ * around each phase of every subsequent layer and resets the accumulators
+ * (0 disables).  Synchronises.
+ */
+int mpo_set_profiling(gbs_mpo *h, int enable);
+
+/*
+ * Accumulated profile since profiling was enabled (synchronises):
+ *   phase_ms[8] (nullable): summed device time per phase, in milliseconds:
+ *     0 Fock tables, 1 sector planning, 2 Theta contraction, 3 block SVD,
+ *     4 truncation select, 5 zero + scatter, 6 entropy, 7 unused
+ *   phase_launches[8] (nullable): layers timed per phase
+ *   work[4] (nullable): [0] SVD work sum over blocks of 16 m n^2 + 36 n^3 real
+ *     flops (complex m x n block, m >= n), [1] sector elements sum r*s,
+ *     [2] candidate singular values, [3] layers.
+ */
+int mpo_get_profile(gbs_mpo *h, double *phase_ms, long long *phase_launches, double *work);
+
+/* Releases every device allocation of the handle (NULL is a no-op). */
+void mpo_free(gbs_mpo *h);
+
+/* Thread-local message of the last failing call on this thread. */
+const char *mpo_last_error(void);
+
+/*
+ * Host-only helper (no device work): Clements rectangular decomposition of an
+ * interferometer into M(M-1)/2 beam splitters on neighbouring modes plus an
+ * output phase screen (App. A M-layer array; Clements et al., Optica 2016),
+ * grouped into as-soon-as-possible layers of disjoint gates.
+ *   U_reim     host [2*M*M], U[i][j] row-major, interleaved (re, im); must be
+ *              unitary to 1e-10
+ *   layer_ptr  host [M+1]: gates of layer l are [layer_ptr[l], layer_ptr[l+1])
+ *   left_site, theta, phi  host [M(M-1)/2], in application order
+ *   phase      host [M], D = diag(e^{i phase})
+ * Returns the number of layers (>= 0) or a negative error code.
+ * U = D * T_L * ... * T_1 with theta in [0, pi/2], phi in (-pi, pi].
+ */
+int gbs_clements_decompose(int M, const double *U_reim, int *layer_ptr, int *left_site,
+                           double *theta, double *phi, double *phase);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GBS_MPO_H */

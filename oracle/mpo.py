@@ -166,12 +166,12 @@ class DenseMPO:
         """
         M = len(rhos)
         d = rhos[0].shape[0]
-        lam_d = product_lambdas(rhos)
         A = [1.0]
         for j in range(M):
             A.append(A[-1] * float(np.linalg.norm(rhos[j])))
-        charge = [np.array(sorted(ld.keys()), dtype=int).reshape(-1, 2) for ld in lam_d]
-        lam = [np.array([lam_d[b][tuple(q)] for q in charge[b]]) for b in range(M + 1)]
+        bonds = product_bonds(rhos, chi)
+        charge = [bd[0] for bd in bonds]
+        lam = [bd[1] for bd in bonds]
         G = []
         for j in range(M):
             idx = {tuple(q): i for i, q in enumerate(charge[j])}
@@ -185,9 +185,7 @@ class DenseMPO:
                             wq = (lam[j][a] / A[j]) ** 2
                             T[a, m, mp, qi] = rhos[j][m, mp] / (A[j + 1] * math.sqrt(wq))
             G.append(T)
-        mpo = cls(G, lam, charge, d)
-        mpo.truncate_all(chi)
-        return mpo
+        return cls(G, lam, charge, d)
 
     @classmethod
     def product_by_sweeps(cls, rhos, chi: int):
@@ -370,29 +368,51 @@ class DenseMPO:
         return np.transpose(T, perm)
 
 
-def product_lambdas(rhos):
-    """Closed form of the untruncated product-state Schmidt values with the
-    auxiliary leg: lam_b[q]^2 = (prod_{j<b} ||rho_j||_F^2) * w_b(q) where w_b is
-    the 2-D convolution of |rho_j|^2 over modes j >= b (App. D charges;
-    derivation in the design notes).  Returns per bond a dict {q: lam}."""
+def _weights(rhos):
+    """w_b on the grid [0, (M-b)(d-1)]^2: 2-D convolution of |rho_j|^2, j >= b."""
     M = len(rhos)
     d = rhos[0].shape[0]
     w = [None] * (M + 1)
-    w[M] = {(0, 0): 1.0}
+    w[M] = np.ones((1, 1))
     for b in range(M - 1, -1, -1):
-        acc: dict[tuple, float] = {}
+        prev = w[b + 1]
+        W = prev.shape[0] + d - 1
+        acc = np.zeros((W, W))
         a2 = np.abs(rhos[b]) ** 2
-        for q, v in w[b + 1].items():
-            for m in range(d):
-                for mp in range(d):
-                    if a2[m, mp] != 0:
-                        key = (q[0] + m, q[1] + mp)
-                        acc[key] = acc.get(key, 0.0) + v * a2[m, mp]
+        for m in range(d):
+            for mp in range(d):
+                if a2[m, mp] != 0:
+                    acc[m:m + prev.shape[0], mp:mp + prev.shape[1]] += a2[m, mp] * prev
         w[b] = acc
+    return w
+
+
+def product_lambdas(rhos):
+    """Closed form of the untruncated product-state Schmidt values with the
+    auxiliary leg: lam_b[q]^2 = (prod_{j<b} ||rho_j||_F^2) * w_b(q) where w_b is
+    the 2-D convolution of |rho_j|^2 over modes j >= b (App. D charges; the
+    Schmidt decomposition of a product state has one vector per right charge).
+    Returns per bond a dict {q: lam} over the charges with w_b(q) > 0."""
+    M = len(rhos)
+    w = _weights(rhos)
     out = []
     A2 = 1.0
     for b in range(M + 1):
-        out.append({q: math.sqrt(A2 * v) for q, v in w[b].items() if v > 0})
+        nz = np.argwhere(w[b] > 0)
+        out.append({(int(q0), int(q1)): math.sqrt(A2 * w[b][q0, q1]) for q0, q1 in nz})
         if b < M:
             A2 *= float((np.abs(rhos[b]) ** 2).sum())
+    return out
+
+
+def product_bonds(rhos, chi: int):
+    """Bond charges and Schmidt values of the initial state after the top-chi
+    (mirror-pair rule) truncation of every bond, without building tensors."""
+    lam_d = product_lambdas(rhos)
+    out = []
+    for ld in lam_d:
+        ch = np.array(sorted(ld.keys()), dtype=int).reshape(-1, 2)
+        lam = np.array([ld[tuple(q)] for q in ch])
+        keep = select(ch, lam, chi)
+        out.append((ch[keep], lam[keep]))
     return out

@@ -1,0 +1,738 @@
+// One layer of disjoint beam splitters on the U(1) Vidal MPO (App. D).
+//
+// For a gate on modes (j, j+1) the bonds are L = j, C = j+1, R = j+2.  A new
+// centre charge q gives the sector block (App. D, Eq. theta)
+//   Theta(q)[a, b] = lam_L[a] lam_R[b] sum_alpha W(c_a, c_alpha, c_b, q)
+//                    Gamma_j[a, alpha] lam_C[alpha] Gamma_{j+1}[alpha, b],
+// rows a with c_a - q in [0,d)^2, columns b with q - c_b in [0,d)^2, and
+//   W = U[n][i][j] conj(U[n'][i'][j'])        (Sec. II, U (x) conj(U)),
+// where (n, n') = c_a - c_b are the photons on the two modes, (i, i') =
+// c_a - q the new and (j, j') = c_a - c_alpha the old photons of mode j.
+// Every block is SVD'd (App. D: block-wise SVD of all Theta(c)), the chi
+// largest singular values over all blocks are kept under the mirror-pair rule,
+// and Gamma~_j = V / lam_L, Gamma~_{j+1} = W^dag / lam_R (App. D).
+//
+// Kernels, in launch order: k_fock (Fock tables), k_plan (sector planning),
+// k_contract (Theta blocks), k_svd (one-sided Jacobi), k_select (truncation),
+// k_zero + k_scatter (new tensors), k_entropy_layer (EE of the new bonds).
+#include <math.h>
+
+#include "blockops.h"
+#include "internal.h"
+
+namespace gbs {
+
+// ----------------------------------------------------------------------------
+// Fock beam-splitter tables by the creation-operator recursion: with
+// U a1^dag U^dag = T11 a1^dag + T21 a2^dag and U a2^dag U^dag = T12 a1^dag +
+// T22 a2^dag, the block of total photon number n follows from block n-1:
+//   B_n[i][j] = (T11 sqrt(i) B_{n-1}[i-1][j-1] + T21 sqrt(n-i) B_{n-1}[i][j-1]) / sqrt(j)
+//   B_n[i][0] = (T12 sqrt(i) B_{n-1}[i-1][0]   + T22 sqrt(n-i) B_{n-1}[i][0])   / sqrt(n)
+// where i, j count photons in mode 1 of the output / input.  Stored entries
+// are those with both modes inside the cutoff: tab[n][i][j], i, j, n-i, n-j < d.
+// ----------------------------------------------------------------------------
+__global__ void k_fock(Layer ly, int d) {
+  const int g = blockIdx.x;
+  const GateParam gp = ly.gates[g];
+  const int nmax = 2 * d - 2;
+  const int W = nmax + 1;
+  __shared__ cd s_b[2][32 * 32];
+  const double ct = cos(gp.theta), st = sin(gp.theta);
+  const cd T11 = cmk(cos(gp.phi) * ct, sin(gp.phi) * ct);
+  const cd T21 = cmk(cos(gp.phi) * st, sin(gp.phi) * st);
+  const cd T12 = cmk(-st, 0.0);
+  const cd T22 = cmk(ct, 0.0);
+  cd *tab = ly.fock + (size_t)g * W * d * d;
+  for (int i = threadIdx.x; i < W * d * d; i += blockDim.x) tab[i] = cmk(0.0, 0.0);
+  if (threadIdx.x == 0) s_b[0][0] = cmk(1.0, 0.0);
+  __syncthreads();
+  if (threadIdx.x == 0) tab[0] = cmk(1.0, 0.0);
+  for (int n = 1; n <= nmax; ++n) {
+    const cd *prev = s_b[(n - 1) & 1];
+    cd *cur = s_b[n & 1];
+    for (int idx = threadIdx.x; idx < (n + 1) * (n + 1); idx += blockDim.x) {
+      const int i = idx / (n + 1), j = idx % (n + 1);
+      cd acc = cmk(0.0, 0.0);
+      if (j >= 1) {
+        if (i >= 1) cfma(acc, cscale(T11, sqrt((double)i)), prev[(i - 1) * 32 + (j - 1)]);
+        if (i <= n - 1) cfma(acc, cscale(T21, sqrt((double)(n - i))), prev[i * 32 + (j - 1)]);
+        acc = cscale(acc, 1.0 / sqrt((double)j));
+      } else {
+        if (i >= 1) cfma(acc, cscale(T12, sqrt((double)i)), prev[(i - 1) * 32]);
+        if (i <= n - 1) cfma(acc, cscale(T22, sqrt((double)(n - i))), prev[i * 32]);
+        acc = cscale(acc, 1.0 / sqrt((double)n));
+      }
+      cur[i * 32 + j] = acc;
+      if (i < d && n - i < d && j < d && n - j < d) tab[((size_t)n * d + i) * d + j] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_fock(Layer ly, int d, hipStream_t s) {
+  hipLaunchKernelGGL(k_fock, dim3(ly.ngates), dim3(256), 0, s, ly, d);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Sector planning: one workgroup per gate.  New centre charges q lie in the
+// box [lo0, hi0] x [lo1, hi1] spanned by the outer bonds; for each q the
+// block has r = #{a : c_a - q in [0,d)^2} rows and s = #{b : q - c_b in [0,d)^2}
+// columns, counted with binary searches on the sorted bonds.  Non-empty
+// blocks are compacted in charge order, offsets assigned, row / column index
+// lists written and each block's mirror (n', n) located.
+// ----------------------------------------------------------------------------
+__device__ inline int count_window(const int *c, int D, int n, int lo, int hi) {
+  if (hi < lo || n < 0) return 0;
+  lo = max(lo, 0);
+  if (hi < lo) return 0;
+  return lower_bound(c, D, pack_charge(n, hi + 1)) - lower_bound(c, D, pack_charge(n, lo));
+}
+
+constexpr int CHUNK = 256;
+
+__global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap, int sv_cap) {
+  const int g = blockIdx.x;
+  const int d = st.d, chi = st.chi;
+  const int j = ly.gates[g].site;
+  const int *cL = st.chg + (size_t)j * chi;
+  const int *cR = st.chg + (size_t)(j + 2) * chi;
+  const int DL = st.dim[j], DR = st.dim[j + 2];
+  BlkDesc *blk = ly.blk + (size_t)g * ly.max_blk;
+  int *rows = ly.rows + (size_t)g * rows_cap;
+  int *cols = ly.cols + (size_t)g * rows_cap;
+  __shared__ int s_min1L, s_max1L, s_min1R, s_max1R;
+  __shared__ long long s_scan[17];
+  __shared__ int s_iscan[17];
+  if (threadIdx.x == 0) {
+    s_min1L = 1 << 30; s_max1L = -1; s_min1R = 1 << 30; s_max1R = -1;
+  }
+  __syncthreads();
+  {
+    int mn = 1 << 30, mx = -1;
+    for (int a = threadIdx.x; a < DL; a += blockDim.x) {
+      mn = min(mn, charge_np(cL[a]));
+      mx = max(mx, charge_np(cL[a]));
+    }
+    atomicMin(&s_min1L, mn);
+    atomicMax(&s_max1L, mx);
+    mn = 1 << 30; mx = -1;
+    for (int b = threadIdx.x; b < DR; b += blockDim.x) {
+      mn = min(mn, charge_np(cR[b]));
+      mx = max(mx, charge_np(cR[b]));
+    }
+    atomicMin(&s_min1R, mn);
+    atomicMax(&s_max1R, mx);
+  }
+  __syncthreads();
+  GateTot tot = {};
+  if (DL == 0 || DR == 0) {
+    if (threadIdx.x == 0) ly.tot[g] = tot;
+    return;
+  }
+  const int minL0 = charge_n(cL[0]), maxL0 = charge_n(cL[DL - 1]);
+  const int minR0 = charge_n(cR[0]), maxR0 = charge_n(cR[DR - 1]);
+  const int lo0 = max(max(minL0 - (d - 1), minR0), 0), hi0 = min(maxL0, maxR0 + d - 1);
+  const int lo1 = max(max(s_min1L - (d - 1), s_min1R), 0), hi1 = min(s_max1L, s_max1R + d - 1);
+  const int W0 = hi0 - lo0 + 1, W1 = hi1 - lo1 + 1;
+  if (W0 <= 0 || W1 <= 0) {
+    if (threadIdx.x == 0) ly.tot[g] = tot;
+    return;
+  }
+  const long long area = (long long)W0 * W1;
+  if (area > ly.box_cap) {
+    if (threadIdx.x == 0) {
+      atomicOr(st.err, ERR_BOX_OVERFLOW);
+      ly.tot[g] = tot;
+    }
+    return;
+  }
+  // pass 1: compact the non-empty blocks in charge order
+  long long nb = 0;
+  for (long long c0 = 0; c0 < area; c0 += blockDim.x) {
+    const long long cell = c0 + threadIdx.x;
+    int r = 0, s = 0;
+    int q0 = 0, q1 = 0;
+    if (cell < area) {
+      q0 = lo0 + (int)(cell / W1);
+      q1 = lo1 + (int)(cell % W1);
+      for (int n = q0; n <= q0 + d - 1; ++n) r += count_window(cL, DL, n, q1, q1 + d - 1);
+      if (r > 0)
+        for (int n = max(q0 - d + 1, 0); n <= q0; ++n)
+          s += count_window(cR, DR, n, q1 - d + 1, q1);
+    }
+    const long long flag = (r > 0 && s > 0) ? 1 : 0;
+    long long total;
+    const long long pos = nb + block_exclusive_scan<long long>(flag, s_scan, total);
+    if (flag) {
+      if (pos < ly.max_blk) {
+        BlkDesc B = {};
+        B.q = pack_charge(q0, q1);
+        B.r = r;
+        B.s = s;
+        B.t = r < s;
+        B.m = max(r, s);
+        B.n = min(r, s);
+        B.gate = g;
+        blk[pos] = B;
+      } else {
+        atomicOr(st.err, ERR_WORKSPACE);
+      }
+    }
+    nb += total;
+  }
+  __syncthreads();
+  const int nblk = (int)min(nb, (long long)ly.max_blk);
+  // pass 2: offsets
+  long long eb = 0, vb = 0;
+  int svb = 0, rb = 0, cb = 0, chb = 0, maxr = 0, maxc = 0;
+  double fl = 0.0;
+  for (int b0 = 0; b0 < nblk; b0 += blockDim.x) {
+    const int bi = b0 + threadIdx.x;
+    long long e = 0, v = 0;
+    int sv = 0, r = 0, c = 0, ch = 0;
+    if (bi < nblk) {
+      const BlkDesc &B = blk[bi];
+      e = (long long)B.r * B.s;
+      v = (long long)B.n * B.n;
+      sv = B.n;
+      r = B.r;
+      c = B.s;
+      ch = (int)((e + CHUNK - 1) / CHUNK);
+      fl += 16.0 * B.m * (double)B.n * B.n + 36.0 * (double)B.n * B.n * B.n;
+      maxr = max(maxr, B.r);
+      maxc = max(maxc, B.s);
+    }
+    long long te, tv;
+    int tsv, tr, tc, tch;
+    const long long pe = eb + block_exclusive_scan<long long>(e, s_scan, te);
+    const long long pv = vb + block_exclusive_scan<long long>(v, s_scan, tv);
+    const int psv = svb + block_exclusive_scan<int>(sv, s_iscan, tsv);
+    const int pr = rb + block_exclusive_scan<int>(r, s_iscan, tr);
+    const int pc = cb + block_exclusive_scan<int>(c, s_iscan, tc);
+    const int pch = chb + block_exclusive_scan<int>(ch, s_iscan, tch);
+    if (bi < nblk) {
+      BlkDesc &B = blk[bi];
+      B.eoff = pe;
+      B.voff = pv;
+      B.svoff = psv;
+      B.roff = pr;
+      B.coff = pc;
+      B.uoff = pch;   // chunk offset until the select kernel reuses the field
+      // mirror block by binary search on the sorted charges
+      const int qm = pack_charge(charge_np(B.q), charge_n(B.q));
+      int lo = 0, hi = nblk;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (blk[mid].q < qm) lo = mid + 1; else hi = mid;
+      }
+      B.mirror = (lo < nblk && blk[lo].q == qm) ? lo : -1;
+    }
+    eb += te; vb += tv; svb += tsv; rb += tr; cb += tc; chb += tch;
+  }
+  __syncthreads();
+  if (rb > rows_cap || cb > rows_cap || svb > sv_cap) {
+    if (threadIdx.x == 0) atomicOr(st.err, ERR_WORKSPACE);
+    if (threadIdx.x == 0) ly.tot[g] = tot;
+    return;
+  }
+  // pass 3: row / column index lists (ascending)
+  for (int bi = threadIdx.x; bi < nblk; bi += blockDim.x) {
+    const BlkDesc B = blk[bi];
+    const int q0 = charge_n(B.q), q1 = charge_np(B.q);
+    int k = 0;
+    for (int n = q0; n <= q0 + d - 1; ++n) {
+      const int a0 = lower_bound(cL, DL, pack_charge(n, q1));
+      const int a1 = lower_bound(cL, DL, pack_charge(n, q1 + d));
+      for (int a = a0; a < a1; ++a) rows[B.roff + k++] = a;
+    }
+    k = 0;
+    for (int n = max(q0 - d + 1, 0); n <= q0; ++n) {
+      const int b0 = lower_bound(cR, DR, pack_charge(n, max(q1 - d + 1, 0)));
+      const int b1 = lower_bound(cR, DR, pack_charge(n, q1 + 1));
+      for (int b = b0; b < b1; ++b) cols[B.coff + k++] = b;
+    }
+  }
+  // block-wide max of maxr / maxc, sum of the SVD work
+  __shared__ int s_mr, s_mc;
+  __shared__ double s_fl;
+  if (threadIdx.x == 0) { s_mr = 0; s_mc = 0; s_fl = 0.0; }
+  __syncthreads();
+  atomicMax(&s_mr, maxr);
+  atomicMax(&s_mc, maxc);
+  atomicAdd(&s_fl, fl);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    tot.nblk = nblk;
+    tot.sv = svb;
+    tot.rows = rb;
+    tot.cols = cb;
+    tot.maxr = s_mr;
+    tot.maxc = s_mc;
+    tot.elems = eb;
+    tot.vsz = vb;
+    tot.chunks = chb;
+    tot.svd_flops = s_fl;
+    ly.tot[g] = tot;
+  }
+}
+
+hipError_t launch_plan(State st, Layer ly, hipStream_t s) {
+  const int rows_cap = st.d * st.d * st.chi;
+  hipLaunchKernelGGL(k_plan, dim3(ly.ngates), dim3(1024), 0, s, st, ly, rows_cap, rows_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_lists(State, Layer, hipStream_t) { return hipSuccess; }
+
+// Locate the gate of a flat index given per-gate starts (ascending).
+__device__ inline int find_gate_blk(const GateBase *base, int ng, int flat) {
+  int g = 0;
+  while (g + 1 < ng && base[g + 1].blk <= flat) ++g;
+  return g;
+}
+__device__ inline int find_gate_chunk(const GateBase *base, int ng, long long flat) {
+  int g = 0;
+  while (g + 1 < ng && base[g + 1].echunk <= flat) ++g;
+  return g;
+}
+
+// ----------------------------------------------------------------------------
+// Theta(q) blocks: one 256-element chunk of one block per workgroup, one
+// element per thread (b fastest).  The sum over alpha runs over the bond-C
+// charges p with c_a - p and p - c_b both in [0,d)^2: p0 in
+// [max(c_b0, c_a0-d+1), min(c_b0+d-1, c_a0)], same for p1, i.e. one
+// contiguous run of the sorted bond per p0.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(CHUNK) void k_contract(State st, Layer ly, int rows_cap) {
+  const long long chunk = blockIdx.x;
+  const int g = find_gate_chunk(ly.base, ly.ngates, chunk);
+  const int d = st.d, chi = st.chi;
+  const int j = ly.gates[g].site;
+  const GateBase gb = ly.base[g];
+  const int nblk = ly.tot[g].nblk;
+  const BlkDesc *blk = ly.blk + (size_t)g * ly.max_blk;
+  // block containing this chunk (chunk offsets stored in uoff)
+  const int lc = (int)(chunk - gb.echunk);
+  int lo = 0, hi = nblk;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (blk[mid].uoff <= lc) lo = mid; else hi = mid;
+  }
+  const BlkDesc B = blk[lo];
+  const long long e = (long long)(lc - B.uoff) * CHUNK + threadIdx.x;
+  if (e >= (long long)B.r * B.s) return;
+  const int ia = (int)(e / B.s), ib = (int)(e % B.s);
+  const int a = ly.rows[(size_t)g * rows_cap + B.roff + ia];
+  const int b = ly.cols[(size_t)g * rows_cap + B.coff + ib];
+  const int *cL = st.chg + (size_t)j * chi;
+  const int *cC = st.chg + (size_t)(j + 1) * chi;
+  const int *cR = st.chg + (size_t)(j + 2) * chi;
+  const int DC = st.dim[j + 1];
+  const int ca = cL[a], cb = cR[b];
+  const int ca0 = charge_n(ca), ca1 = charge_np(ca), cb0 = charge_n(cb), cb1 = charge_np(cb);
+  const int q0 = charge_n(B.q), q1 = charge_np(B.q);
+  const int n0 = ca0 - cb0, n1 = ca1 - cb1;
+  const int i0 = ca0 - q0, i1 = ca1 - q1;
+  const cd *tab = ly.fock + (size_t)g * (2 * d - 1) * d * d;
+  const cd *Ga = st.gam + (size_t)j * chi * chi + (size_t)a * chi;
+  const cd *Gb = st.gam + (size_t)(j + 1) * chi * chi + b;
+  const double *lC = st.lam + (size_t)(j + 1) * chi;
+  const int p0lo = max(cb0, ca0 - d + 1), p0hi = min(cb0 + d - 1, ca0);
+  const int p1lo = max(cb1, ca1 - d + 1), p1hi = min(cb1 + d - 1, ca1);
+  cd acc = cmk(0.0, 0.0);
+  for (int p0 = p0lo; p0 <= p0hi; ++p0) {
+    const int al0 = lower_bound(cC, DC, pack_charge(p0, p1lo));
+    const int al1 = lower_bound(cC, DC, pack_charge(p0, p1hi + 1));
+    const cd wk = tab[((size_t)n0 * d + i0) * d + (ca0 - p0)];
+    for (int al = al0; al < al1; ++al) {
+      const int p1 = charge_np(cC[al]);
+      const cd wb = tab[((size_t)n1 * d + i1) * d + (ca1 - p1)];
+      const cd w = cmulc(wb, wk);                        // U_ket * conj(U_bra)
+      const cd x = cscale(cmul(Ga[al], Gb[(size_t)al * chi]), lC[al]);
+      cfma(acc, w, x);
+    }
+  }
+  const double sc = st.lam[(size_t)j * chi + a] * st.lam[(size_t)(j + 2) * chi + b];
+  acc = cscale(acc, sc);
+  cd *Aop = ly.A + gb.e + B.eoff;
+  if (!B.t) Aop[(size_t)ib * B.m + ia] = acc;          // Theta, m = r rows
+  else Aop[(size_t)ia * B.m + ib] = acc;               // Theta^T, m = s rows
+}
+
+hipError_t launch_contract(State st, Layer ly, hipStream_t s) {
+  if (ly.total_chunks == 0) return hipSuccess;
+  const int rows_cap = st.d * st.d * st.chi;
+  hipLaunchKernelGGL(k_contract, dim3((unsigned)ly.total_chunks), dim3(CHUNK), 0, s, st, ly,
+                     rows_cap);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi SVD of one block per workgroup.  Column pairs
+// follow the round-robin tournament (n/2 disjoint pairs per round, n-1 rounds
+// per sweep); each wavefront rotates one pair at a time with 64-lane
+// reductions.  For columns x, y with x^H y = |g| e^{i psi}:
+//   zeta = (|y|^2 - |x|^2) / (2 |g|),  t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+//   c = 1 / sqrt(1 + t^2), s = c t,
+//   x <- c x - s e^{-i psi} y,  y <- s x + c e^{-i psi} y,
+// and the same column operation accumulates the right factor V.  At
+// convergence A = U Sigma with orthogonal columns and A0 = U Sigma V^H.
+// ----------------------------------------------------------------------------
+constexpr int SVD_THREADS = 256;
+constexpr int MAX_SWEEPS = 60;
+
+__device__ inline void jacobi_pair(cd *A, int m, cd *V, int n, int p, int q, int lane,
+                                   double tol, int &rot) {
+  double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+  for (int i = lane; i < m; i += 64) {
+    const cd x = A[(size_t)p * m + i], y = A[(size_t)q * m + i];
+    al += cabs2(x);
+    be += cabs2(y);
+    gr += x.re * y.re + x.im * y.im;
+    gi += x.re * y.im - x.im * y.re;
+  }
+  al = wave_sum(al);
+  be = wave_sum(be);
+  gr = wave_sum(gr);
+  gi = wave_sum(gi);
+  const double ga = sqrt(gr * gr + gi * gi);
+  if (!(ga > tol * sqrt(al * be)) || ga < 1e-300) return;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double s = c * t;
+  const cd e = cmk(gr / ga, -gi / ga);      // e^{-i psi}
+  for (int i = lane; i < m; i += 64) {
+    const cd x = A[(size_t)p * m + i];
+    const cd y = cmul(e, A[(size_t)q * m + i]);
+    A[(size_t)p * m + i] = csub(cscale(x, c), cscale(y, s));
+    A[(size_t)q * m + i] = cadd(cscale(x, s), cscale(y, c));
+  }
+  for (int i = lane; i < n; i += 64) {
+    const cd x = V[(size_t)p * n + i];
+    const cd y = cmul(e, V[(size_t)q * n + i]);
+    V[(size_t)p * n + i] = csub(cscale(x, c), cscale(y, s));
+    V[(size_t)q * n + i] = cadd(cscale(x, s), cscale(y, c));
+  }
+  rot = 1;
+}
+
+__global__ __launch_bounds__(SVD_THREADS) void k_svd(State st, Layer ly, int sv_cap) {
+  const int flat = blockIdx.x;
+  const int g = find_gate_blk(ly.base, ly.ngates, flat);
+  const GateBase gb = ly.base[g];
+  BlkDesc *Bp = ly.blk + (size_t)g * ly.max_blk + (flat - gb.blk);
+  const int m = Bp->m, n = Bp->n;
+  cd *A = ly.A + gb.e + Bp->eoff;
+  cd *V = ly.V + gb.v + Bp->voff;
+  double *sv = ly.sv + (size_t)g * sv_cap + Bp->svoff;
+  int *perm = ly.perm + (size_t)g * sv_cap + Bp->svoff;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = SVD_THREADS / 64;
+  for (int idx = threadIdx.x; idx < n * n; idx += SVD_THREADS)
+    V[idx] = cmk((idx % n) == (idx / n) ? 1.0 : 0.0, 0.0);
+  __shared__ int s_rot;
+  __syncthreads();
+  const int np = n + (n & 1);
+  // rotate while |x^H y| > tol |x| |y|; tol covers the rounding of an m-term dot product
+  const double tol = fmax(1e-15, 2.3e-16 * m);
+  int sweep = 0;
+  if (n > 1) {
+    for (sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
+      if (threadIdx.x == 0) s_rot = 0;
+      __syncthreads();
+      int rot = 0;
+      for (int round = 0; round < np - 1; ++round) {
+        for (int k = wave; k < np / 2; k += nw) {
+          int p, q;
+          if (k == 0) {
+            p = round;
+            q = np - 1;
+          } else {
+            p = (round + k) % (np - 1);
+            q = (round - k + np - 1) % (np - 1);
+          }
+          if (p >= n || q >= n) continue;
+          jacobi_pair(A, m, V, n, p, q, lane, tol, rot);
+        }
+        __syncthreads();
+      }
+      if (rot) s_rot = 1;
+      __syncthreads();
+      const int any = s_rot;
+      __syncthreads();
+      if (!any) break;
+    }
+    if (sweep == MAX_SWEEPS && threadIdx.x == 0) atomicOr(st.err, ERR_SVD_NOT_CONVERGED);
+  }
+  // singular values = column norms, sorted descending (ties by column)
+  extern __shared__ double s_sig[];
+  for (int c = threadIdx.x; c < n; c += SVD_THREADS) {
+    double acc = 0.0;
+    for (int i = 0; i < m; ++i) acc += cabs2(A[(size_t)c * m + i]);
+    s_sig[c] = sqrt(acc);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += SVD_THREADS) {
+    const double v = s_sig[c];
+    int rank = 0;
+    for (int o = 0; o < n; ++o) {
+      const double w = s_sig[o];
+      rank += (w > v) || (w == v && o < c);
+    }
+    sv[rank] = v;
+    perm[rank] = c;
+    if (!isfinite(v)) atomicOr(st.err, ERR_NONFINITE);
+  }
+  if (threadIdx.x == 0) Bp->sweeps = sweep;
+}
+
+hipError_t launch_svd(State st, Layer ly, hipStream_t s) {
+  if (ly.total_blocks == 0) return hipSuccess;
+  const int sv_cap = st.d * st.d * st.chi;
+  const size_t lds = sizeof(double) * (size_t)st.chi;
+  hipLaunchKernelGGL(k_svd, dim3(ly.total_blocks), dim3(SVD_THREADS), lds, s, st, ly, sv_cap);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Truncation, one workgroup per gate: rank cut 1e-14 of the gate's largest
+// singular value, mirror-pair units, size-weighted top-chi select, kept counts
+// per block and the new bond's offsets (charge order, then decreasing value).
+// ----------------------------------------------------------------------------
+__device__ inline int count_above(const double *sv, int n, double cut) {
+  int lo = 0, hi = n;   // sv descending: first index with sv < cut
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (sv[mid] >= cut) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(1024) void k_select(State st, Layer ly, int sv_cap) {
+  const int g = blockIdx.x;
+  const int chi = st.chi;
+  const int j = ly.gates[g].site;
+  const int nblk = ly.tot[g].nblk;
+  BlkDesc *blk = ly.blk + (size_t)g * ly.max_blk;
+  const double *sv = ly.sv + (size_t)g * sv_cap;
+  unsigned long long *uv = ly.uval + (size_t)g * sv_cap;
+  unsigned long long *uk = ly.ukey + (size_t)g * sv_cap;
+  int *us = ly.usize + (size_t)g * sv_cap;
+  __shared__ double s_max;
+  __shared__ int s_iscan[17];
+  if (threadIdx.x == 0) s_max = 0.0;
+  __syncthreads();
+  double mx = 0.0;
+  for (int bi = threadIdx.x; bi < nblk; bi += blockDim.x) mx = fmax(mx, sv[blk[bi].svoff]);
+  atomicMax((unsigned long long *)&s_max, (unsigned long long)__double_as_longlong(mx));
+  __syncthreads();
+  const double cut = 1e-14 * s_max;
+  for (int bi = threadIdx.x; bi < nblk; bi += blockDim.x)
+    blk[bi].len = (s_max > 0.0) ? count_above(sv + blk[bi].svoff, blk[bi].n, cut) : 0;
+  __syncthreads();
+  // units owned by each block
+  int ub = 0;
+  for (int b0 = 0; b0 < nblk; b0 += blockDim.x) {
+    const int bi = b0 + threadIdx.x;
+    int cnt = 0;
+    if (bi < nblk) {
+      const BlkDesc &B = blk[bi];
+      const int q0 = charge_n(B.q), q1 = charge_np(B.q);
+      if (q0 == q1) cnt = B.len;
+      else if (q0 < q1) cnt = max(B.len, B.mirror >= 0 ? blk[B.mirror].len : 0);
+      else cnt = (B.mirror < 0) ? B.len : 0;
+    }
+    int tot;
+    const int pos = ub + block_exclusive_scan<int>(cnt, s_iscan, tot);
+    if (bi < nblk) blk[bi].uoff = pos;
+    ub += tot;
+  }
+  __syncthreads();
+  const int U = ub;
+  for (int bi = threadIdx.x; bi < nblk; bi += blockDim.x) {
+    const BlkDesc B = blk[bi];
+    const int q0 = charge_n(B.q), q1 = charge_np(B.q);
+    const bool owner = (q0 == q1) || (q0 < q1) || (B.mirror < 0);
+    if (!owner) continue;
+    const bool paired = (q0 != q1) && (B.mirror >= 0);
+    const int lp = paired ? blk[B.mirror].len : 0;
+    const double *sp = paired ? sv + blk[B.mirror].svoff : nullptr;
+    const int cnt = paired ? max(B.len, lp) : B.len;
+    const int canon = pack_charge(min(q0, q1), max(q0, q1));
+    for (int i = 0; i < cnt; ++i) {
+      double v = 0.0;
+      int sz = 0;
+      if (i < B.len) { v = sv[B.svoff + i]; ++sz; }
+      if (i < lp) { v = fmax(v, sp[i]); ++sz; }
+      uv[B.uoff + i] = (unsigned long long)__double_as_longlong(v);
+      uk[B.uoff + i] = ((unsigned long long)(canon + 1) << 20) | (unsigned long long)i;
+      us[B.uoff + i] = sz;
+    }
+  }
+  __syncthreads();
+  const SelectResult sr = topk_select(uv, uk, us, U, chi, st.err);
+  // kept units of each owner form a prefix of its ranks
+  for (int bi = threadIdx.x; bi < nblk; bi += blockDim.x) {
+    const BlkDesc B = blk[bi];
+    const int q0 = charge_n(B.q), q1 = charge_np(B.q);
+    const bool owner = (q0 == q1) || (q0 < q1) || (B.mirror < 0);
+    const int ob = owner ? bi : B.mirror;
+    const BlkDesc O = blk[ob];
+    const int oq0 = charge_n(O.q), oq1 = charge_np(O.q);
+    const bool opaired = (oq0 != oq1) && (O.mirror >= 0);
+    const int cnt = opaired ? max(O.len, blk[O.mirror].len) : O.len;
+    int K = 0;
+    while (K < cnt && unit_kept(sr, uv[O.uoff + K], uk[O.uoff + K])) ++K;
+    blk[bi].kq = min(K, B.len);
+  }
+  __syncthreads();
+  int nb = 0;
+  for (int b0 = 0; b0 < nblk; b0 += blockDim.x) {
+    const int bi = b0 + threadIdx.x;
+    const int k = (bi < nblk) ? blk[bi].kq : 0;
+    int tot;
+    const int pos = nb + block_exclusive_scan<int>(k, s_iscan, tot);
+    if (bi < nblk) blk[bi].boff = pos;
+    nb += tot;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) st.dim[j + 1] = min(nb, chi);
+}
+
+hipError_t launch_select(State st, Layer ly, hipStream_t s) {
+  const int sv_cap = st.d * st.d * st.chi;
+  hipLaunchKernelGGL(k_select, dim3(ly.ngates), dim3(1024), 0, s, st, ly, sv_cap);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// New tensors: zero Gamma_j, Gamma_{j+1} and the new bond, then write
+//   lam[beta] = sigma_i, c[beta] = q,
+//   Gamma_j[a, beta] = V_Theta[a, i] / lam_L[a],
+//   Gamma_{j+1}[beta, b] = W^H_Theta[i, b] / lam_R[b]
+// for the kept ranks i of every block (beta = boff + i).
+// Stored operand A = Theta: V_Theta = U, W^H = V_acc^H; A = Theta^T:
+// Theta = conj(V_acc) Sigma U^T, so V_Theta = conj(V_acc), W^H = U^T.
+// ----------------------------------------------------------------------------
+__global__ void k_zero(State st, Layer ly) {
+  const int g = blockIdx.y;
+  const int j = ly.gates[g].site;
+  const size_t chi2 = (size_t)st.chi * st.chi;
+  cd *G0 = st.gam + (size_t)j * chi2;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * chi2;
+       i += (size_t)gridDim.x * blockDim.x)
+    G0[i] = cmk(0.0, 0.0);
+  if (blockIdx.x == 0) {
+    const int nd = st.dim[j + 1];
+    for (int i = nd + threadIdx.x; i < st.chi; i += blockDim.x) {
+      st.lam[(size_t)(j + 1) * st.chi + i] = 0.0;
+      st.chg[(size_t)(j + 1) * st.chi + i] = CHARGE_NONE;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scatter(State st, Layer ly, int sv_cap, int rows_cap) {
+  const int flat = blockIdx.x;
+  const int g = find_gate_blk(ly.base, ly.ngates, flat);
+  const GateBase gb = ly.base[g];
+  const BlkDesc B = ly.blk[(size_t)g * ly.max_blk + (flat - gb.blk)];
+  if (B.kq == 0) return;
+  const int chi = st.chi;
+  const int j = ly.gates[g].site;
+  const cd *A = ly.A + gb.e + B.eoff;
+  const cd *V = ly.V + gb.v + B.voff;
+  const double *sv = ly.sv + (size_t)g * sv_cap + B.svoff;
+  const int *perm = ly.perm + (size_t)g * sv_cap + B.svoff;
+  const int *rows = ly.rows + (size_t)g * rows_cap + B.roff;
+  const int *cols = ly.cols + (size_t)g * rows_cap + B.coff;
+  const double *lL = st.lam + (size_t)j * chi;
+  const double *lR = st.lam + (size_t)(j + 2) * chi;
+  cd *G1 = st.gam + (size_t)j * chi * chi;
+  cd *G2 = st.gam + (size_t)(j + 1) * chi * chi;
+  for (int i = threadIdx.x; i < B.kq; i += blockDim.x) {
+    st.lam[(size_t)(j + 1) * chi + B.boff + i] = sv[i];
+    st.chg[(size_t)(j + 1) * chi + B.boff + i] = B.q;
+  }
+  for (int idx = threadIdx.x; idx < B.kq * B.r; idx += blockDim.x) {
+    const int i = idx / B.r, ia = idx % B.r;
+    const int col = perm[i];
+    cd v;
+    if (!B.t) v = cscale(A[(size_t)col * B.m + ia], 1.0 / sv[i]);
+    else v = cconj(V[(size_t)col * B.n + ia]);
+    const int a = rows[ia];
+    G1[(size_t)a * chi + B.boff + i] = cscale(v, 1.0 / lL[a]);
+  }
+  for (int idx = threadIdx.x; idx < B.kq * B.s; idx += blockDim.x) {
+    const int i = idx / B.s, ib = idx % B.s;
+    const int col = perm[i];
+    cd w;
+    if (!B.t) w = cconj(V[(size_t)col * B.n + ib]);
+    else w = cscale(A[(size_t)col * B.m + ib], 1.0 / sv[i]);
+    const int b = cols[ib];
+    G2[(size_t)(B.boff + i) * chi + b] = cscale(w, 1.0 / lR[b]);
+  }
+}
+
+hipError_t launch_scatter(State st, Layer ly, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero, dim3(64, ly.ngates), dim3(256), 0, s, st, ly);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || ly.total_blocks == 0) return e;
+  const int sv_cap = st.d * st.d * st.chi;
+  hipLaunchKernelGGL(k_scatter, dim3(ly.total_blocks), dim3(256), 0, s, st, ly, sv_cap, sv_cap);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Operator EE of a bond: S = -sum p log2 p, p = lam^2 / sum lam^2.
+// ----------------------------------------------------------------------------
+__device__ inline void bond_entropy(State st, int b) {
+  const int D = st.dim[b];
+  const double *lam = st.lam + (size_t)b * st.chi;
+  __shared__ double s_a[16], s_b[16];
+  double n2 = 0.0;
+  for (int i = threadIdx.x; i < D; i += blockDim.x) n2 += lam[i] * lam[i];
+  n2 = wave_sum(n2);
+  if ((threadIdx.x & 63) == 0) s_a[threadIdx.x >> 6] = n2;
+  __syncthreads();
+  double tot = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += s_a[w];
+  double h = 0.0;
+  for (int i = threadIdx.x; i < D; i += blockDim.x) {
+    const double p = lam[i] * lam[i] / tot;
+    if (p > 0.0) h -= p * log2(p);
+  }
+  h = wave_sum(h);
+  if ((threadIdx.x & 63) == 0) s_b[threadIdx.x >> 6] = h;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double S = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) S += s_b[w];
+    st.ee[b] = S;
+    if (!isfinite(S)) atomicOr(st.err, ERR_NONFINITE);
+    else if (b >= 1 && b <= st.M - 1)
+      atomicMax(st.ee_max, (unsigned long long)__double_as_longlong(fmax(S, 0.0)));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_entropy_layer(State st, Layer ly) {
+  bond_entropy(st, ly.gates[blockIdx.x].site + 1);
+}
+
+hipError_t launch_entropy_layer(State st, Layer ly, hipStream_t s) {
+  hipLaunchKernelGGL(k_entropy_layer, dim3(ly.ngates), dim3(256), 0, s, st, ly);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_entropy_all(State st) {
+  bond_entropy(st, blockIdx.x + 1);
+}
+
+hipError_t launch_entropy_all(State st, hipStream_t s) {
+  if (st.M < 2) return hipSuccess;
+  hipLaunchKernelGGL(k_entropy_all, dim3(st.M - 1), dim3(256), 0, s, st);
+  return hipGetLastError();
+}
+
+}  // namespace gbs

@@ -1,0 +1,117 @@
+// Internal structures of libgbsmpo: the device-resident state of one
+// simulation, the per-layer workspace, and the kernel launch wrappers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "common.h"
+
+namespace gbs {
+
+// One beam splitter of a layer.
+struct GateParam {
+  int site;       // acts on modes (site, site + 1)
+  int pad;
+  double theta, phi;
+};
+
+// One charge sector Theta(q) of one gate (App. D, Eq. theta).
+struct BlkDesc {
+  int q;          // packed new centre charge
+  int r, s;       // rows (left-bond indices), cols (right-bond indices)
+  int m, n;       // stored SVD operand is m x n column-major, m = max(r, s)
+  int t;          // 1 when the stored operand is Theta^T (r < s)
+  int mirror;     // local index of the block of the mirrored charge, -1 if none
+  int sweeps;     // Jacobi sweeps used
+  int len;        // singular values >= rank cut
+  int kq;         // singular vectors kept
+  int boff;       // first new-bond index of this block
+  int uoff;       // first unit (selection) index owned by this block
+  long long eoff; // operand offset: local to the gate after planning,
+                  // global after the host fix-up
+  long long voff; // offset of the n x n right factor
+  int svoff;      // offset of the n singular values / permutation
+  int roff, coff; // offsets of the row / column index lists
+  int gate;       // gate index inside the layer
+};
+
+// Per-gate plan totals (device -> host).
+struct GateTot {
+  int nblk, sv, rows, cols, maxr, maxc, chunks, pad;
+  long long elems, vsz;
+  double svd_flops;   // sum over blocks of 16 m n^2 + 36 n^3 (complex SVD convention)
+};
+
+// Per-gate global offsets (host -> device).
+struct GateBase {
+  long long e, v;
+  int sv, rows, cols, blk;
+  long long echunk;   // first 256-element chunk of the gate
+};
+
+// Device-resident state of one simulation (App. D Vidal form with charges).
+struct State {
+  int M, d, chi;
+  cd *gam;          // M site matrices chi x chi, row-major, leading dim chi
+  double *lam;      // (M+1) x chi Schmidt values
+  int *chg;         // (M+1) x chi packed charges, sorted, CHARGE_NONE padded
+  int *dim;         // (M+1) bond sizes
+  double *ee;       // (M+1) operator EE per bond (bits)
+  unsigned long long *ee_max;  // running max of EE (double bits)
+  int *err;         // latched error bits
+};
+
+// Workspace of one layer of gates.
+struct Layer {
+  int ngates;
+  GateParam *gates;
+  cd *fock;          // ngates x (2d-1) x d x d, [n][i1][j1]
+  BlkDesc *blk;      // ngates x max_blk, per-gate regions
+  int max_blk;
+  int box_cap;       // largest admissible charge box per gate
+  GateTot *tot;      // ngates
+  GateBase *base;    // ngates
+  int *rows, *cols;  // global row / column index lists
+  cd *A;             // sector operands (overwritten by U * Sigma)
+  cd *V;             // right factors
+  double *sv;        // singular values, sorted descending per block
+  int *perm;         // rank -> operand column
+  unsigned long long *uval;   // selection units: value bits
+  unsigned long long *ukey;   // selection units: tie key
+  int *usize;                 // selection units: size (1 or 2)
+  long long total_chunks;     // 256-element chunks in the layer
+  int total_blocks;
+};
+
+// ---------------- launch wrappers (one translation unit each) ----------------
+// initial state
+hipError_t launch_init_rho(const double *r, const int *nint, double eta, int M, int d,
+                           double *rho, hipStream_t s);
+hipError_t launch_init_norms(const double *rho, int M, int d, double *A, hipStream_t s);
+hipError_t launch_init_conv(const double *rho, int M, int d, int b, const long long *woff,
+                            double *w, hipStream_t s);
+hipError_t launch_init_select(State st, const double *w, const long long *woff,
+                              const double *A, unsigned long long *uval,
+                              unsigned long long *ukey, int *usize, long long ucap,
+                              hipStream_t s);
+hipError_t launch_init_gamma(State st, const double *rho, const double *A, hipStream_t s);
+
+// one layer
+hipError_t launch_fock(Layer ly, int d, hipStream_t s);
+hipError_t launch_plan(State st, Layer ly, hipStream_t s);
+hipError_t launch_lists(State st, Layer ly, hipStream_t s);
+hipError_t launch_contract(State st, Layer ly, hipStream_t s);
+hipError_t launch_svd(State st, Layer ly, hipStream_t s);
+hipError_t launch_select(State st, Layer ly, hipStream_t s);
+hipError_t launch_scatter(State st, Layer ly, hipStream_t s);
+hipError_t launch_entropy_layer(State st, Layer ly, hipStream_t s);
+
+// readouts
+hipError_t launch_entropy_all(State st, hipStream_t s);
+hipError_t launch_phases(State st, const double *phase, hipStream_t s);
+hipError_t launch_marginals(State st, cd *envL, cd *envR, double *P, double *trace,
+                            hipStream_t s);
+
+}  // namespace gbs

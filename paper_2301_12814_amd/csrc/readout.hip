@@ -1,0 +1,157 @@
+// Readouts of the U(1) Vidal MPO: output phase screen, trace and photon
+// marginals (the trace deficit 1 - Tr rho is the paper's error proxy,
+// Sec. III and App. A).
+//
+// With the auxiliary total-charge leg contracted with the all-ones vector and
+// every site with the identity (local ket = bra), the trace is a chain of
+// matrix-vector products over the diagonal-compatible entries of each site
+// matrix (c_a - c_b = (n, n), 0 <= n < d):
+//   E_M = 1,  E_j[a] = sum_b Gamma_j[a, b] lam_{j+1}[b] E_{j+1}[b],
+//   L_0 = 1,  L_{j+1}[b] = sum_a L_j[a] lam_j[a] Gamma_j[a, b],
+//   Tr rho = sum_a lam_0[a] E_0[a],
+//   Tr(rho Pi_{j,n}) = sum_{c_a - c_b = (n,n)} L_j[a] lam_j[a] Gamma_j[a,b] lam_{j+1}[b] E_{j+1}[b].
+#include "internal.h"
+
+namespace gbs {
+
+__device__ inline int diag_photons(int ca, int cb, int d) {
+  const int m = charge_n(ca) - charge_n(cb), mp = charge_np(ca) - charge_np(cb);
+  return (m == mp && m >= 0 && m < d) ? m : -1;
+}
+
+// one wavefront per row a of site j
+__global__ __launch_bounds__(256) void k_env_right(State st, int j, cd *E) {
+  const int chi = st.chi, d = st.d;
+  const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int Dl = st.dim[j], Dr = st.dim[j + 1];
+  if (a >= Dl) return;
+  const int ca = st.chg[(size_t)j * chi + a];
+  const cd *G = st.gam + (size_t)j * chi * chi + (size_t)a * chi;
+  const cd *En = E + (size_t)(j + 1) * chi;
+  const double *lr = st.lam + (size_t)(j + 1) * chi;
+  const int *cr = st.chg + (size_t)(j + 1) * chi;
+  double re = 0.0, im = 0.0;
+  for (int b = lane; b < Dr; b += 64) {
+    if (diag_photons(ca, cr[b], d) < 0) continue;
+    const cd x = cscale(cmul(G[b], En[b]), lr[b]);
+    re += x.re;
+    im += x.im;
+  }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (lane == 0) E[(size_t)j * chi + a] = cmk(re, im);
+}
+
+// one thread per column b of site j
+__global__ __launch_bounds__(256) void k_env_left(State st, int j, cd *L) {
+  const int chi = st.chi, d = st.d;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int Dl = st.dim[j], Dr = st.dim[j + 1];
+  if (b >= Dr) return;
+  const int cb = st.chg[(size_t)(j + 1) * chi + b];
+  const cd *G = st.gam + (size_t)j * chi * chi + b;
+  const cd *Lp = L + (size_t)j * chi;
+  const double *ll = st.lam + (size_t)j * chi;
+  const int *cl = st.chg + (size_t)j * chi;
+  cd acc = cmk(0.0, 0.0);
+  for (int a = 0; a < Dl; ++a) {
+    if (diag_photons(cl[a], cb, d) < 0) continue;
+    cfma(acc, cscale(Lp[a], ll[a]), G[(size_t)a * chi]);
+  }
+  L[(size_t)(j + 1) * chi + b] = acc;
+}
+
+__global__ void k_env_init(State st, cd *L, cd *E, double *P) {
+  const int chi = st.chi;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < chi; i += gridDim.x * blockDim.x) {
+    L[i] = cmk(1.0, 0.0);
+    E[(size_t)st.M * chi + i] = cmk(i == 0 ? 1.0 : 0.0, 0.0);
+  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < st.M * st.d;
+       i += gridDim.x * blockDim.x)
+    P[i] = 0.0;
+}
+
+// one wavefront per row a of site j = blockIdx.y
+__global__ __launch_bounds__(256) void k_marg(State st, const cd *L, const cd *E, double *P) {
+  const int chi = st.chi, d = st.d;
+  const int j = blockIdx.y;
+  const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  __shared__ double s_bin[4][16];
+  for (int i = threadIdx.x; i < 64; i += blockDim.x) (&s_bin[0][0])[i] = 0.0;
+  __syncthreads();
+  const int Dl = st.dim[j], Dr = st.dim[j + 1];
+  if (a < Dl) {
+    const int ca = st.chg[(size_t)j * chi + a];
+    const cd la = cscale(L[(size_t)j * chi + a], st.lam[(size_t)j * chi + a]);
+    const cd *G = st.gam + (size_t)j * chi * chi + (size_t)a * chi;
+    const cd *En = E + (size_t)(j + 1) * chi;
+    const double *lr = st.lam + (size_t)(j + 1) * chi;
+    const int *cr = st.chg + (size_t)(j + 1) * chi;
+    for (int n = 0; n < d; ++n) {
+      double re = 0.0;
+      for (int b = lane; b < Dr; b += 64) {
+        if (diag_photons(ca, cr[b], d) != n) continue;
+        const cd x = cmul(cmul(la, G[b]), cscale(En[b], lr[b]));
+        re += x.re;
+      }
+      re = wave_sum(re);
+      if (lane == 0) s_bin[threadIdx.x >> 6][n] = re;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < d) {
+    const double v = s_bin[0][threadIdx.x] + s_bin[1][threadIdx.x] + s_bin[2][threadIdx.x] +
+                     s_bin[3][threadIdx.x];
+    if (v != 0.0) atomicAdd(&P[j * d + threadIdx.x], v);
+  }
+}
+
+__global__ void k_trace(State st, const cd *E, double *trace) {
+  __shared__ double s[4];
+  double acc = 0.0;
+  for (int a = threadIdx.x; a < st.dim[0]; a += blockDim.x) acc += st.lam[a] * E[a].re;
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) *trace = s[0] + s[1] + s[2] + s[3];
+}
+
+hipError_t launch_marginals(State st, cd *envL, cd *envR, double *P, double *trace,
+                            hipStream_t s) {
+  const int chi = st.chi;
+  hipLaunchKernelGGL(k_env_init, dim3((chi + 255) / 256), dim3(256), 0, s, st, envL, envR, P);
+  for (int j = st.M - 1; j >= 0; --j)
+    hipLaunchKernelGGL(k_env_right, dim3((chi + 3) / 4), dim3(256), 0, s, st, j, envR);
+  for (int j = 0; j < st.M; ++j)
+    hipLaunchKernelGGL(k_env_left, dim3((chi + 255) / 256), dim3(256), 0, s, st, j, envL);
+  hipLaunchKernelGGL(k_marg, dim3((chi + 3) / 4, st.M), dim3(256), 0, s, st, envL, envR, P);
+  hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, s, st, envR, trace);
+  return hipGetLastError();
+}
+
+// Output phase screen: Gamma_j[a, b] *= e^{i phase_j (m - m')}, (m, m') = c_a - c_b.
+__global__ void k_phases(State st, const double *phase) {
+  const int j = blockIdx.y;
+  const int chi = st.chi;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)chi * chi) return;
+  const int a = (int)(idx / chi), b = (int)(idx % chi);
+  if (a >= st.dim[j] || b >= st.dim[j + 1]) return;
+  const int ca = st.chg[(size_t)j * chi + a], cb = st.chg[(size_t)(j + 1) * chi + b];
+  const int dm = (charge_n(ca) - charge_n(cb)) - (charge_np(ca) - charge_np(cb));
+  const double ang = phase[j] * dm;
+  cd *G = st.gam + (size_t)j * chi * chi + idx;
+  *G = cmul(*G, cmk(cos(ang), sin(ang)));
+}
+
+hipError_t launch_phases(State st, const double *phase, hipStream_t s) {
+  const long long n = (long long)st.chi * st.chi;
+  hipLaunchKernelGGL(k_phases, dim3((unsigned)((n + 255) / 256), st.M), dim3(256), 0, s, st,
+                     phase);
+  return hipGetLastError();
+}
+
+}  // namespace gbs

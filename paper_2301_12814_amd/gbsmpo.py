@@ -1,0 +1,194 @@
+"""Thin ctypes binding of libgbsmpo.so (argument marshalling only).
+
+Every step of the simulation runs in the HIP kernels of the library; this
+module only converts Python/NumPy arguments to the C ABI declared in
+``include/gbs_mpo.h``.  There is no fallback: if the library is missing or
+fails to load, an error is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgbsmpo.so")
+
+MPO_OK, MPO_EINVAL, MPO_ENOMEM, MPO_EDEVICE, MPO_ENUMERIC, MPO_EBUSY = 0, -1, -2, -3, -4, -5
+MPO_FP64, MPO_MIXED = 0, 1
+
+_lib = None
+
+
+class GbsMpoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise GbsMpoError(MPO_EDEVICE, f"{LIB_PATH} not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        c_int, c_double, c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+        pd = ctypes.POINTER(ctypes.c_double)
+        pi = ctypes.POINTER(ctypes.c_int)
+        pll = ctypes.POINTER(ctypes.c_longlong)
+        L.mpo_init_lossy_squeezed.argtypes = [c_int, pd, c_double, c_int, c_int, c_int, c_void_p,
+                                              ctypes.POINTER(c_void_p)]
+        L.mpo_apply_bs_layer.argtypes = [c_void_p, c_int, pi, pd, pd]
+        L.mpo_apply_phases.argtypes = [c_void_p, pd]
+        L.mpo_entropy.argtypes = [c_void_p, pd, pd]
+        L.mpo_photon_marginals.argtypes = [c_void_p, pd, pd]
+        L.mpo_sync.argtypes = [c_void_p]
+        L.mpo_get_bond.argtypes = [c_void_p, c_int, pi, pd, pi]
+        L.mpo_get_site.argtypes = [c_void_p, c_int, pd]
+        L.mpo_layer_stats.argtypes = [c_void_p, pll]
+        L.mpo_free.argtypes = [c_void_p]
+        L.mpo_free.restype = None
+        L.mpo_last_error.restype = ctypes.c_char_p
+        L.gbs_clements_decompose.argtypes = [c_int, pd, pi, pi, pd, pd, pd]
+        L.mpo_set_profiling.argtypes = [c_void_p, c_int]
+        L.mpo_get_profile.argtypes = [c_void_p, pd, pll, pd]
+        for name in ("mpo_set_profiling", "mpo_get_profile", "mpo_init_lossy_squeezed", "mpo_apply_bs_layer", "mpo_apply_phases",
+                     "mpo_entropy", "mpo_photon_marginals", "mpo_sync", "mpo_get_bond",
+                     "mpo_get_site", "mpo_layer_stats", "gbs_clements_decompose"):
+            getattr(L, name).restype = c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc < 0:
+        raise GbsMpoError(rc, lib().mpo_last_error().decode())
+    return rc
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(int(stream.cuda_stream))      # torch.cuda.Stream
+
+
+def clements(U: np.ndarray):
+    """Library Clements decomposition: (layers, phases); each layer is a tuple of
+    arrays (left_site int32, theta, phi) in application order."""
+    U = np.ascontiguousarray(U, dtype=complex)
+    M = U.shape[0]
+    G = M * (M - 1) // 2
+    ure = np.ascontiguousarray(np.stack([U.real, U.imag], axis=-1).reshape(-1))
+    ptr = np.zeros(M + 1, dtype=np.int32)
+    site = np.zeros(max(G, 1), dtype=np.int32)
+    th = np.zeros(max(G, 1))
+    ph = np.zeros(max(G, 1))
+    phase = np.zeros(M)
+    nl = _check(lib().gbs_clements_decompose(M, _dp(ure), _ip(ptr), _ip(site), _dp(th), _dp(ph),
+                                             _dp(phase)))
+    layers = [(site[ptr[l]:ptr[l + 1]].copy(), th[ptr[l]:ptr[l + 1]].copy(),
+               ph[ptr[l]:ptr[l + 1]].copy()) for l in range(nl)]
+    return layers, phase
+
+
+class MPO:
+    """One simulation: lossy squeezed product state evolved by beam-splitter layers."""
+
+    def __init__(self, M, r, eta, d, chi, precision=MPO_FP64, stream=None):
+        L = lib()
+        r = np.ascontiguousarray(np.broadcast_to(np.asarray(r, dtype=float), (M,)))
+        h = ctypes.c_void_p()
+        _check(L.mpo_init_lossy_squeezed(int(M), _dp(r), float(eta), int(d), int(chi),
+                                         int(precision), _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self.M, self.d, self.chi = int(M), int(d), int(chi)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mpo_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def apply_layer(self, sites, theta, phi):
+        sites = np.ascontiguousarray(sites, dtype=np.int32)
+        theta = np.ascontiguousarray(theta, dtype=float)
+        phi = np.ascontiguousarray(phi, dtype=float)
+        _check(lib().mpo_apply_bs_layer(self._h, len(sites), _ip(sites), _dp(theta), _dp(phi)))
+
+    def apply_phases(self, phase):
+        phase = np.ascontiguousarray(phase, dtype=float)
+        _check(lib().mpo_apply_phases(self._h, _dp(phase)))
+
+    def entropy(self):
+        S = np.zeros(max(self.M - 1, 1))
+        smax = ctypes.c_double()
+        _check(lib().mpo_entropy(self._h, _dp(S), ctypes.byref(smax)))
+        return S[: self.M - 1], smax.value
+
+    def marginals(self):
+        P = np.zeros(self.M * self.d)
+        tr = ctypes.c_double()
+        _check(lib().mpo_photon_marginals(self._h, _dp(P), ctypes.byref(tr)))
+        return P.reshape(self.M, self.d), tr.value
+
+    def bond(self, b):
+        D = ctypes.c_int()
+        lam = np.zeros(self.chi)
+        ch = np.zeros(2 * self.chi, dtype=np.int32)
+        _check(lib().mpo_get_bond(self._h, int(b), ctypes.byref(D), _dp(lam), _ip(ch)))
+        n = D.value
+        return lam[:n].copy(), ch[: 2 * n].reshape(n, 2).copy()
+
+    def site(self, j):
+        G = np.zeros(2 * self.chi * self.chi)
+        _check(lib().mpo_get_site(self._h, int(j), _dp(G)))
+        Dl = self.bond(j)[0].shape[0]
+        Dr = self.bond(j + 1)[0].shape[0]
+        return (G[0::2] + 1j * G[1::2])[: Dl * Dr].reshape(Dl, Dr)
+
+    def layer_stats(self):
+        s = (ctypes.c_longlong * 6)()
+        _check(lib().mpo_layer_stats(self._h, s))
+        keys = ("blocks", "elements", "candidates", "max_rows", "max_cols", "max_sweeps")
+        return dict(zip(keys, list(s)))
+
+    def sync(self):
+        _check(lib().mpo_sync(self._h))
+
+    PHASES = ("fock", "plan", "contract", "svd", "select", "scatter", "entropy", "unused")
+
+    def set_profiling(self, on: bool = True):
+        _check(lib().mpo_set_profiling(self._h, 1 if on else 0))
+
+    def profile(self):
+        """(per-phase summed ms, per-phase timed layers, work dict)."""
+        ms = np.zeros(8)
+        n = np.zeros(8, dtype=np.int64)
+        work = np.zeros(4)
+        _check(lib().mpo_get_profile(self._h, _dp(ms),
+                                     n.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
+                                     _dp(work)))
+        return (dict(zip(self.PHASES, ms.tolist())), dict(zip(self.PHASES, n.tolist())),
+                dict(svd_flops=work[0], elements=work[1], candidates=work[2], layers=work[3]))

@@ -1,0 +1,227 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Bars: bond charges bit-exact; Schmidt values within 1e-10 relative (plus
+1e-12 of the bond's largest value, the absolute accuracy of the oracle's dense
+LAPACK SVD); entropies within 1e-10; photon marginals and trace within 1e-10.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import brute, clements as oclem, mpo as omp, states
+from paper_2301_12814_amd import gbsmpo, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rhos_of(w):
+    return [states.lossy_squeezed_rho(r, w.eta, w.d) for r in w.r]
+
+
+def assert_bond_equal(lam, ch, olam, och, ctx, rtol=1e-10, atol_rel=1e-12):
+    assert lam.shape == olam.shape, (ctx, lam.shape, olam.shape)
+    assert np.array_equal(ch, och), ctx
+    if len(lam):
+        err = np.abs(lam - olam)
+        tol = rtol * np.abs(olam) + atol_rel * np.abs(olam).max()
+        assert np.all(err <= tol), (ctx, float((err / np.maximum(tol, 1e-300)).max()))
+
+
+def compare_state(g, o, ctx, **kw):
+    for b in range(o.M + 1):
+        lam, ch = g.bond(b)
+        assert_bond_equal(lam, ch, o.lam[b], o.charge[b], f"{ctx} bond {b}", **kw)
+    S, _ = g.entropy()
+    assert np.abs(S - o.entropies()).max() < 1e-10, ctx
+
+
+def test_gpu_init_small_matches_oracle():
+    w = inputs.workload("small")
+    say("init small", w)
+    with gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi) as g:
+        o = omp.DenseMPO.product(rhos_of(w), w.chi)
+        compare_state(g, o, "init", rtol=1e-12)
+        P, tr = g.marginals()
+        oP, otr, _ = o.marginals()
+        assert abs(tr - otr) < 1e-13
+        assert np.abs(P - oP).max() < 1e-13
+
+
+def test_gpu_small_workload_full_run():
+    """Whole small-workload run (8 modes, 28 beam splitters, chi=32): every bond
+    after every layer, then marginals and trace, against the oracle."""
+    w = inputs.workload("small")
+    U = inputs.haar_unitary(w.M, w.seed)
+    layers, phase = gbsmpo.clements(U)
+    og, oph = oclem.decompose(U)
+    olayers = oclem.layers(w.M, og)
+    o = omp.DenseMPO.product(rhos_of(w), w.chi)
+    with gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi) as g:
+        for li, (S, T, P) in enumerate(layers):
+            say("small layer", li)
+            g.apply_layer(S, T, P)
+            for (k, th, ph) in olayers[li]:
+                o.apply_gate(k, th, ph, w.chi)
+            compare_state(g, o, f"layer {li}")
+        g.apply_phases(phase)
+        o.apply_phases(oph)
+        P, tr = g.marginals()
+        oP, otr, _ = o.marginals()
+        assert abs(tr - otr) < 1e-10 * otr
+        assert np.abs(P - oP).max() < 1e-10
+        _, smax = g.entropy()
+        assert smax >= o.entropies().max() - 1e-12
+
+
+@pytest.mark.parametrize("M,d,r,eta,seed", [(3, 4, [0.7, 0.4, 0.9], 0.6, 11),
+                                            (4, 3, [0.9, 0.0, 0.4, 0.7], 0.6, 12)])
+def test_gpu_untruncated_matches_brute_force(M, d, r, eta, seed):
+    """chi above every rank: the library's marginals and trace equal the full
+    density-matrix evolution."""
+    chi = 512
+    U = inputs.haar_unitary(M, seed)
+    layers, phase = gbsmpo.clements(U)
+    rhos = [states.lossy_squeezed_rho(x, eta, d) for x in r]
+    rho = brute.product_rho(rhos)
+    og, oph = oclem.decompose(U)
+    for (k, th, ph) in og:
+        rho = brute.apply_gate(rho, k, th, ph)
+    rho = brute.apply_phases(rho, oph)
+    say("brute", M, d)
+    with gbsmpo.MPO(M, r, eta, d, chi) as g:
+        for (S, T, P) in layers:
+            g.apply_layer(S, T, P)
+        g.apply_phases(phase)
+        P, tr = g.marginals()
+    bP, btr = brute.marginals(rho)
+    assert abs(tr - btr) < 1e-12
+    assert np.abs(P - bP).max() < 1e-12
+
+
+def test_gpu_medium_shape_reduced_chi_matches_oracle():
+    """Medium shape (M=32, d=8, r=0.8, sqrt-scaling eta) at chi=16 so that the
+    dense oracle stays fast: the first four layers, bond by bond."""
+    w = inputs.workload("medium")
+    chi = 16
+    U = inputs.haar_unitary(w.M, w.seed)
+    layers, _ = gbsmpo.clements(U)
+    og, _ = oclem.decompose(U)
+    olayers = oclem.layers(w.M, og)
+    o = omp.DenseMPO.product(rhos_of(w), chi)
+    with gbsmpo.MPO(w.M, w.r, w.eta, w.d, chi) as g:
+        compare_state(g, o, "init", rtol=1e-12)
+        for li in range(4):
+            say("medium-shape layer", li)
+            S, T, P = layers[li]
+            g.apply_layer(S, T, P)
+            for (k, th, ph) in olayers[li]:
+                o.apply_gate(k, th, ph, chi)
+            compare_state(g, o, f"layer {li}")
+        P, tr = g.marginals()
+        oP, otr, _ = o.marginals()
+        assert abs(tr - otr) < 1e-10 * otr
+        assert np.abs(P - oP).max() < 1e-10
+
+
+@pytest.mark.parametrize("name", ["medium", "large"])
+def test_gpu_full_size_initial_state(name):
+    """Full-size initial states (chi = 256 / 1024): every bond's kept charges
+    and Schmidt values against the oracle's closed form."""
+    w = inputs.workload(name)
+    say("init", name)
+    bonds = omp.product_bonds(rhos_of(w), w.chi)
+    with gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi) as g:
+        for b in range(w.M + 1):
+            lam, ch = g.bond(b)
+            assert_bond_equal(lam, ch, bonds[b][1], bonds[b][0], f"{name} bond {b}", rtol=1e-12)
+        S, _ = g.entropy()
+        for b in range(1, w.M):
+            p = bonds[b][1] ** 2
+            p = p / p.sum()
+            assert abs(S[b - 1] + (p * np.log2(p)).sum()) < 1e-11
+
+
+def _mirror_ok(lam, ch, rtol):
+    byq = {}
+    for q, l in zip(map(tuple, ch), lam):
+        byq.setdefault(q, []).append(l)
+    for q, ls in byq.items():
+        m = byq.get((q[1], q[0]))
+        if m is None or len(m) != len(ls):
+            return False
+        if not np.allclose(np.sort(ls), np.sort(m), rtol=rtol, atol=0):
+            return False
+    return True
+
+
+def test_gpu_large_first_layers_invariants():
+    """Large workload (M=64, d=8, chi=1024), first two layers at full size:
+    properties that hold at any size (bond sizes, mirror-symmetric spectra from
+    Hermiticity, non-increasing trace, finite entropies)."""
+    w = inputs.workload("large")
+    U = inputs.haar_unitary(w.M, w.seed)
+    layers, _ = gbsmpo.clements(U)
+    with gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi) as g:
+        _, tr0 = g.marginals()
+        for li in range(2):
+            say("large layer", li)
+            g.apply_layer(*layers[li])
+            st = g.layer_stats()
+            say(st)
+            for k in layers[li][0]:
+                lam, ch = g.bond(int(k) + 1)
+                assert 0 < len(lam) <= w.chi
+                assert _mirror_ok(lam, ch, 1e-9)
+        _, tr = g.marginals()
+        assert tr <= tr0 * (1 + 1e-12)
+        S, smax = g.entropy()
+        assert np.all(np.isfinite(S)) and smax > 0
+
+
+def test_gpu_edge_cases():
+    # all-vacuum input: one charge, zero entropy, P = delta_{n0}
+    with gbsmpo.MPO(4, 0.0, 0.5, 3, 8) as g:
+        g.apply_layer([0, 2], [0.4, 0.9], [0.1, 2.0])
+        g.apply_layer([1], [0.3], [0.5])
+        S, smax = g.entropy()
+        assert np.all(S == 0) and smax == 0
+        P, tr = g.marginals()
+        assert abs(tr - 1) < 1e-15 and np.allclose(P[:, 0], 1) and np.allclose(P[:, 1:], 0)
+    # chi = 1 and d = 2 (smallest sizes)
+    with gbsmpo.MPO(3, [0.5, 0.2, 0.0], 0.7, 2, 1) as g:
+        g.apply_layer([0], [0.7], [0.3])
+        lam, ch = g.bond(1)
+        assert len(lam) == 1
+    # identity gate leaves bonds unchanged; phases leave EE and marginals unchanged
+    w = inputs.workload("small")
+    with gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi) as g:
+        before = [g.bond(b) for b in range(w.M + 1)]
+        S0, _ = g.entropy()
+        P0, tr0 = g.marginals()
+        g.apply_layer([0, 2, 4, 6], [0.0] * 4, [0.0] * 4)
+        for b in range(w.M + 1):
+            lam, ch = g.bond(b)
+            assert np.array_equal(ch, before[b][1])
+            assert np.allclose(lam, before[b][0], rtol=1e-13)
+        g.apply_phases(np.linspace(-2, 2, w.M))
+        S1, _ = g.entropy()
+        P1, tr1 = g.marginals()
+        assert np.abs(S1 - S0).max() < 1e-12 and np.abs(P1 - P0).max() < 1e-12
+        # invalid arguments are rejected and leave the state unchanged
+        with pytest.raises(gbsmpo.GbsMpoError):
+            g.apply_layer([0, 1], [0.1, 0.2], [0.0, 0.0])        # overlapping gates
+        with pytest.raises(gbsmpo.GbsMpoError):
+            g.apply_layer([7], [0.1], [0.0])                      # out of range
+        S2, _ = g.entropy()
+        assert np.array_equal(S1, S2)
+    with pytest.raises(gbsmpo.GbsMpoError):
+        gbsmpo.MPO(4, 0.5, 1.5, 4, 8)                             # eta > 1
+    with pytest.raises(gbsmpo.GbsMpoError):
+        gbsmpo.MPO(4, -0.1, 0.5, 4, 8)                            # r < 0
