@@ -216,6 +216,8 @@ extern "C" int mpo_init_lossy_squeezed(int M, const double *r, double eta, int d
   TRY(dalloc(h, &ly.blk, (size_t)max_gates * cap_g));
   TRY(dalloc(h, &ly.tot, max_gates));
   TRY(dalloc(h, &ly.base, max_gates));
+  TRY(dalloc(h, &ly.mirL, (size_t)max_gates * chi));
+  TRY(dalloc(h, &ly.mirR, (size_t)max_gates * chi));
   TRY(dalloc(h, &ly.rows, (size_t)max_gates * cap_g));
   TRY(dalloc(h, &ly.cols, (size_t)max_gates * cap_g));
   TRY(dalloc(h, &ly.sv, (size_t)max_gates * cap_g));

@@ -101,11 +101,38 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
   BlkDesc *blk = ly.blk + (size_t)g * ly.max_blk;
   int *rows = ly.rows + (size_t)g * rows_cap;
   int *cols = ly.cols + (size_t)g * rows_cap;
+  int *mirL = ly.mirL + (size_t)g * chi;
+  int *mirR = ly.mirR + (size_t)g * chi;
+  const double *lamL = st.lam + (size_t)j * chi;
+  const double *lamR = st.lam + (size_t)(j + 2) * chi;
+  __shared__ int s_sym;
   __shared__ int s_min1L, s_max1L, s_min1R, s_max1R;
   __shared__ long long s_scan[17];
   __shared__ int s_iscan[17];
   if (threadIdx.x == 0) {
     s_min1L = 1 << 30; s_max1L = -1; s_min1R = 1 << 30; s_max1R = -1;
+    s_sym = 1;
+  }
+  __syncthreads();
+  // pass 0: mirror index maps.  The mirror of index a (charge (n, n'), rank k
+  // inside its charge run) is the index of charge (n', n) with the same rank.
+  // The gate exploits Hermiticity only when both outer bonds are exactly
+  // mirror symmetric (same charges, bitwise equal Schmidt values).
+  for (int a = threadIdx.x; a < DL; a += blockDim.x) {
+    const int c = cL[a];
+    const int cm = pack_charge(charge_np(c), charge_n(c));
+    const int am = lower_bound(cL, DL, cm) + (a - lower_bound(cL, DL, c));
+    const bool ok = am < DL && cL[am] == cm && lamL[am] == lamL[a];
+    mirL[a] = ok ? am : -1;
+    if (!ok) s_sym = 0;
+  }
+  for (int b = threadIdx.x; b < DR; b += blockDim.x) {
+    const int c = cR[b];
+    const int cm = pack_charge(charge_np(c), charge_n(c));
+    const int bm = lower_bound(cR, DR, cm) + (b - lower_bound(cR, DR, c));
+    const bool ok = bm < DR && cR[bm] == cm && lamR[bm] == lamR[b];
+    mirR[b] = ok ? bm : -1;
+    if (!ok) s_sym = 0;
   }
   __syncthreads();
   {
@@ -183,6 +210,21 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
   }
   __syncthreads();
   const int nblk = (int)min(nb, (long long)ly.max_blk);
+  const int sym = s_sym;
+  // mirror block by binary search on the sorted charges; with symmetric outer
+  // bonds only canonical (n <= n') blocks are computed, mirrors are derived
+  for (int bi = threadIdx.x; bi < nblk; bi += blockDim.x) {
+    BlkDesc &B = blk[bi];
+    const int qm = pack_charge(charge_np(B.q), charge_n(B.q));
+    int lo = 0, hi = nblk;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (blk[mid].q < qm) lo = mid + 1; else hi = mid;
+    }
+    B.mirror = (lo < nblk && blk[lo].q == qm) ? lo : -1;
+    B.comp = !(sym && B.mirror >= 0 && charge_n(B.q) > charge_np(B.q));
+  }
+  __syncthreads();
   // pass 2: offsets
   long long eb = 0, vb = 0;
   int svb = 0, rb = 0, cb = 0, chb = 0, maxr = 0, maxc = 0;
@@ -193,13 +235,15 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
     int sv = 0, r = 0, c = 0, ch = 0;
     if (bi < nblk) {
       const BlkDesc &B = blk[bi];
-      e = (long long)B.r * B.s;
-      v = (long long)B.n * B.n;
-      sv = B.n;
+      if (B.comp) {
+        e = (long long)B.r * B.s;
+        v = (long long)B.n * B.n;
+        sv = B.n;
+        ch = (int)((e + CHUNK - 1) / CHUNK);
+        fl += 16.0 * B.m * (double)B.n * B.n + 36.0 * (double)B.n * B.n * B.n;
+      }
       r = B.r;
       c = B.s;
-      ch = (int)((e + CHUNK - 1) / CHUNK);
-      fl += 16.0 * B.m * (double)B.n * B.n + 36.0 * (double)B.n * B.n * B.n;
       maxr = max(maxr, B.r);
       maxc = max(maxc, B.s);
     }
@@ -219,14 +263,6 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
       B.roff = pr;
       B.coff = pc;
       B.uoff = pch;   // chunk offset until the select kernel reuses the field
-      // mirror block by binary search on the sorted charges
-      const int qm = pack_charge(charge_np(B.q), charge_n(B.q));
-      int lo = 0, hi = nblk;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (blk[mid].q < qm) lo = mid + 1; else hi = mid;
-      }
-      B.mirror = (lo < nblk && blk[lo].q == qm) ? lo : -1;
     }
     eb += te; vb += tv; svb += tsv; rb += tr; cb += tc; chb += tch;
   }
@@ -272,6 +308,7 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
     tot.elems = eb;
     tot.vsz = vb;
     tot.chunks = chb;
+    tot.sym = sym;
     tot.svd_flops = s_fl;
     ly.tot[g] = tot;
   }
@@ -380,17 +417,36 @@ hipError_t launch_contract(State st, Layer ly, hipStream_t s) {
 // convergence A = U Sigma with orthogonal columns and A0 = U Sigma V^H.
 // ----------------------------------------------------------------------------
 constexpr int SVD_THREADS = 256;
+constexpr int SVD_LDS_THREADS = 512;
 constexpr int MAX_SWEEPS = 60;
+constexpr int RPL = 8;        // column rows cached per lane (m <= 512)
 
-__device__ inline void jacobi_pair(cd *A, int m, cd *V, int n, int p, int q, int lane,
-                                   double tol, int &rot) {
+// Rotation of the column pair (p, q) of A (m x n) and of the right factor V.
+__device__ __forceinline__ void jacobi_pair(cd *A, int m, cd *V, int n, int p, int q, int lane,
+                                            double tol, int &rot) {
+  cd *xp = A + (size_t)p * m, *xq = A + (size_t)q * m;
   double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
-  for (int i = lane; i < m; i += 64) {
-    const cd x = A[(size_t)p * m + i], y = A[(size_t)q * m + i];
-    al += cabs2(x);
-    be += cabs2(y);
-    gr += x.re * y.re + x.im * y.im;
-    gi += x.re * y.im - x.im * y.re;
+  const bool cached = m <= 64 * RPL;
+  cd rx[RPL], ry[RPL];
+  if (cached) {
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+      const int i = lane + 64 * k;
+      rx[k] = i < m ? xp[i] : cmk(0.0, 0.0);
+      ry[k] = i < m ? xq[i] : cmk(0.0, 0.0);
+      al += cabs2(rx[k]);
+      be += cabs2(ry[k]);
+      gr += rx[k].re * ry[k].re + rx[k].im * ry[k].im;
+      gi += rx[k].re * ry[k].im - rx[k].im * ry[k].re;
+    }
+  } else {
+    for (int i = lane; i < m; i += 64) {
+      const cd x = xp[i], y = xq[i];
+      al += cabs2(x);
+      be += cabs2(y);
+      gr += x.re * y.re + x.im * y.im;
+      gi += x.re * y.im - x.im * y.re;
+    }
   }
   al = wave_sum(al);
   be = wave_sum(be);
@@ -403,96 +459,225 @@ __device__ inline void jacobi_pair(cd *A, int m, cd *V, int n, int p, int q, int
   const double c = 1.0 / sqrt(1.0 + t * t);
   const double s = c * t;
   const cd e = cmk(gr / ga, -gi / ga);      // e^{-i psi}
-  for (int i = lane; i < m; i += 64) {
-    const cd x = A[(size_t)p * m + i];
-    const cd y = cmul(e, A[(size_t)q * m + i]);
-    A[(size_t)p * m + i] = csub(cscale(x, c), cscale(y, s));
-    A[(size_t)q * m + i] = cadd(cscale(x, s), cscale(y, c));
+  if (cached) {
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+      const int i = lane + 64 * k;
+      if (i < m) {
+        const cd y = cmul(e, ry[k]);
+        xp[i] = csub(cscale(rx[k], c), cscale(y, s));
+        xq[i] = cadd(cscale(rx[k], s), cscale(y, c));
+      }
+    }
+  } else {
+    for (int i = lane; i < m; i += 64) {
+      const cd x = xp[i];
+      const cd y = cmul(e, xq[i]);
+      xp[i] = csub(cscale(x, c), cscale(y, s));
+      xq[i] = cadd(cscale(x, s), cscale(y, c));
+    }
   }
+  cd *vp = V + (size_t)p * n, *vq = V + (size_t)q * n;
   for (int i = lane; i < n; i += 64) {
-    const cd x = V[(size_t)p * n + i];
-    const cd y = cmul(e, V[(size_t)q * n + i]);
-    V[(size_t)p * n + i] = csub(cscale(x, c), cscale(y, s));
-    V[(size_t)q * n + i] = cadd(cscale(x, s), cscale(y, c));
+    const cd x = vp[i];
+    const cd y = cmul(e, vq[i]);
+    vp[i] = csub(cscale(x, c), cscale(y, s));
+    vq[i] = cadd(cscale(x, s), cscale(y, c));
   }
   rot = 1;
 }
 
-__global__ __launch_bounds__(SVD_THREADS) void k_svd(State st, Layer ly, int sv_cap) {
-  const int flat = blockIdx.x;
-  const int g = find_gate_blk(ly.base, ly.ngates, flat);
-  const GateBase gb = ly.base[g];
-  BlkDesc *Bp = ly.blk + (size_t)g * ly.max_blk + (flat - gb.blk);
-  const int m = Bp->m, n = Bp->n;
-  cd *A = ly.A + gb.e + Bp->eoff;
-  cd *V = ly.V + gb.v + Bp->voff;
-  double *sv = ly.sv + (size_t)g * sv_cap + Bp->svoff;
-  int *perm = ly.perm + (size_t)g * sv_cap + Bp->svoff;
+// Cyclic sweeps in round-robin order until a sweep makes no rotation.
+// Returns the number of sweeps (MAX_SWEEPS when not converged).
+__device__ __forceinline__ int jacobi_sweeps(cd *A, int m, cd *V, int n, int *s_rot) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nw = SVD_THREADS / 64;
-  for (int idx = threadIdx.x; idx < n * n; idx += SVD_THREADS)
-    V[idx] = cmk((idx % n) == (idx / n) ? 1.0 : 0.0, 0.0);
-  __shared__ int s_rot;
-  __syncthreads();
+  const int nw = blockDim.x >> 6;
   const int np = n + (n & 1);
   // rotate while |x^H y| > tol |x| |y|; tol covers the rounding of an m-term dot product
   const double tol = fmax(1e-15, 2.3e-16 * m);
   int sweep = 0;
-  if (n > 1) {
-    for (sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
-      if (threadIdx.x == 0) s_rot = 0;
-      __syncthreads();
-      int rot = 0;
-      for (int round = 0; round < np - 1; ++round) {
-        for (int k = wave; k < np / 2; k += nw) {
-          int p, q;
-          if (k == 0) {
-            p = round;
-            q = np - 1;
-          } else {
-            p = (round + k) % (np - 1);
-            q = (round - k + np - 1) % (np - 1);
-          }
-          if (p >= n || q >= n) continue;
-          jacobi_pair(A, m, V, n, p, q, lane, tol, rot);
+  if (n <= 1) return 0;
+  for (sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
+    if (threadIdx.x == 0) *s_rot = 0;
+    __syncthreads();
+    int rot = 0;
+    for (int round = 0; round < np - 1; ++round) {
+      for (int k = wave; k < np / 2; k += nw) {
+        int p, q;
+        if (k == 0) {
+          p = round;
+          q = np - 1;
+        } else {
+          p = (round + k) % (np - 1);
+          q = (round - k + np - 1) % (np - 1);
         }
-        __syncthreads();
+        if (p >= n || q >= n) continue;
+        jacobi_pair(A, m, V, n, p, q, lane, tol, rot);
       }
-      if (rot) s_rot = 1;
       __syncthreads();
-      const int any = s_rot;
-      __syncthreads();
-      if (!any) break;
     }
-    if (sweep == MAX_SWEEPS && threadIdx.x == 0) atomicOr(st.err, ERR_SVD_NOT_CONVERGED);
+    if (rot) *s_rot = 1;
+    __syncthreads();
+    const int any = *s_rot;
+    __syncthreads();
+    if (!any) break;
   }
-  // singular values = column norms, sorted descending (ties by column)
-  extern __shared__ double s_sig[];
-  for (int c = threadIdx.x; c < n; c += SVD_THREADS) {
-    double acc = 0.0;
-    for (int i = 0; i < m; ++i) acc += cabs2(A[(size_t)c * m + i]);
-    s_sig[c] = sqrt(acc);
+  return sweep;
+}
+
+// Self-mirror block (q = (n, n)) of a Hermitian state: Theta[a~, b~] =
+// conj(Theta[a, b]) with a~ the mirror index, so every non-degenerate left
+// singular vector is J-real up to a phase, v[a~] = e^{i phi} conj(v[a]).
+// The bilinear sum s = sum_a v[a] v[a~] = e^{i phi} |v|^2 gives the phase;
+// both factors of the column are multiplied by e^{-i phi / 2}.
+__device__ __forceinline__ void self_mirror_phase(const State &st, const Layer &ly, int g,
+                                                  const BlkDesc &B, cd *A, cd *V,
+                                                  int rows_cap) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int m = B.m, n = B.n, r = B.r;
+  const int *rl = ly.rows + (size_t)g * rows_cap + B.roff;
+  const int *mL = ly.mirL + (size_t)g * st.chi;
+  cd *X = !B.t ? A : V;          // stored columns indexed by the left-bond rows
+  const int ld = !B.t ? m : n;
+  for (int c = wave; c < n; c += nw) {
+    double sr = 0.0, si = 0.0, nr = 0.0;
+    for (int ia = lane; ia < r; ia += 64) {
+      const int am = lower_bound(rl, r, mL[rl[ia]]);
+      const cd x = X[(size_t)c * ld + ia], y = X[(size_t)c * ld + am];
+      const cd p = cmul(x, y);
+      sr += p.re;
+      si += p.im;
+      nr += cabs2(x);
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    nr = wave_sum(nr);
+    const double sa = sqrt(sr * sr + si * si);
+    if (sa > 0.5 * nr && sa > 0.0) {
+      const double ang = -0.5 * atan2(si, sr);
+      const cd f = cmk(cos(ang), sin(ang));
+      for (int i = lane; i < m; i += 64) A[(size_t)c * m + i] = cmul(A[(size_t)c * m + i], f);
+      for (int i = lane; i < n; i += 64) V[(size_t)c * n + i] = cmul(V[(size_t)c * n + i], f);
+    }
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < n; c += SVD_THREADS) {
-    const double v = s_sig[c];
+}
+
+// Singular values = column norms, sorted descending (ties by column).
+__device__ __forceinline__ void sort_values(const State &st, const cd *A, int m, int n,
+                                            double *sig, double *sv, int *perm) {
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    double acc = 0.0;
+    for (int i = 0; i < m; ++i) acc += cabs2(A[(size_t)c * m + i]);
+    sig[c] = sqrt(acc);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const double v = sig[c];
     int rank = 0;
     for (int o = 0; o < n; ++o) {
-      const double w = s_sig[o];
+      const double w = sig[o];
       rank += (w > v) || (w == v && o < c);
     }
     sv[rank] = v;
     perm[rank] = c;
     if (!isfinite(v)) atomicOr(st.err, ERR_NONFINITE);
   }
+}
+
+__device__ inline size_t lds_need(int m, int n) {
+  return sizeof(cd) * ((size_t)m * n + (size_t)n * n) + sizeof(double) * (size_t)n;
+}
+
+// Blocks whose operand and right factor fit in LDS: the whole Jacobi runs
+// on-chip; the factors are copied back for the scatter.
+__global__ __launch_bounds__(SVD_LDS_THREADS) void k_svd_lds(State st, Layer ly, int sv_cap,
+                                                             int rows_cap, int lds_bytes) {
+  const int flat = blockIdx.x;
+  const int g = find_gate_blk(ly.base, ly.ngates, flat);
+  const GateBase gb = ly.base[g];
+  BlkDesc *Bp = ly.blk + (size_t)g * ly.max_blk + (flat - gb.blk);
+  const BlkDesc B = *Bp;
+  if (!B.comp || lds_need(B.m, B.n) > (size_t)lds_bytes) return;
+  const int m = B.m, n = B.n;
+  extern __shared__ double s_dyn[];
+  cd *sA = reinterpret_cast<cd *>(s_dyn);
+  cd *sV = sA + (size_t)m * n;
+  double *sig = reinterpret_cast<double *>(sV + (size_t)n * n);
+  __shared__ int s_rot;
+  cd *A = ly.A + gb.e + B.eoff;
+  cd *V = ly.V + gb.v + B.voff;
+  for (int i = threadIdx.x; i < m * n; i += blockDim.x) sA[i] = A[i];
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x)
+    sV[idx] = cmk((idx % n) == (idx / n) ? 1.0 : 0.0, 0.0);
+  __syncthreads();
+  const int sweep = jacobi_sweeps(sA, m, sV, n, &s_rot);
+  if (sweep == MAX_SWEEPS && threadIdx.x == 0) atomicOr(st.err, ERR_SVD_NOT_CONVERGED);
+  if (charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym)
+    self_mirror_phase(st, ly, g, B, sA, sV, rows_cap);
+  sort_values(st, sA, m, n, sig, ly.sv + (size_t)g * sv_cap + B.svoff,
+              ly.perm + (size_t)g * sv_cap + B.svoff);
+  for (int i = threadIdx.x; i < m * n; i += blockDim.x) A[i] = sA[i];
+  for (int i = threadIdx.x; i < n * n; i += blockDim.x) V[i] = sV[i];
   if (threadIdx.x == 0) Bp->sweeps = sweep;
+}
+
+// Blocks too large for LDS: operand and right factor stay in global memory.
+__global__ __launch_bounds__(SVD_THREADS) void k_svd(State st, Layer ly, int sv_cap,
+                                                      int rows_cap, int lds_bytes) {
+  const int flat = blockIdx.x;
+  const int g = find_gate_blk(ly.base, ly.ngates, flat);
+  const GateBase gb = ly.base[g];
+  BlkDesc *Bp = ly.blk + (size_t)g * ly.max_blk + (flat - gb.blk);
+  const BlkDesc B = *Bp;
+  if (!B.comp) {                 // mirror block: derived from its canonical block
+    if (threadIdx.x == 0) Bp->sweeps = 0;
+    return;
+  }
+  if (lds_need(B.m, B.n) <= (size_t)lds_bytes) return;   // done by k_svd_lds
+  const int m = B.m, n = B.n;
+  cd *A = ly.A + gb.e + B.eoff;
+  cd *V = ly.V + gb.v + B.voff;
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x)
+    V[idx] = cmk((idx % n) == (idx / n) ? 1.0 : 0.0, 0.0);
+  __shared__ int s_rot;
+  __syncthreads();
+  const int sweep = jacobi_sweeps(A, m, V, n, &s_rot);
+  if (sweep == MAX_SWEEPS && threadIdx.x == 0) atomicOr(st.err, ERR_SVD_NOT_CONVERGED);
+  if (charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym)
+    self_mirror_phase(st, ly, g, B, A, V, rows_cap);
+  extern __shared__ double s_sig[];
+  sort_values(st, A, m, n, s_sig, ly.sv + (size_t)g * sv_cap + B.svoff,
+              ly.perm + (size_t)g * sv_cap + B.svoff);
+  if (threadIdx.x == 0) Bp->sweeps = sweep;
+}
+
+int svd_lds_bytes() {
+  static int bytes = -1;
+  if (bytes < 0) {
+    int dev = 0, v = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      v = 65536;
+    bytes = (v > 163840 ? 163840 : v) - 1024;   // room for static LDS
+    hipFuncSetAttribute((const void *)k_svd_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        bytes);
+  }
+  return bytes;
 }
 
 hipError_t launch_svd(State st, Layer ly, hipStream_t s) {
   if (ly.total_blocks == 0) return hipSuccess;
   const int sv_cap = st.d * st.d * st.chi;
+  const int lb = svd_lds_bytes();
+  hipLaunchKernelGGL(k_svd_lds, dim3(ly.total_blocks), dim3(SVD_LDS_THREADS), (size_t)lb, s, st,
+                     ly, sv_cap, sv_cap, lb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const size_t lds = sizeof(double) * (size_t)st.chi;
-  hipLaunchKernelGGL(k_svd, dim3(ly.total_blocks), dim3(SVD_THREADS), lds, s, st, ly, sv_cap);
+  hipLaunchKernelGGL(k_svd, dim3(ly.total_blocks), dim3(SVD_THREADS), lds, s, st, ly, sv_cap,
+                     sv_cap, lb);
   return hipGetLastError();
 }
 
@@ -525,12 +710,17 @@ __global__ __launch_bounds__(1024) void k_select(State st, Layer ly, int sv_cap)
   if (threadIdx.x == 0) s_max = 0.0;
   __syncthreads();
   double mx = 0.0;
-  for (int bi = threadIdx.x; bi < nblk; bi += blockDim.x) mx = fmax(mx, sv[blk[bi].svoff]);
+  for (int bi = threadIdx.x; bi < nblk; bi += blockDim.x)
+    if (blk[bi].comp) mx = fmax(mx, sv[blk[bi].svoff]);
   atomicMax((unsigned long long *)&s_max, (unsigned long long)__double_as_longlong(mx));
   __syncthreads();
   const double cut = 1e-14 * s_max;
   for (int bi = threadIdx.x; bi < nblk; bi += blockDim.x)
-    blk[bi].len = (s_max > 0.0) ? count_above(sv + blk[bi].svoff, blk[bi].n, cut) : 0;
+    if (blk[bi].comp)
+      blk[bi].len = (s_max > 0.0) ? count_above(sv + blk[bi].svoff, blk[bi].n, cut) : 0;
+  __syncthreads();
+  for (int bi = threadIdx.x; bi < nblk; bi += blockDim.x)   // derived blocks share the spectrum
+    if (!blk[bi].comp) blk[bi].len = blk[blk[bi].mirror].len;
   __syncthreads();
   // units owned by each block
   int ub = 0;
@@ -558,7 +748,8 @@ __global__ __launch_bounds__(1024) void k_select(State st, Layer ly, int sv_cap)
     if (!owner) continue;
     const bool paired = (q0 != q1) && (B.mirror >= 0);
     const int lp = paired ? blk[B.mirror].len : 0;
-    const double *sp = paired ? sv + blk[B.mirror].svoff : nullptr;
+    const double *sp =
+        paired ? sv + (blk[B.mirror].comp ? blk[B.mirror].svoff : B.svoff) : nullptr;
     const int cnt = paired ? max(B.len, lp) : B.len;
     const int canon = pack_charge(min(q0, q1), max(q0, q1));
     for (int i = 0; i < cnt; ++i) {
@@ -637,16 +828,25 @@ __global__ __launch_bounds__(256) void k_scatter(State st, Layer ly, int sv_cap,
   const int flat = blockIdx.x;
   const int g = find_gate_blk(ly.base, ly.ngates, flat);
   const GateBase gb = ly.base[g];
-  const BlkDesc B = ly.blk[(size_t)g * ly.max_blk + (flat - gb.blk)];
-  if (B.kq == 0) return;
+  const BlkDesc *blk = ly.blk + (size_t)g * ly.max_blk;
+  const BlkDesc B = blk[flat - gb.blk];
+  if (!B.comp || B.kq == 0) return;   // derived blocks are written by their canonical block
   const int chi = st.chi;
   const int j = ly.gates[g].site;
+  const bool sym = ly.tot[g].sym != 0;
+  const int q0 = charge_n(B.q), q1 = charge_np(B.q);
+  const bool selfm = sym && q0 == q1;
+  const bool mirw = sym && q0 < q1 && B.mirror >= 0;
+  const int mboff = mirw ? blk[B.mirror].boff : 0;
+  const int mq = pack_charge(q1, q0);
   const cd *A = ly.A + gb.e + B.eoff;
   const cd *V = ly.V + gb.v + B.voff;
   const double *sv = ly.sv + (size_t)g * sv_cap + B.svoff;
   const int *perm = ly.perm + (size_t)g * sv_cap + B.svoff;
   const int *rows = ly.rows + (size_t)g * rows_cap + B.roff;
   const int *cols = ly.cols + (size_t)g * rows_cap + B.coff;
+  const int *mL = ly.mirL + (size_t)g * chi;
+  const int *mR = ly.mirR + (size_t)g * chi;
   const double *lL = st.lam + (size_t)j * chi;
   const double *lR = st.lam + (size_t)(j + 2) * chi;
   cd *G1 = st.gam + (size_t)j * chi * chi;
@@ -654,24 +854,49 @@ __global__ __launch_bounds__(256) void k_scatter(State st, Layer ly, int sv_cap,
   for (int i = threadIdx.x; i < B.kq; i += blockDim.x) {
     st.lam[(size_t)(j + 1) * chi + B.boff + i] = sv[i];
     st.chg[(size_t)(j + 1) * chi + B.boff + i] = B.q;
+    if (mirw) {
+      st.lam[(size_t)(j + 1) * chi + mboff + i] = sv[i];
+      st.chg[(size_t)(j + 1) * chi + mboff + i] = mq;
+    }
   }
+  // V_Theta[ia, i] and W^H_Theta[i, ib] from the stored factors
+  auto vth = [&](int ia, int i) -> cd {
+    const int col = perm[i];
+    return !B.t ? cscale(A[(size_t)col * B.m + ia], 1.0 / sv[i])
+                : cconj(V[(size_t)col * B.n + ia]);
+  };
+  auto wth = [&](int i, int ib) -> cd {
+    const int col = perm[i];
+    return !B.t ? cconj(V[(size_t)col * B.n + ib])
+                : cscale(A[(size_t)col * B.m + ib], 1.0 / sv[i]);
+  };
   for (int idx = threadIdx.x; idx < B.kq * B.r; idx += blockDim.x) {
     const int i = idx / B.r, ia = idx % B.r;
-    const int col = perm[i];
-    cd v;
-    if (!B.t) v = cscale(A[(size_t)col * B.m + ia], 1.0 / sv[i]);
-    else v = cconj(V[(size_t)col * B.n + ia]);
     const int a = rows[ia];
+    cd v = vth(ia, i);
+    if (selfm) {   // exact J-reality: v[a~] = conj(v[a]) bitwise
+      const cd vm = vth(lower_bound(rows, B.r, mL[a]), i);
+      v = cscale(cadd(v, cconj(vm)), 0.5);
+    }
     G1[(size_t)a * chi + B.boff + i] = cscale(v, 1.0 / lL[a]);
+    if (mirw) {
+      const int am = mL[a];
+      G1[(size_t)am * chi + mboff + i] = cscale(cconj(v), 1.0 / lL[am]);
+    }
   }
   for (int idx = threadIdx.x; idx < B.kq * B.s; idx += blockDim.x) {
     const int i = idx / B.s, ib = idx % B.s;
-    const int col = perm[i];
-    cd w;
-    if (!B.t) w = cconj(V[(size_t)col * B.n + ib]);
-    else w = cscale(A[(size_t)col * B.m + ib], 1.0 / sv[i]);
     const int b = cols[ib];
+    cd w = wth(i, ib);
+    if (selfm) {
+      const cd wm = wth(i, lower_bound(cols, B.s, mR[b]));
+      w = cscale(cadd(w, cconj(wm)), 0.5);
+    }
     G2[(size_t)(B.boff + i) * chi + b] = cscale(w, 1.0 / lR[b]);
+    if (mirw) {
+      const int bm = mR[b];
+      G2[(size_t)(mboff + i) * chi + bm] = cscale(cconj(w), 1.0 / lR[bm]);
+    }
   }
 }
 

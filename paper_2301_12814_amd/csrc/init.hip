@@ -45,8 +45,9 @@ __global__ void k_init_rho(const double *r, const int *nint, double eta, int d, 
                                   (m > 0 ? m * le : 0.0) + (l > 0 ? l * l1e : 0.0));
         const double lkb = 0.5 * (lgamma(b + 1.0) - lgamma(mp + 1.0) - lgamma(l + 1.0) +
                                   (mp > 0 ? mp * le : 0.0) + (l > 0 ? l * l1e : 0.0));
-        // sign of psi[2n] is sign(tanh r)^n = + for r >= 0
-        acc += exp(lka + lkb + lpa + lpb);
+        // sign of psi[2n] is sign(tanh r)^n = + for r >= 0; the two factors are
+        // grouped so that rho[m][m'] and rho[m'][m] round identically
+        acc += exp((lka + lpa) + (lkb + lpb));
       }
     }
     rho[(size_t)j * d * d + idx] = acc;
@@ -77,7 +78,9 @@ hipError_t launch_init_norms(const double *rho, int M, int d, double *A, hipStre
 }
 
 // w_b[q0][q1] = sum_{m,m'} w_{b+1}[q0-m][q1-m'] rho_b[m][m']^2 on a W_b x W_b grid,
-// W_b = (M-b)(d-1)+1.
+// W_b = (M-b)(d-1)+1.  rho_b is symmetric, so w_b is; each canonical cell
+// q0 <= q1 is computed once and written to both mirror cells, which keeps the
+// mirror charges' Schmidt values bitwise equal.
 __global__ void k_init_conv(const double *rho, int M, int d, int b, const long long *woff,
                             double *w) {
   const int Wb = (M - b) * (d - 1) + 1;
@@ -85,6 +88,7 @@ __global__ void k_init_conv(const double *rho, int M, int d, int b, const long l
   const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= (long long)Wb * Wb) return;
   const int q0 = (int)(cell / Wb), q1 = (int)(cell % Wb);
+  if (q0 > q1) return;
   const double *wn = w + woff[b + 1];
   const double *rb = rho + (size_t)b * d * d;
   double acc = 0.0;
@@ -99,6 +103,7 @@ __global__ void k_init_conv(const double *rho, int M, int d, int b, const long l
     }
   }
   w[woff[b] + cell] = acc;
+  w[woff[b] + (long long)q1 * Wb + q0] = acc;
 }
 
 hipError_t launch_init_conv(const double *rho, int M, int d, int b, const long long *woff,

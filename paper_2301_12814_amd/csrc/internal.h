@@ -35,11 +35,12 @@ struct BlkDesc {
   int svoff;      // offset of the n singular values / permutation
   int roff, coff; // offsets of the row / column index lists
   int gate;       // gate index inside the layer
+  int comp;       // 1: contracted and SVD'd here; 0: derived from its mirror block
 };
 
 // Per-gate plan totals (device -> host).
 struct GateTot {
-  int nblk, sv, rows, cols, maxr, maxc, chunks, pad;
+  int nblk, sv, rows, cols, maxr, maxc, chunks, sym;
   long long elems, vsz;
   double svd_flops;   // sum over blocks of 16 m n^2 + 36 n^3 (complex SVD convention)
 };
@@ -73,7 +74,8 @@ struct Layer {
   int box_cap;       // largest admissible charge box per gate
   GateTot *tot;      // ngates
   GateBase *base;    // ngates
-  int *rows, *cols;  // global row / column index lists
+  int *rows, *cols;  // per-gate row / column index lists
+  int *mirL, *mirR;  // per gate: mirror index on the left / right bond, -1 if none
   cd *A;             // sector operands (overwritten by U * Sigma)
   cd *V;             // right factors
   double *sv;        // singular values, sorted descending per block
