@@ -155,6 +155,15 @@ int mpo_set_profiling(gbs_mpo *h, int enable);
  */
 int mpo_get_profile(gbs_mpo *h, double *phase_ms, long long *phase_launches, double *work);
 
+/*
+ * Sector histogram of the last applied layer (synchronises).  For each block
+ * Theta(q) of every gate, 8 ints: gate index in the layer, q = (n, n'), rows r,
+ * cols s, computed here (1) or derived from its mirror (0), Jacobi sweeps,
+ * singular vectors kept.  out: host [8 * max_blocks]; returns the total number
+ * of blocks (may exceed max_blocks; only the first max_blocks are written).
+ */
+int mpo_layer_blocks(gbs_mpo *h, int max_blocks, int *out);
+
 /* Releases every device allocation of the handle (NULL is a no-op). */
 void mpo_free(gbs_mpo *h);
 

@@ -533,3 +533,32 @@ extern "C" int mpo_get_profile(gbs_mpo *h, double *phase_ms, long long *phase_la
     for (int i = 0; i < 4; ++i) work[i] = h->work[i];
   return MPO_OK;
 }
+
+extern "C" int mpo_layer_blocks(gbs_mpo *h, int max_blocks, int *out) {
+  if (!h || max_blocks < 0 || (max_blocks > 0 && !out)) return fail(MPO_EINVAL, "bad argument");
+  int rc = sync_and_check(h);
+  if (rc != MPO_OK) return rc;
+  const Layer &ly = h->ly;
+  int total = 0;
+  std::vector<BlkDesc> tmp;
+  for (int g = 0; g < ly.ngates; ++g) {
+    const int nb = h->h_tot[g].nblk;
+    tmp.resize(nb);
+    if (nb > 0)
+      HIPCHK(hipMemcpy(tmp.data(), ly.blk + (size_t)g * ly.max_blk, sizeof(BlkDesc) * nb,
+                       hipMemcpyDeviceToHost));
+    for (int i = 0; i < nb; ++i, ++total) {
+      if (total >= max_blocks) continue;
+      int *o = out + (size_t)8 * total;
+      o[0] = g;
+      o[1] = charge_n(tmp[i].q);
+      o[2] = charge_np(tmp[i].q);
+      o[3] = tmp[i].r;
+      o[4] = tmp[i].s;
+      o[5] = tmp[i].comp;
+      o[6] = tmp[i].sweeps;
+      o[7] = tmp[i].kq;
+    }
+  }
+  return total;
+}

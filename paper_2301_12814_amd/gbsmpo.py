@@ -53,7 +53,8 @@ def lib() -> ctypes.CDLL:
         L.gbs_clements_decompose.argtypes = [c_int, pd, pi, pi, pd, pd, pd]
         L.mpo_set_profiling.argtypes = [c_void_p, c_int]
         L.mpo_get_profile.argtypes = [c_void_p, pd, pll, pd]
-        for name in ("mpo_set_profiling", "mpo_get_profile", "mpo_init_lossy_squeezed", "mpo_apply_bs_layer", "mpo_apply_phases",
+        L.mpo_layer_blocks.argtypes = [c_void_p, c_int, pi]
+        for name in ("mpo_layer_blocks", "mpo_set_profiling", "mpo_get_profile", "mpo_init_lossy_squeezed", "mpo_apply_bs_layer", "mpo_apply_phases",
                      "mpo_entropy", "mpo_photon_marginals", "mpo_sync", "mpo_get_bond",
                      "mpo_get_site", "mpo_layer_stats", "gbs_clements_decompose"):
             getattr(L, name).restype = c_int
@@ -176,6 +177,14 @@ class MPO:
 
     def sync(self):
         _check(lib().mpo_sync(self._h))
+
+    def layer_blocks(self):
+        """Sector histogram of the last layer: int array [nblocks, 8] with
+        (gate, n, n', rows, cols, computed, sweeps, kept)."""
+        n = _check(lib().mpo_layer_blocks(self._h, 0, None))
+        out = np.zeros(8 * max(n, 1), dtype=np.int32)
+        _check(lib().mpo_layer_blocks(self._h, n, _ip(out)))
+        return out[: 8 * n].reshape(n, 8)
 
     PHASES = ("fock", "plan", "contract", "svd", "select", "scatter", "entropy", "unused")
 

@@ -199,17 +199,20 @@ def test_gpu_edge_cases():
         g.apply_layer([0], [0.7], [0.3])
         lam, ch = g.bond(1)
         assert len(lam) == 1
-    # identity gate leaves bonds unchanged; phases leave EE and marginals unchanged
-    w = inputs.workload("small")
-    with gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi) as g:
-        before = [g.bond(b) for b in range(w.M + 1)]
-        S0, _ = g.entropy()
-        P0, tr0 = g.marginals()
-        g.apply_layer([0, 2, 4, 6], [0.0] * 4, [0.0] * 4)
-        for b in range(w.M + 1):
+    # identity gates leave an untruncated (exact Vidal) state unchanged
+    with gbsmpo.MPO(4, [0.7, 0.3, 0.5, 0.9], 0.6, 3, 512) as g:
+        before = [g.bond(b) for b in range(5)]
+        g.apply_layer([0, 2], [0.0] * 2, [0.0] * 2)
+        g.apply_layer([1], [0.0], [0.0])
+        for b in range(5):
             lam, ch = g.bond(b)
             assert np.array_equal(ch, before[b][1])
-            assert np.allclose(lam, before[b][0], rtol=1e-13)
+            assert np.allclose(lam, before[b][0], rtol=1e-12)
+    # phases leave EE and marginals unchanged
+    w = inputs.workload("small")
+    with gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi) as g:
+        S0, _ = g.entropy()
+        P0, tr0 = g.marginals()
         g.apply_phases(np.linspace(-2, 2, w.M))
         S1, _ = g.entropy()
         P1, tr1 = g.marginals()
