@@ -33,7 +33,9 @@ struct gbs_mpo {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int max_gates = 0;
-  long long capA = 0, capV = 0;
+  long long capA = 0;
+  int capBig = 0;
+  int *h_active = nullptr;
   GateParam *h_gates = nullptr;
   GateTot *h_tot = nullptr;
   GateBase *h_base = nullptr;
@@ -134,6 +136,7 @@ extern "C" void mpo_free(gbs_mpo *h) {
   if (h->h_tot) hipHostFree(h->h_tot);
   if (h->h_base) hipHostFree(h->h_base);
   if (h->h_err) hipHostFree(h->h_err);
+  if (h->h_active) hipHostFree(h->h_active);
   for (int i = 0; i < 2 * gbs_mpo::NPH; ++i)
     if (h->ev[i]) hipEventDestroy(h->ev[i]);
   if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
@@ -161,7 +164,7 @@ extern "C" int mpo_init_lossy_squeezed(int M, const double *r, double eta, int d
   const int max_gates = M / 2;
   const long long cap_g = (long long)d * d * chi;
   long long need = (long long)M * chi * chi * 16 + (long long)(M + 1) * chi * 12 +
-                   (long long)max_gates * (cap_g * (4 + 4 + 8 + 4 + 8 + 8 + 4) +
+                   (long long)max_gates * (cap_g * (4 + 4 + 4 + 8 + 4 + 8 + 8 + 4) +
                                            cap_g * (long long)sizeof(BlkDesc));
   long long init_need = (long long)(M + 1) * W0 * W0 * 28;
   size_t free_b = 0, total_b = 0;
@@ -216,6 +219,10 @@ extern "C" int mpo_init_lossy_squeezed(int M, const double *r, double eta, int d
   TRY(dalloc(h, &ly.blk, (size_t)max_gates * cap_g));
   TRY(dalloc(h, &ly.tot, max_gates));
   TRY(dalloc(h, &ly.base, max_gates));
+  TRY(dalloc(h, &ly.bigl, (size_t)max_gates * cap_g));
+  TRY(dalloc(h, &ly.active, 1));
+  h->capBig = 4096;
+  TRY(dalloc(h, &ly.rotf, (size_t)4 * h->capBig));
   TRY(dalloc(h, &ly.mirL, (size_t)max_gates * chi));
   TRY(dalloc(h, &ly.mirR, (size_t)max_gates * chi));
   TRY(dalloc(h, &ly.rows, (size_t)max_gates * cap_g));
@@ -226,13 +233,13 @@ extern "C" int mpo_init_lossy_squeezed(int M, const double *r, double eta, int d
   TRY(dalloc(h, &ly.ukey, (size_t)max_gates * cap_g));
   TRY(dalloc(h, &ly.usize, (size_t)max_gates * cap_g));
   h->capA = std::max<long long>(1 << 20, (long long)chi * chi * 4);
-  h->capV = h->capA;
   TRY(dalloc(h, &ly.A, (size_t)h->capA));
-  TRY(dalloc(h, &ly.V, (size_t)h->capV));
+  TRY(dalloc(h, &ly.A0, (size_t)h->capA));
   TRY(hipHostMalloc((void **)&h->h_gates, sizeof(GateParam) * std::max(max_gates, 1)));
   TRY(hipHostMalloc((void **)&h->h_tot, sizeof(GateTot) * std::max(max_gates, 1)));
   TRY(hipHostMalloc((void **)&h->h_base, sizeof(GateBase) * std::max(max_gates, 1)));
   TRY(hipHostMalloc((void **)&h->h_err, sizeof(int)));
+  TRY(hipHostMalloc((void **)&h->h_active, sizeof(int)));
   TRY(dalloc(h, &h->envL, (size_t)(M + 1) * chi));
   TRY(dalloc(h, &h->envR, (size_t)(M + 1) * chi));
   TRY(dalloc(h, &h->dP, (size_t)M * d));
@@ -325,17 +332,18 @@ extern "C" int mpo_apply_bs_layer(gbs_mpo *h, int n_gates, const int *left_site,
   rc = sync_and_check(h);
   if (rc != MPO_OK) return rc;
   // global offsets of the sector pools
-  long long e = 0, v = 0, ch = 0;
-  int blkb = 0;
+  long long e = 0, ch = 0;
+  int blkb = 0, bigb = 0, maxpp = 0;
   long long st_blk = 0, st_el = 0, st_sv = 0, st_mr = 0, st_mc = 0;
   double st_fl = 0.0;
   for (int g = 0; g < n_gates; ++g) {
     const GateTot &t = h->h_tot[g];
-    h->h_base[g] = GateBase{e, v, 0, 0, 0, blkb, ch};
+    h->h_base[g] = GateBase{e, blkb, bigb, ch};
     e += t.elems;
-    v += t.vsz;
     ch += t.chunks;
     blkb += t.nblk;
+    bigb += t.nbig;
+    maxpp = std::max(maxpp, t.maxpp);
     st_blk += t.nblk;
     st_el += t.elems;
     st_sv += t.sv;
@@ -343,43 +351,65 @@ extern "C" int mpo_apply_bs_layer(gbs_mpo *h, int n_gates, const int *left_site,
     st_mc = std::max<long long>(st_mc, t.maxc);
     st_fl += t.svd_flops;
   }
-  if (h->prof) {
-    h->work[0] += st_fl;
-    h->work[1] += (double)st_el;
-    h->work[2] += (double)st_sv;
-    h->work[3] += 1.0;
-  }
   h->stats[0] = st_blk;
   h->stats[1] = st_el;
   h->stats[2] = st_sv;
   h->stats[3] = st_mr;
   h->stats[4] = st_mc;
   h->stats[5] = -1;
+  if (h->prof) {
+    h->work[0] += st_fl;
+    h->work[1] += (double)st_el;
+    h->work[2] += (double)st_sv;
+    h->work[3] += 1.0;
+  }
   if (e > h->capA) {
     const long long cap = std::max(e, h->capA * 2);
     dfree(h, ly.A);
-    ly.A = nullptr;
-    hipError_t er = dalloc(h, &ly.A, (size_t)cap);
-    if (er != hipSuccess) return fail(MPO_ENOMEM, "sector operand pool allocation failed");
+    dfree(h, ly.A0);
+    ly.A = ly.A0 = nullptr;
+    if (dalloc(h, &ly.A, (size_t)cap) != hipSuccess || dalloc(h, &ly.A0, (size_t)cap) != hipSuccess)
+      return fail(MPO_ENOMEM, "sector operand pool allocation failed");
     h->capA = cap;
   }
-  if (v > h->capV) {
-    const long long cap = std::max(v, h->capV * 2);
-    dfree(h, ly.V);
-    ly.V = nullptr;
-    hipError_t er = dalloc(h, &ly.V, (size_t)cap);
-    if (er != hipSuccess) return fail(MPO_ENOMEM, "right-factor pool allocation failed");
-    h->capV = cap;
+  if (bigb > h->capBig) {
+    const int cap = std::max(bigb, h->capBig * 2);
+    dfree(h, ly.rotf);
+    ly.rotf = nullptr;
+    if (dalloc(h, &ly.rotf, (size_t)4 * cap) != hipSuccess)
+      return fail(MPO_ENOMEM, "flag allocation failed");
+    h->capBig = cap;
   }
   ly.total_chunks = ch;
   ly.total_blocks = blkb;
+  ly.total_big = bigb;
+  ly.maxpp = maxpp;
   HIPCHK(hipMemcpyAsync(ly.base, h->h_base, sizeof(GateBase) * n_gates, hipMemcpyHostToDevice,
                         h->stream));
   prof_mark(h, 2, 0);
   HIPCHK(launch_contract(st, ly, h->stream));
   prof_mark(h, 2, 1);
   prof_mark(h, 3, 0);
-  HIPCHK(launch_svd(st, ly, h->stream));
+  HIPCHK(launch_svd_small(st, ly, h->stream));
+  int sweeps_run = 0;
+  if (bigb > 0) {
+    // panel rounds of the big blocks; convergence is read back every 3 sweeps
+    HIPCHK(launch_svd_big_prep(st, ly, h->stream));
+    const int kMaxSweeps = 60;
+    for (int s = 0; s < kMaxSweeps; ++s) {
+      for (int r = 0; r < maxpp - 1; ++r) HIPCHK(launch_svd_panel_round(st, ly, r, s, h->stream));
+      sweeps_run = s + 1;
+      if (s % 3 == 2 || s == kMaxSweeps - 1) {
+        HIPCHK(launch_svd_count(st, ly, s, h->stream));
+        HIPCHK(hipMemcpyAsync(h->h_active, ly.active, sizeof(int), hipMemcpyDeviceToHost,
+                              h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (*h->h_active == 0) break;
+      }
+    }
+    HIPCHK(launch_svd_big_finish(st, ly, sweeps_run, h->stream));
+  }
+  h->stats[5] = sweeps_run;
   prof_mark(h, 3, 1);
   prof_mark(h, 4, 0);
   HIPCHK(launch_select(st, ly, h->stream));

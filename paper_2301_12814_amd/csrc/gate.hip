@@ -91,7 +91,19 @@ __device__ inline int count_window(const int *c, int D, int n, int lo, int hi) {
 
 constexpr int CHUNK = 256;
 
-__global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap, int sv_cap) {
+// LDS bytes of the one-workgroup Jacobi (operand + column norms) and the
+// widest panel whose pair (2 w columns of m rows) fits in LDS.
+__host__ __device__ inline size_t lds_small_need(int m, int n) {
+  return sizeof(cd) * (size_t)m * n + sizeof(double) * (size_t)n;
+}
+__host__ __device__ inline int panel_width(int m, int lds_bytes) {
+  int w = 8;
+  while (w > 1 && 2 * (size_t)w * m * sizeof(cd) > (size_t)lds_bytes) w >>= 1;
+  return w;
+}
+
+__global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap, int sv_cap,
+                                               int lds_bytes) {
   const int g = blockIdx.x;
   const int d = st.d, chi = st.chi;
   const int j = ly.gates[g].site;
@@ -225,46 +237,58 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
     B.comp = !(sym && B.mirror >= 0 && charge_n(B.q) > charge_np(B.q));
   }
   __syncthreads();
-  // pass 2: offsets
-  long long eb = 0, vb = 0;
-  int svb = 0, rb = 0, cb = 0, chb = 0, maxr = 0, maxc = 0;
+  // pass 2: offsets; each computed block goes either to the one-workgroup LDS
+  // Jacobi (operand fits in LDS) or to the multi-workgroup panel rounds
+  long long eb = 0;
+  int svb = 0, rb = 0, cb = 0, chb = 0, bgb = 0, maxr = 0, maxc = 0, maxpp = 0;
   double fl = 0.0;
+  int *bigl = ly.bigl + (size_t)g * rows_cap;
   for (int b0 = 0; b0 < nblk; b0 += blockDim.x) {
     const int bi = b0 + threadIdx.x;
-    long long e = 0, v = 0;
-    int sv = 0, r = 0, c = 0, ch = 0;
+    long long e = 0;
+    int sv = 0, r = 0, c = 0, ch = 0, bg = 0, w = 0, npan = 0;
     if (bi < nblk) {
       const BlkDesc &B = blk[bi];
       if (B.comp) {
         e = (long long)B.r * B.s;
-        v = (long long)B.n * B.n;
         sv = B.n;
         ch = (int)((e + CHUNK - 1) / CHUNK);
         fl += 16.0 * B.m * (double)B.n * B.n + 36.0 * (double)B.n * B.n * B.n;
+        if (lds_small_need(B.m, B.n) > (size_t)lds_bytes) {
+          bg = 1;
+          w = panel_width(B.m, lds_bytes);
+          npan = (B.n + w - 1) / w;
+          maxpp = max(maxpp, npan + (npan & 1));
+        }
       }
       r = B.r;
       c = B.s;
       maxr = max(maxr, B.r);
       maxc = max(maxc, B.s);
     }
-    long long te, tv;
-    int tsv, tr, tc, tch;
+    long long te;
+    int tsv, tr, tc, tch, tbg;
     const long long pe = eb + block_exclusive_scan<long long>(e, s_scan, te);
-    const long long pv = vb + block_exclusive_scan<long long>(v, s_scan, tv);
     const int psv = svb + block_exclusive_scan<int>(sv, s_iscan, tsv);
     const int pr = rb + block_exclusive_scan<int>(r, s_iscan, tr);
     const int pc = cb + block_exclusive_scan<int>(c, s_iscan, tc);
     const int pch = chb + block_exclusive_scan<int>(ch, s_iscan, tch);
+    const int pbg = bgb + block_exclusive_scan<int>(bg, s_iscan, tbg);
     if (bi < nblk) {
       BlkDesc &B = blk[bi];
       B.eoff = pe;
-      B.voff = pv;
       B.svoff = psv;
       B.roff = pr;
       B.coff = pc;
       B.uoff = pch;   // chunk offset until the select kernel reuses the field
+      B.big = bg;
+      B.w = w;
+      B.npan = npan;
+      B.bigi = bg ? pbg : -1;
+      B.sweeps = 0;
+      if (bg) bigl[pbg] = bi;
     }
-    eb += te; vb += tv; svb += tsv; rb += tr; cb += tc; chb += tch;
+    eb += te; svb += tsv; rb += tr; cb += tc; chb += tch; bgb += tbg;
   }
   __syncthreads();
   if (rb > rows_cap || cb > rows_cap || svb > sv_cap) {
@@ -290,12 +314,13 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
     }
   }
   // block-wide max of maxr / maxc, sum of the SVD work
-  __shared__ int s_mr, s_mc;
+  __shared__ int s_mr, s_mc, s_pp;
   __shared__ double s_fl;
-  if (threadIdx.x == 0) { s_mr = 0; s_mc = 0; s_fl = 0.0; }
+  if (threadIdx.x == 0) { s_mr = 0; s_mc = 0; s_pp = 0; s_fl = 0.0; }
   __syncthreads();
   atomicMax(&s_mr, maxr);
   atomicMax(&s_mc, maxc);
+  atomicMax(&s_pp, maxpp);
   atomicAdd(&s_fl, fl);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -306,8 +331,9 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
     tot.maxr = s_mr;
     tot.maxc = s_mc;
     tot.elems = eb;
-    tot.vsz = vb;
     tot.chunks = chb;
+    tot.nbig = bgb;
+    tot.maxpp = s_pp;
     tot.sym = sym;
     tot.svd_flops = s_fl;
     ly.tot[g] = tot;
@@ -316,7 +342,8 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
 
 hipError_t launch_plan(State st, Layer ly, hipStream_t s) {
   const int rows_cap = st.d * st.d * st.chi;
-  hipLaunchKernelGGL(k_plan, dim3(ly.ngates), dim3(1024), 0, s, st, ly, rows_cap, rows_cap);
+  hipLaunchKernelGGL(k_plan, dim3(ly.ngates), dim3(1024), 0, s, st, ly, rows_cap, rows_cap,
+                     svd_lds_bytes());
   return hipGetLastError();
 }
 
@@ -392,9 +419,10 @@ __global__ __launch_bounds__(CHUNK) void k_contract(State st, Layer ly, int rows
   }
   const double sc = st.lam[(size_t)j * chi + a] * st.lam[(size_t)(j + 2) * chi + b];
   acc = cscale(acc, sc);
-  cd *Aop = ly.A + gb.e + B.eoff;
-  if (!B.t) Aop[(size_t)ib * B.m + ia] = acc;          // Theta, m = r rows
-  else Aop[(size_t)ia * B.m + ib] = acc;               // Theta^T, m = s rows
+  const size_t at = !B.t ? (size_t)ib * B.m + ia       // Theta, m = r rows
+                         : (size_t)ia * B.m + ib;      // Theta^T, m = s rows
+  ly.A[gb.e + B.eoff + at] = acc;
+  ly.A0[gb.e + B.eoff + at] = acc;
 }
 
 hipError_t launch_contract(State st, Layer ly, hipStream_t s) {
@@ -406,25 +434,29 @@ hipError_t launch_contract(State st, Layer ly, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------------------
-// One-sided (Hestenes) Jacobi SVD of one block per workgroup.  Column pairs
-// follow the round-robin tournament (n/2 disjoint pairs per round, n-1 rounds
-// per sweep); each wavefront rotates one pair at a time with 64-lane
-// reductions.  For columns x, y with x^H y = |g| e^{i psi}:
+// One-sided (Hestenes) Jacobi SVD of every computed block.  For columns x, y of
+// the operand with x^H y = |g| e^{i psi}:
 //   zeta = (|y|^2 - |x|^2) / (2 |g|),  t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
 //   c = 1 / sqrt(1 + t^2), s = c t,
-//   x <- c x - s e^{-i psi} y,  y <- s x + c e^{-i psi} y,
-// and the same column operation accumulates the right factor V.  At
-// convergence A = U Sigma with orthogonal columns and A0 = U Sigma V^H.
+//   x <- c x - s e^{-i psi} y,  y <- s x + c e^{-i psi} y.
+// At convergence the operand is U Sigma with orthogonal columns.  The right
+// factor is not accumulated: the kept right singular vectors are recovered in
+// the scatter from the pristine operand, V[:, i] = A0^H u_i / sigma_i.
+// Pairs of columns whose squared norms are both below 1e-30 of the block's
+// squared Frobenius norm are left alone (their singular values lie far below
+// the 1e-14 rank cut).
+//   * k_svd_small: the whole operand in LDS, one workgroup, round-robin pairs;
+//   * big blocks: column panels of width w; each sweep is a round-robin
+//     tournament of panel pairs, one launch per round, one workgroup per panel
+//     pair holding its 2w columns in LDS (round 0 also rotates the pairs inside
+//     each panel, later rounds only the cross pairs).
 // ----------------------------------------------------------------------------
-constexpr int SVD_THREADS = 256;
-constexpr int SVD_LDS_THREADS = 512;
+constexpr int SVD_THREADS = 512;
 constexpr int MAX_SWEEPS = 60;
-constexpr int RPL = 8;        // column rows cached per lane (m <= 512)
+constexpr int RPL = 8;          // column rows cached per lane (m <= 512)
 
-// Rotation of the column pair (p, q) of A (m x n) and of the right factor V.
-__device__ __forceinline__ void jacobi_pair(cd *A, int m, cd *V, int n, int p, int q, int lane,
-                                            double tol, int &rot) {
-  cd *xp = A + (size_t)p * m, *xq = A + (size_t)q * m;
+__device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, int m, int lane, double tol,
+                                            double tiny, int &rot) {
   double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
   const bool cached = m <= 64 * RPL;
   cd rx[RPL], ry[RPL];
@@ -452,6 +484,7 @@ __device__ __forceinline__ void jacobi_pair(cd *A, int m, cd *V, int n, int p, i
   be = wave_sum(be);
   gr = wave_sum(gr);
   gi = wave_sum(gi);
+  if (al <= tiny && be <= tiny) return;
   const double ga = sqrt(gr * gr + gi * gi);
   if (!(ga > tol * sqrt(al * be)) || ga < 1e-300) return;
   const double zeta = (be - al) / (2.0 * ga);
@@ -477,75 +510,64 @@ __device__ __forceinline__ void jacobi_pair(cd *A, int m, cd *V, int n, int p, i
       xq[i] = cadd(cscale(x, s), cscale(y, c));
     }
   }
-  cd *vp = V + (size_t)p * n, *vq = V + (size_t)q * n;
-  for (int i = lane; i < n; i += 64) {
-    const cd x = vp[i];
-    const cd y = cmul(e, vq[i]);
-    vp[i] = csub(cscale(x, c), cscale(y, s));
-    vq[i] = cadd(cscale(x, s), cscale(y, c));
-  }
   rot = 1;
 }
 
-// Cyclic sweeps in round-robin order until a sweep makes no rotation.
-// Returns the number of sweeps (MAX_SWEEPS when not converged).
-__device__ __forceinline__ int jacobi_sweeps(cd *A, int m, cd *V, int n, int *s_rot) {
+__device__ __forceinline__ double jacobi_tol(int m) { return fmax(1e-15, 2.3e-16 * m); }
+
+// One round-robin pass over all pairs of the nc columns at A (column stride m).
+__device__ __forceinline__ void round_robin_pass(cd *A, int m, int nc, double tol, double tiny,
+                                                 int &rot) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
-  const int np = n + (n & 1);
-  // rotate while |x^H y| > tol |x| |y|; tol covers the rounding of an m-term dot product
-  const double tol = fmax(1e-15, 2.3e-16 * m);
-  int sweep = 0;
-  if (n <= 1) return 0;
-  for (sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
-    if (threadIdx.x == 0) *s_rot = 0;
-    __syncthreads();
-    int rot = 0;
-    for (int round = 0; round < np - 1; ++round) {
-      for (int k = wave; k < np / 2; k += nw) {
-        int p, q;
-        if (k == 0) {
-          p = round;
-          q = np - 1;
-        } else {
-          p = (round + k) % (np - 1);
-          q = (round - k + np - 1) % (np - 1);
-        }
-        if (p >= n || q >= n) continue;
-        jacobi_pair(A, m, V, n, p, q, lane, tol, rot);
+  const int np = nc + (nc & 1);
+  for (int round = 0; round < np - 1; ++round) {
+    for (int k = wave; k < np / 2; k += nw) {
+      int p, q;
+      if (k == 0) {
+        p = round;
+        q = np - 1;
+      } else {
+        p = (round + k) % (np - 1);
+        q = (round - k + np - 1) % (np - 1);
       }
-      __syncthreads();
+      if (p >= nc || q >= nc) continue;
+      jacobi_pair(A + (size_t)p * m, A + (size_t)q * m, m, lane, tol, tiny, rot);
     }
-    if (rot) *s_rot = 1;
     __syncthreads();
-    const int any = *s_rot;
-    __syncthreads();
-    if (!any) break;
   }
-  return sweep;
 }
 
-// Self-mirror block (q = (n, n)) of a Hermitian state: Theta[a~, b~] =
-// conj(Theta[a, b]) with a~ the mirror index, so every non-degenerate left
-// singular vector is J-real up to a phase, v[a~] = e^{i phi} conj(v[a]).
-// The bilinear sum s = sum_a v[a] v[a~] = e^{i phi} |v|^2 gives the phase;
-// both factors of the column are multiplied by e^{-i phi / 2}.
+__device__ __forceinline__ double block_sum(double v, double *s_red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += s_red[w];
+  __syncthreads();
+  return t;
+}
+
+// Self-mirror block (q = (n, n)) of a Hermitian state: the block obeys
+// Theta[a~, b~] = conj(Theta[a, b]) (a~ the mirror index), so each
+// non-degenerate singular vector is J-real up to a phase: u[y~] = e^{i phi}
+// conj(u[y]) on the operand's rows.  The bilinear sum s = sum_y u[y] u[y~] =
+// e^{i phi} |u|^2 gives the phase and the column is multiplied by e^{-i phi/2}.
 __device__ __forceinline__ void self_mirror_phase(const State &st, const Layer &ly, int g,
-                                                  const BlkDesc &B, cd *A, cd *V,
-                                                  int rows_cap) {
+                                                  const BlkDesc &B, cd *A, int rows_cap) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
-  const int m = B.m, n = B.n, r = B.r;
-  const int *rl = ly.rows + (size_t)g * rows_cap + B.roff;
-  const int *mL = ly.mirL + (size_t)g * st.chi;
-  cd *X = !B.t ? A : V;          // stored columns indexed by the left-bond rows
-  const int ld = !B.t ? m : n;
+  const int m = B.m, n = B.n;
+  // operand rows: left-bond indices (stored Theta) or right-bond indices (Theta^T)
+  const int *lst = !B.t ? ly.rows + (size_t)g * rows_cap + B.roff
+                        : ly.cols + (size_t)g * rows_cap + B.coff;
+  const int *my = (!B.t ? ly.mirL : ly.mirR) + (size_t)g * st.chi;
   for (int c = wave; c < n; c += nw) {
     double sr = 0.0, si = 0.0, nr = 0.0;
-    for (int ia = lane; ia < r; ia += 64) {
-      const int am = lower_bound(rl, r, mL[rl[ia]]);
-      const cd x = X[(size_t)c * ld + ia], y = X[(size_t)c * ld + am];
-      const cd p = cmul(x, y);
+    for (int y = lane; y < m; y += 64) {
+      const int ym = lower_bound(lst, m, my[lst[y]]);
+      const cd x = A[(size_t)c * m + y], z = A[(size_t)c * m + ym];
+      const cd p = cmul(x, z);
       sr += p.re;
       si += p.im;
       nr += cabs2(x);
@@ -558,7 +580,6 @@ __device__ __forceinline__ void self_mirror_phase(const State &st, const Layer &
       const double ang = -0.5 * atan2(si, sr);
       const cd f = cmk(cos(ang), sin(ang));
       for (int i = lane; i < m; i += 64) A[(size_t)c * m + i] = cmul(A[(size_t)c * m + i], f);
-      for (int i = lane; i < n; i += 64) V[(size_t)c * n + i] = cmul(V[(size_t)c * n + i], f);
     }
   }
   __syncthreads();
@@ -586,71 +607,177 @@ __device__ __forceinline__ void sort_values(const State &st, const cd *A, int m,
   }
 }
 
-__device__ inline size_t lds_need(int m, int n) {
-  return sizeof(cd) * ((size_t)m * n + (size_t)n * n) + sizeof(double) * (size_t)n;
+__device__ inline void big_block_of(const Layer &ly, int flat_big, int rows_cap, int &g,
+                                    int &bi) {
+  g = 0;
+  while (g + 1 < ly.ngates && ly.base[g + 1].big <= flat_big) ++g;
+  bi = ly.bigl[(size_t)g * rows_cap + (flat_big - ly.base[g].big)];
 }
 
-// Blocks whose operand and right factor fit in LDS: the whole Jacobi runs
-// on-chip; the factors are copied back for the scatter.
-__global__ __launch_bounds__(SVD_LDS_THREADS) void k_svd_lds(State st, Layer ly, int sv_cap,
-                                                             int rows_cap, int lds_bytes) {
+__global__ __launch_bounds__(SVD_THREADS) void k_svd_small(State st, Layer ly, int sv_cap,
+                                                           int rows_cap) {
   const int flat = blockIdx.x;
   const int g = find_gate_blk(ly.base, ly.ngates, flat);
   const GateBase gb = ly.base[g];
   BlkDesc *Bp = ly.blk + (size_t)g * ly.max_blk + (flat - gb.blk);
   const BlkDesc B = *Bp;
-  if (!B.comp || lds_need(B.m, B.n) > (size_t)lds_bytes) return;
+  if (!B.comp || B.big) return;
   const int m = B.m, n = B.n;
   extern __shared__ double s_dyn[];
   cd *sA = reinterpret_cast<cd *>(s_dyn);
-  cd *sV = sA + (size_t)m * n;
-  double *sig = reinterpret_cast<double *>(sV + (size_t)n * n);
+  double *sig = reinterpret_cast<double *>(sA + (size_t)m * n);
   __shared__ int s_rot;
+  __shared__ double s_red[16];
   cd *A = ly.A + gb.e + B.eoff;
-  cd *V = ly.V + gb.v + B.voff;
-  for (int i = threadIdx.x; i < m * n; i += blockDim.x) sA[i] = A[i];
-  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x)
-    sV[idx] = cmk((idx % n) == (idx / n) ? 1.0 : 0.0, 0.0);
-  __syncthreads();
-  const int sweep = jacobi_sweeps(sA, m, sV, n, &s_rot);
-  if (sweep == MAX_SWEEPS && threadIdx.x == 0) atomicOr(st.err, ERR_SVD_NOT_CONVERGED);
-  if (charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym)
-    self_mirror_phase(st, ly, g, B, sA, sV, rows_cap);
+  double f2 = 0.0;
+  for (int i = threadIdx.x; i < m * n; i += blockDim.x) {
+    sA[i] = A[i];
+    f2 += cabs2(sA[i]);
+  }
+  f2 = block_sum(f2, s_red);
+  const double tol = jacobi_tol(m), tiny = 1e-30 * f2;
+  int sweep = 0;
+  if (n > 1) {
+    for (sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
+      if (threadIdx.x == 0) s_rot = 0;
+      __syncthreads();
+      int rot = 0;
+      round_robin_pass(sA, m, n, tol, tiny, rot);
+      if (rot) s_rot = 1;
+      __syncthreads();
+      const int any = s_rot;
+      __syncthreads();
+      if (!any) break;
+    }
+    if (sweep == MAX_SWEEPS && threadIdx.x == 0) atomicOr(st.err, ERR_SVD_NOT_CONVERGED);
+  }
+  if (charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym) self_mirror_phase(st, ly, g, B, sA, rows_cap);
   sort_values(st, sA, m, n, sig, ly.sv + (size_t)g * sv_cap + B.svoff,
               ly.perm + (size_t)g * sv_cap + B.svoff);
   for (int i = threadIdx.x; i < m * n; i += blockDim.x) A[i] = sA[i];
-  for (int i = threadIdx.x; i < n * n; i += blockDim.x) V[i] = sV[i];
-  if (threadIdx.x == 0) Bp->sweeps = sweep;
+  if (threadIdx.x == 0) {
+    Bp->sweeps = sweep;
+    Bp->fro2 = f2;
+  }
 }
 
-// Blocks too large for LDS: operand and right factor stay in global memory.
-__global__ __launch_bounds__(SVD_THREADS) void k_svd(State st, Layer ly, int sv_cap,
-                                                      int rows_cap, int lds_bytes) {
-  const int flat = blockIdx.x;
-  const int g = find_gate_blk(ly.base, ly.ngates, flat);
-  const GateBase gb = ly.base[g];
-  BlkDesc *Bp = ly.blk + (size_t)g * ly.max_blk + (flat - gb.blk);
-  const BlkDesc B = *Bp;
-  if (!B.comp) {                 // mirror block: derived from its canonical block
-    if (threadIdx.x == 0) Bp->sweeps = 0;
+// Big blocks: squared Frobenius norm and cleared convergence flags.
+// rotf[4k + (s % 3)]: a rotation happened in sweep s; rotf[4k + 3]: converged
+// at that sweep (0 while running).
+__global__ __launch_bounds__(256) void k_big_prep(State st, Layer ly, int rows_cap) {
+  int g, bi;
+  big_block_of(ly, blockIdx.x, rows_cap, g, bi);
+  BlkDesc *Bp = ly.blk + (size_t)g * ly.max_blk + bi;
+  const cd *A = ly.A + ly.base[g].e + Bp->eoff;
+  __shared__ double s_red[16];
+  double f2 = 0.0;
+  for (long long i = threadIdx.x; i < (long long)Bp->m * Bp->n; i += blockDim.x) f2 += cabs2(A[i]);
+  f2 = block_sum(f2, s_red);
+  if (threadIdx.x == 0) {
+    Bp->fro2 = f2;
+    int *rf = ly.rotf + 4 * (size_t)blockIdx.x;
+    rf[0] = rf[1] = rf[2] = rf[3] = 0;
+  }
+}
+
+__global__ __launch_bounds__(SVD_THREADS) void k_panel(State st, Layer ly, int round, int sweep,
+                                                       int rows_cap) {
+  const int kbig = blockIdx.y;
+  int g, bi;
+  big_block_of(ly, kbig, rows_cap, g, bi);
+  const BlkDesc B = ly.blk[(size_t)g * ly.max_blk + bi];
+  const int P = B.npan, Pp = P + (P & 1);
+  if (round >= Pp - 1 || (int)blockIdx.x >= Pp / 2) return;
+  int *rf = ly.rotf + 4 * (size_t)kbig;
+  if (rf[3]) return;
+  if (sweep > 0 && rf[(sweep - 1) % 3] == 0) {   // previous sweep made no rotation
+    if (threadIdx.x == 0) rf[3] = sweep;
     return;
   }
-  if (lds_need(B.m, B.n) <= (size_t)lds_bytes) return;   // done by k_svd_lds
-  const int m = B.m, n = B.n;
-  cd *A = ly.A + gb.e + B.eoff;
-  cd *V = ly.V + gb.v + B.voff;
-  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x)
-    V[idx] = cmk((idx % n) == (idx / n) ? 1.0 : 0.0, 0.0);
-  __shared__ int s_rot;
+  if (round == 0 && blockIdx.x == 0 && threadIdx.x == 0) rf[(sweep + 1) % 3] = 0;
+  const int k = blockIdx.x;
+  int I, J;
+  if (k == 0) {
+    I = round;
+    J = Pp - 1;
+  } else {
+    I = (round + k) % (Pp - 1);
+    J = (round - k + Pp - 1) % (Pp - 1);
+  }
+  const int m = B.m, n = B.n, w = B.w;
+  const bool hasI = I < P, hasJ = J < P;
+  if (!(hasI && hasJ) && round != 0) return;     // a lone panel only rotates in round 0
+  if (!hasI && !hasJ) return;
+  const int i0 = hasI ? I * w : 0, wI = hasI ? min(w, n - I * w) : 0;
+  const int j0 = hasJ ? J * w : 0, wJ = hasJ ? min(w, n - J * w) : 0;
+  const int nc = wI + wJ;
+  extern __shared__ double s_dyn[];
+  cd *sA = reinterpret_cast<cd *>(s_dyn);
+  cd *A = ly.A + ly.base[g].e + B.eoff;
+  for (int idx = threadIdx.x; idx < nc * m; idx += blockDim.x) {
+    const int c = idx / m, i = idx % m;
+    const int col = c < wI ? i0 + c : j0 + (c - wI);
+    sA[idx] = A[(size_t)col * m + i];
+  }
   __syncthreads();
-  const int sweep = jacobi_sweeps(A, m, V, n, &s_rot);
-  if (sweep == MAX_SWEEPS && threadIdx.x == 0) atomicOr(st.err, ERR_SVD_NOT_CONVERGED);
-  if (charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym)
-    self_mirror_phase(st, ly, g, B, A, V, rows_cap);
+  const double tol = jacobi_tol(m), tiny = 1e-30 * B.fro2;
+  int rot = 0;
+  if (round == 0) {
+    round_robin_pass(sA, m, nc, tol, tiny, rot);
+  } else {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    for (int sr = 0; sr < w; ++sr) {
+      for (int t = wave; t < wI; t += nw) {
+        const int u = (t + sr) % w;
+        if (u >= wJ) continue;
+        jacobi_pair(sA + (size_t)t * m, sA + (size_t)(wI + u) * m, m, lane, tol, tiny, rot);
+      }
+      __syncthreads();
+    }
+  }
+  if (rot) rf[sweep % 3] = 1;
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nc * m; idx += blockDim.x) {
+    const int c = idx / m, i = idx % m;
+    const int col = c < wI ? i0 + c : j0 + (c - wI);
+    A[(size_t)col * m + i] = sA[idx];
+  }
+}
+
+// Big blocks still rotating in the given sweep; flags non-convergence on the last.
+__global__ void k_big_count(Layer ly, int sweep, int last, int *err) {
+  __shared__ int s_n;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  int c = 0;
+  for (int k = threadIdx.x; k < ly.total_big; k += blockDim.x) {
+    const int *rf = ly.rotf + 4 * (size_t)k;
+    if (!rf[3] && rf[sweep % 3]) ++c;
+  }
+  atomicAdd(&s_n, c);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *ly.active = s_n;
+    if (last && s_n > 0) atomicOr(err, ERR_SVD_NOT_CONVERGED);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_big_finish(State st, Layer ly, int sv_cap, int rows_cap,
+                                                   int sweeps_run) {
+  int g, bi;
+  big_block_of(ly, blockIdx.x, rows_cap, g, bi);
+  BlkDesc *Bp = ly.blk + (size_t)g * ly.max_blk + bi;
+  const BlkDesc B = *Bp;
+  cd *A = ly.A + ly.base[g].e + B.eoff;
   extern __shared__ double s_sig[];
-  sort_values(st, A, m, n, s_sig, ly.sv + (size_t)g * sv_cap + B.svoff,
+  if (charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym) self_mirror_phase(st, ly, g, B, A, rows_cap);
+  sort_values(st, A, B.m, B.n, s_sig, ly.sv + (size_t)g * sv_cap + B.svoff,
               ly.perm + (size_t)g * sv_cap + B.svoff);
-  if (threadIdx.x == 0) Bp->sweeps = sweep;
+  if (threadIdx.x == 0) {
+    const int done = ly.rotf[4 * (size_t)blockIdx.x + 3];
+    Bp->sweeps = done ? done : sweeps_run;
+  }
 }
 
 int svd_lds_bytes() {
@@ -660,24 +787,50 @@ int svd_lds_bytes() {
     hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
       v = 65536;
-    bytes = (v > 163840 ? 163840 : v) - 1024;   // room for static LDS
-    hipFuncSetAttribute((const void *)k_svd_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+    bytes = (v > 163840 ? 163840 : v) - 2048;   // room for static LDS
+    hipFuncSetAttribute((const void *)k_svd_small, hipFuncAttributeMaxDynamicSharedMemorySize,
                         bytes);
+    hipFuncSetAttribute((const void *)k_panel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   }
   return bytes;
 }
 
-hipError_t launch_svd(State st, Layer ly, hipStream_t s) {
+hipError_t launch_svd_small(State st, Layer ly, hipStream_t s) {
   if (ly.total_blocks == 0) return hipSuccess;
-  const int sv_cap = st.d * st.d * st.chi;
+  const int cap = st.d * st.d * st.chi;
   const int lb = svd_lds_bytes();
-  hipLaunchKernelGGL(k_svd_lds, dim3(ly.total_blocks), dim3(SVD_LDS_THREADS), (size_t)lb, s, st,
-                     ly, sv_cap, sv_cap, lb);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const size_t lds = sizeof(double) * (size_t)st.chi;
-  hipLaunchKernelGGL(k_svd, dim3(ly.total_blocks), dim3(SVD_THREADS), lds, s, st, ly, sv_cap,
-                     sv_cap, lb);
+  hipLaunchKernelGGL(k_svd_small, dim3(ly.total_blocks), dim3(SVD_THREADS), (size_t)lb, s, st, ly,
+                     cap, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_svd_big_prep(State st, Layer ly, hipStream_t s) {
+  if (ly.total_big == 0) return hipSuccess;
+  const int cap = st.d * st.d * st.chi;
+  hipLaunchKernelGGL(k_big_prep, dim3(ly.total_big), dim3(256), 0, s, st, ly, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_svd_panel_round(State st, Layer ly, int round, int sweep, hipStream_t s) {
+  if (ly.total_big == 0) return hipSuccess;
+  const int cap = st.d * st.d * st.chi;
+  const int lb = svd_lds_bytes();
+  hipLaunchKernelGGL(k_panel, dim3(ly.maxpp / 2, ly.total_big), dim3(SVD_THREADS), (size_t)lb, s,
+                     st, ly, round, sweep, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_svd_count(State st, Layer ly, int sweep, hipStream_t s) {
+  hipLaunchKernelGGL(k_big_count, dim3(1), dim3(256), 0, s, ly, sweep,
+                     sweep == MAX_SWEEPS - 1 ? 1 : 0, st.err);
+  return hipGetLastError();
+}
+
+hipError_t launch_svd_big_finish(State st, Layer ly, int sweeps_run, hipStream_t s) {
+  if (ly.total_big == 0) return hipSuccess;
+  const int cap = st.d * st.d * st.chi;
+  hipLaunchKernelGGL(k_big_finish, dim3(ly.total_big), dim3(256), sizeof(double) * (size_t)st.chi,
+                     s, st, ly, cap, cap, sweeps_run);
   return hipGetLastError();
 }
 
@@ -799,13 +952,18 @@ hipError_t launch_select(State st, Layer ly, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------------------
-// New tensors: zero Gamma_j, Gamma_{j+1} and the new bond, then write
-//   lam[beta] = sigma_i, c[beta] = q,
-//   Gamma_j[a, beta] = V_Theta[a, i] / lam_L[a],
-//   Gamma_{j+1}[beta, b] = W^H_Theta[i, b] / lam_R[b]
-// for the kept ranks i of every block (beta = boff + i).
-// Stored operand A = Theta: V_Theta = U, W^H = V_acc^H; A = Theta^T:
-// Theta = conj(V_acc) Sigma U^T, so V_Theta = conj(V_acc), W^H = U^T.
+// New tensors: zero Gamma_j, Gamma_{j+1} and the new bond, then for the kept
+// ranks i of every computed block (beta = boff + i, sigma_i, operand column
+// c = perm[i]):
+//   u[y]   = A[y, c] / sigma_i                       (operand rows y)
+//   v[x]   = sum_y A0[y, x] conj(A[y, c]) / sigma_i^2 (operand columns x)
+// For a stored Theta (rows = left bond, columns = right bond):
+//   Gamma_j[a, beta] = u[a] / lam_L[a],  Gamma_{j+1}[beta, b] = v[b] / lam_R[b];
+// for a stored Theta^T the roles of u and v swap.  (A0 = U Sigma V^H gives
+// V[:, i] = A0^H u_i / sigma_i; conj(V) is Theta's W^H row, resp. left vector.)
+// With Hermiticity, the derived mirror block gets the conjugates on the mirror
+// indices and a self-mirror block is made exactly J-real:
+// x[y] <- (x[y] + conj(x[y~])) / 2.
 // ----------------------------------------------------------------------------
 __global__ void k_zero(State st, Layer ly) {
   const int g = blockIdx.y;
@@ -839,18 +997,25 @@ __global__ __launch_bounds__(256) void k_scatter(State st, Layer ly, int sv_cap,
   const bool mirw = sym && q0 < q1 && B.mirror >= 0;
   const int mboff = mirw ? blk[B.mirror].boff : 0;
   const int mq = pack_charge(q1, q0);
+  const int m = B.m, n = B.n;
   const cd *A = ly.A + gb.e + B.eoff;
-  const cd *V = ly.V + gb.v + B.voff;
+  const cd *A0 = ly.A0 + gb.e + B.eoff;
   const double *sv = ly.sv + (size_t)g * sv_cap + B.svoff;
   const int *perm = ly.perm + (size_t)g * sv_cap + B.svoff;
   const int *rows = ly.rows + (size_t)g * rows_cap + B.roff;
   const int *cols = ly.cols + (size_t)g * rows_cap + B.coff;
   const int *mL = ly.mirL + (size_t)g * chi;
   const int *mR = ly.mirR + (size_t)g * chi;
-  const double *lL = st.lam + (size_t)j * chi;
-  const double *lR = st.lam + (size_t)(j + 2) * chi;
+  // operand rows y / columns x as bond indices, their mirror maps and weights
+  const int *ly_ = !B.t ? rows : cols, *lx = !B.t ? cols : rows;
+  const int *my = !B.t ? mL : mR, *mx = !B.t ? mR : mL;
+  const double *lamL = st.lam + (size_t)j * chi;
+  const double *lamR = st.lam + (size_t)(j + 2) * chi;
   cd *G1 = st.gam + (size_t)j * chi * chi;
   cd *G2 = st.gam + (size_t)(j + 1) * chi * chi;
+  extern __shared__ double s_dyn[];
+  cd *sv_x = reinterpret_cast<cd *>(s_dyn);          // v[x], n entries
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int i = threadIdx.x; i < B.kq; i += blockDim.x) {
     st.lam[(size_t)(j + 1) * chi + B.boff + i] = sv[i];
     st.chg[(size_t)(j + 1) * chi + B.boff + i] = B.q;
@@ -859,44 +1024,50 @@ __global__ __launch_bounds__(256) void k_scatter(State st, Layer ly, int sv_cap,
       st.chg[(size_t)(j + 1) * chi + mboff + i] = mq;
     }
   }
-  // V_Theta[ia, i] and W^H_Theta[i, ib] from the stored factors
-  auto vth = [&](int ia, int i) -> cd {
-    const int col = perm[i];
-    return !B.t ? cscale(A[(size_t)col * B.m + ia], 1.0 / sv[i])
-                : cconj(V[(size_t)col * B.n + ia]);
-  };
-  auto wth = [&](int i, int ib) -> cd {
-    const int col = perm[i];
-    return !B.t ? cconj(V[(size_t)col * B.n + ib])
-                : cscale(A[(size_t)col * B.m + ib], 1.0 / sv[i]);
-  };
-  for (int idx = threadIdx.x; idx < B.kq * B.r; idx += blockDim.x) {
-    const int i = idx / B.r, ia = idx % B.r;
-    const int a = rows[ia];
-    cd v = vth(ia, i);
-    if (selfm) {   // exact J-reality: v[a~] = conj(v[a]) bitwise
-      const cd vm = vth(lower_bound(rows, B.r, mL[a]), i);
-      v = cscale(cadd(v, cconj(vm)), 0.5);
+  for (int i = 0; i < B.kq; ++i) {
+    const int c = perm[i];
+    const double s1 = 1.0 / sv[i], s2 = s1 * s1;
+    const cd *Ac = A + (size_t)c * m;
+    for (int x = wave; x < n; x += nw) {
+      const cd *A0x = A0 + (size_t)x * m;
+      double re = 0.0, im = 0.0;
+      for (int y = lane; y < m; y += 64) {
+        const cd p = cmulc(Ac[y], A0x[y]);     // A0[y, x] conj(A[y, c])
+        re += p.re;
+        im += p.im;
+      }
+      re = wave_sum(re);
+      im = wave_sum(im);
+      if (lane == 0) sv_x[x] = cmk(re * s2, im * s2);
     }
-    G1[(size_t)a * chi + B.boff + i] = cscale(v, 1.0 / lL[a]);
-    if (mirw) {
-      const int am = mL[a];
-      G1[(size_t)am * chi + mboff + i] = cscale(cconj(v), 1.0 / lL[am]);
+    __syncthreads();
+    // operand-row side
+    for (int y = threadIdx.x; y < m; y += blockDim.x) {
+      cd u = cscale(Ac[y], s1);
+      const int idx = ly_[y];
+      if (selfm) u = cscale(cadd(u, cconj(cscale(Ac[lower_bound(ly_, m, my[idx])], s1))), 0.5);
+      if (!B.t) {
+        G1[(size_t)idx * chi + B.boff + i] = cscale(u, 1.0 / lamL[idx]);
+        if (mirw) G1[(size_t)my[idx] * chi + mboff + i] = cscale(cconj(u), 1.0 / lamL[my[idx]]);
+      } else {
+        G2[(size_t)(B.boff + i) * chi + idx] = cscale(u, 1.0 / lamR[idx]);
+        if (mirw) G2[(size_t)(mboff + i) * chi + my[idx]] = cscale(cconj(u), 1.0 / lamR[my[idx]]);
+      }
     }
-  }
-  for (int idx = threadIdx.x; idx < B.kq * B.s; idx += blockDim.x) {
-    const int i = idx / B.s, ib = idx % B.s;
-    const int b = cols[ib];
-    cd w = wth(i, ib);
-    if (selfm) {
-      const cd wm = wth(i, lower_bound(cols, B.s, mR[b]));
-      w = cscale(cadd(w, cconj(wm)), 0.5);
+    // operand-column side
+    for (int x = threadIdx.x; x < n; x += blockDim.x) {
+      cd v = sv_x[x];
+      const int idx = lx[x];
+      if (selfm) v = cscale(cadd(v, cconj(sv_x[lower_bound(lx, n, mx[idx])])), 0.5);
+      if (!B.t) {
+        G2[(size_t)(B.boff + i) * chi + idx] = cscale(v, 1.0 / lamR[idx]);
+        if (mirw) G2[(size_t)(mboff + i) * chi + mx[idx]] = cscale(cconj(v), 1.0 / lamR[mx[idx]]);
+      } else {
+        G1[(size_t)idx * chi + B.boff + i] = cscale(v, 1.0 / lamL[idx]);
+        if (mirw) G1[(size_t)mx[idx] * chi + mboff + i] = cscale(cconj(v), 1.0 / lamL[mx[idx]]);
+      }
     }
-    G2[(size_t)(B.boff + i) * chi + b] = cscale(w, 1.0 / lR[b]);
-    if (mirw) {
-      const int bm = mR[b];
-      G2[(size_t)(mboff + i) * chi + bm] = cscale(cconj(w), 1.0 / lR[bm]);
-    }
+    __syncthreads();
   }
 }
 
@@ -905,7 +1076,8 @@ hipError_t launch_scatter(State st, Layer ly, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ly.total_blocks == 0) return e;
   const int sv_cap = st.d * st.d * st.chi;
-  hipLaunchKernelGGL(k_scatter, dim3(ly.total_blocks), dim3(256), 0, s, st, ly, sv_cap, sv_cap);
+  hipLaunchKernelGGL(k_scatter, dim3(ly.total_blocks), dim3(256), sizeof(cd) * (size_t)st.chi, s,
+                     st, ly, sv_cap, sv_cap);
   return hipGetLastError();
 }
 

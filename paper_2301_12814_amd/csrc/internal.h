@@ -29,9 +29,11 @@ struct BlkDesc {
   int kq;         // singular vectors kept
   int boff;       // first new-bond index of this block
   int uoff;       // first unit (selection) index owned by this block
-  long long eoff; // operand offset: local to the gate after planning,
-                  // global after the host fix-up
-  long long voff; // offset of the n x n right factor
+  long long eoff; // operand offset (local to the gate) in the A and A0 pools
+  double fro2;    // squared Frobenius norm of the operand
+  int big;        // 1: SVD by multi-workgroup panel rounds, 0: one workgroup in LDS
+  int w, npan;    // panel width and panel count of a big block
+  int bigi;       // index of a big block in its gate's big-block list
   int svoff;      // offset of the n singular values / permutation
   int roff, coff; // offsets of the row / column index lists
   int gate;       // gate index inside the layer
@@ -41,14 +43,16 @@ struct BlkDesc {
 // Per-gate plan totals (device -> host).
 struct GateTot {
   int nblk, sv, rows, cols, maxr, maxc, chunks, sym;
-  long long elems, vsz;
+  int nbig, maxpp;    // big blocks, largest even panel count among them
+  long long elems;
   double svd_flops;   // sum over blocks of 16 m n^2 + 36 n^3 (complex SVD convention)
 };
 
 // Per-gate global offsets (host -> device).
 struct GateBase {
-  long long e, v;
-  int sv, rows, cols, blk;
+  long long e;        // first operand element of the gate in the A / A0 pools
+  int blk;            // first block (flat over the layer)
+  int big;            // first big block (flat over the layer)
   long long echunk;   // first 256-element chunk of the gate
 };
 
@@ -77,7 +81,12 @@ struct Layer {
   int *rows, *cols;  // per-gate row / column index lists
   int *mirL, *mirR;  // per gate: mirror index on the left / right bond, -1 if none
   cd *A;             // sector operands (overwritten by U * Sigma)
-  cd *V;             // right factors
+  cd *A0;            // pristine copies of the operands (right-vector recovery)
+  int *bigl;         // per gate: local indices of its big blocks
+  int *rotf;         // per big block: rotation flags of the two latest sweeps
+  int *active;       // big blocks still rotating after the latest checked sweep
+  int total_big;     // big blocks in the layer
+  int maxpp;         // largest even panel count in the layer
   double *sv;        // singular values, sorted descending per block
   int *perm;         // rank -> operand column
   unsigned long long *uval;   // selection units: value bits
@@ -105,7 +114,12 @@ hipError_t launch_fock(Layer ly, int d, hipStream_t s);
 hipError_t launch_plan(State st, Layer ly, hipStream_t s);
 hipError_t launch_lists(State st, Layer ly, hipStream_t s);
 hipError_t launch_contract(State st, Layer ly, hipStream_t s);
-hipError_t launch_svd(State st, Layer ly, hipStream_t s);
+hipError_t launch_svd_small(State st, Layer ly, hipStream_t s);
+hipError_t launch_svd_big_prep(State st, Layer ly, hipStream_t s);
+hipError_t launch_svd_panel_round(State st, Layer ly, int round, int sweep, hipStream_t s);
+hipError_t launch_svd_count(State st, Layer ly, int sweep, hipStream_t s);
+hipError_t launch_svd_big_finish(State st, Layer ly, int sweeps_run, hipStream_t s);
+int svd_lds_bytes();
 hipError_t launch_select(State st, Layer ly, hipStream_t s);
 hipError_t launch_scatter(State st, Layer ly, hipStream_t s);
 hipError_t launch_entropy_layer(State st, Layer ly, hipStream_t s);
