@@ -76,6 +76,118 @@ def cpu_baseline(budget_s: float = 25.0):
                        "extrapolated to chi=1024")}
 
 
+def _percentiles(xs):
+    import numpy as np
+    xs = np.asarray(xs, dtype=float)
+    return float(np.percentile(xs, 50)), float(np.percentile(xs, 99))
+
+
+def run_batch(args, prec):
+    """Batched instances: every simulation of the batch-instance law admitted
+    at once, each engine step applies the next layer of all of them."""
+    from paper_2301_12814_amd import gbsmpo, inputs
+    ws = inputs.batch_workloads(args.batch)
+    Us = [inputs.haar_unitary(w.M, w.seed) for w in ws]
+    n_gates = sum(w.M * (w.M - 1) // 2 for w in ws)
+    with gbsmpo.Engine(precision=prec) as eng:
+        eng.set_profiling(True)
+        t0 = time.perf_counter()
+        ids = [eng.add(w.M, w.r, w.eta, w.d, w.chi, U) for w, U in zip(ws, Us)]
+        t_adm = time.perf_counter() - t0
+        print(f"admitted {len(ids)} simulations in {t_adm:.2f} s", file=sys.stderr, flush=True)
+        done_at = {}
+        step = 0
+        while len(done_at) < len(ids):
+            n_act = eng.step()
+            step += 1
+            now = time.perf_counter() - t0
+            for sid in ids:
+                if sid not in done_at and eng.result(sid) is not None:
+                    done_at[sid] = now
+            if step % 8 == 0:
+                print(f"step {step}: {n_act} running, {len(done_at)} done, {now:.1f} s",
+                      file=sys.stderr, flush=True)
+        elapsed = time.perf_counter() - t0
+        ms, n, work = eng.profile()
+        res = [eng.result(s) for s in ids]
+    p50, p99 = _percentiles(list(done_at.values()))
+    return {
+        "metric": "batched simulations/s (256 instances of the batch law)",
+        "value": len(ids) / elapsed, "unit": "simulations/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": elapsed * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == gbsmpo.MPO_FP64 else "mixed",
+        "data": "synthetic (seeded Haar interferometers, batch law)",
+        "config": {"workload": f"batch of {len(ids)}: M~U{{16..48}}, r~U[0.3,1.2], "
+                               f"eta~U[0.2,0.8], d~U{{6,8,10}}, chi~U{{64,...,512}}, seeds 1000+i; "
+                               f"{n_gates} beam splitters"},
+        "gate_updates_per_s": n_gates / elapsed,
+        "completion_s": {"p50": p50, "p99": p99},
+        "engine_steps": step,
+        "phase_ms": ms,
+        "max_S": max(r["S_max"] for r in res),
+    }
+
+
+def run_serve(args, prec):
+    """Continuous batching: Poisson arrivals, admission by projected device
+    bytes, every step applies the next layer of every running simulation."""
+    from paper_2301_12814_amd import gbsmpo, inputs
+    reqs = inputs.serving_requests(args.requests, args.rate)
+    Us = [inputs.haar_unitary(w.M, w.seed) for _, w in reqs]
+    lat, queue_wait = [], []
+    waiting = []                       # indices admitted to the queue, not yet on the device
+    running = {}                       # sid -> request index
+    nxt = 0
+    with gbsmpo.Engine(precision=prec) as eng:
+        t0 = time.perf_counter()
+        admitted_at = {}
+        while nxt < len(reqs) or waiting or running:
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and reqs[nxt][0] <= now:
+                waiting.append(nxt)
+                nxt += 1
+            while waiting:
+                k = waiting[0]
+                w = reqs[k][1]
+                try:
+                    sid = eng.add(w.M, w.r, w.eta, w.d, w.chi, Us[k])
+                except gbsmpo.GbsMpoError as e:
+                    if e.code == gbsmpo.MPO_ENOMEM and running:
+                        break                  # wait for memory to free up
+                    raise
+                waiting.pop(0)
+                running[sid] = k
+                admitted_at[k] = time.perf_counter() - t0
+            if not running:
+                if nxt < len(reqs):            # idle until the next arrival
+                    time.sleep(max(0.0, reqs[nxt][0] - (time.perf_counter() - t0)))
+                continue
+            eng.step()
+            now = time.perf_counter() - t0
+            for sid in list(running):
+                r = eng.result(sid)
+                if r is not None:
+                    k = running.pop(sid)
+                    lat.append(now - reqs[k][0])
+                    queue_wait.append(admitted_at[k] - reqs[k][0])
+                    eng.release(sid)
+                    if len(lat) % 10 == 0:
+                        print(f"{len(lat)} done at {now:.1f} s, {len(running)} running, "
+                              f"{len(waiting)} waiting", file=sys.stderr, flush=True)
+        elapsed = time.perf_counter() - t0
+    p50, p99 = _percentiles(lat)
+    return {
+        "metric": "served simulations/s with p50/p99 latency (continuous batching)",
+        "value": len(lat) / elapsed, "unit": "simulations/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": elapsed * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == gbsmpo.MPO_FP64 else "mixed",
+        "data": "synthetic (Poisson arrivals seed 5, batch law + 5% M=96 d=10 chi=1024)",
+        "config": {"workload": f"{len(reqs)} requests at {args.rate} req/s"},
+        "latency_s": {"p50": p50, "p99": p99, "max": max(lat)},
+        "queue_wait_s": {"p50": _percentiles(queue_wait)[0], "p99": _percentiles(queue_wait)[1]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +197,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--layers", type=int, default=0, help="limit layers per step (debug)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=256, help="instances (workload batch)")
+    ap.add_argument("--requests", type=int, default=200, help="requests (workload serve)")
+    ap.add_argument("--rate", type=float, default=1.0, help="arrivals/s (workload serve)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU (no multi-GPU path); "
@@ -96,13 +211,17 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
 
+    prec = gbsmpo.MPO_FP64 if args.precision == "fp64" else gbsmpo.MPO_MIXED
+    if args.workload in ("batch", "serve"):
+        out = run_batch(args, prec) if args.workload == "batch" else run_serve(args, prec)
+        print(json.dumps(out), flush=True)
+        return
     w = inputs.workload(args.workload)
     U = inputs.haar_unitary(w.M, w.seed)
     layers, _ = gbsmpo.clements(U)
     if args.layers:
         layers = layers[: args.layers]
     n_gates = sum(len(l[0]) for l in layers)
-    prec = gbsmpo.MPO_FP64 if args.precision == "fp64" else gbsmpo.MPO_MIXED
 
     def evolve(g):
         for (S, T, P) in layers:

@@ -167,6 +167,61 @@ int mpo_layer_blocks(gbs_mpo *h, int max_blocks, int *out);
 /* Releases every device allocation of the handle (NULL is a no-op). */
 void mpo_free(gbs_mpo *h);
 
+/*
+ * ---------------------------------------------------------------------------
+ * Batched and continuously batched simulations.
+ *
+ * An engine holds any number of simulations resident in HBM.  Every step
+ * applies the next beam-splitter layer of every running simulation in one
+ * batched launch sequence: the sector contractions, block SVDs, truncations
+ * and scatters of all their gates run in the same kernels (App. D, the
+ * two-site update of each gate is independent of every other gate of the
+ * layer).  Simulations may be added at any step (continuous batching); a
+ * simulation whose last layer was applied is retired: its operator EE maximum,
+ * trace and photon marginals are stored and its device memory released.
+ * A simulation's results do not depend on which other simulations share its
+ * steps.  An engine is not thread-safe.
+ * ---------------------------------------------------------------------------
+ */
+typedef struct gbs_engine gbs_engine;
+
+/* Projected device bytes a simulation of this shape is admitted against
+ * (its state plus its share of the per-layer sector workspace); -1 on bad
+ * arguments. */
+long long mpo_engine_projected_bytes(int M, int d, int chi);
+
+/* New engine on hip_stream (NULL: own stream).  budget_bytes = admission
+ * budget in bytes, 0 for 85% of the currently free HBM. */
+int mpo_engine_create(void *hip_stream, int precision, long long budget_bytes, gbs_engine **out);
+
+/* Admits one simulation: arguments as mpo_init_lossy_squeezed plus the
+ * interferometer U (host [2*M*M], row-major, interleaved re/im), decomposed on
+ * the host into Clements layers.  Returns MPO_ENOMEM (state unchanged) when
+ * the projected bytes do not fit the remaining budget.  *id receives the
+ * simulation id. */
+int mpo_engine_add(gbs_engine *e, int M, const double *r, double eta, int d, int chi,
+                   const double *U_reim, int *id);
+
+/* One step: the next layer of every running simulation; finished ones are
+ * retired.  *n_active (nullable) receives the number still running. */
+int mpo_engine_step(gbs_engine *e, int *n_active);
+
+/* Results of simulation id: *done = 1 once retired, then S_max (EE maximum over
+ * bonds and layers, bits), trace (Tr rho) and P [M*d] (nullable each). */
+int mpo_engine_result(gbs_engine *e, int id, int *done, double *S_max, double *trace,
+                      double *P);
+
+/* Forgets a retired simulation (MPO_EBUSY while it runs). */
+int mpo_engine_release(gbs_engine *e, int id);
+
+/* Phase profiling of the engine's steps (same layout as mpo_get_profile). */
+int mpo_engine_set_profiling(gbs_engine *e, int enable);
+int mpo_engine_get_profile(gbs_engine *e, double *phase_ms, long long *phase_launches,
+                           double *work);
+
+/* Releases the engine and every simulation it holds. */
+void mpo_engine_free(gbs_engine *e);
+
 /* Thread-local message of the last failing call on this thread. */
 const char *mpo_last_error(void);
 

@@ -1,4 +1,6 @@
-// C ABI of libgbsmpo: handle, validation, device memory, layer orchestration.
+// C ABI of libgbsmpo: validation, device memory, and the engine that applies
+// one layer of beam splitters to one or many simulations in one batched
+// launch sequence.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,54 +25,35 @@ static int fail(int code, const std::string &msg) {
   do {                                                                                \
     hipError_t e_ = (x);                                                              \
     if (e_ != hipSuccess)                                                             \
-      return fail(MPO_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));       \
+      return fail(e_ == hipErrorOutOfMemory ? MPO_ENOMEM : MPO_EDEVICE,               \
+                  std::string(#x) + ": " + hipGetErrorString(e_));                    \
   } while (0)
-
-struct gbs_mpo {
-  State st{};
-  Layer ly{};
-  int precision = MPO_FP64;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  int max_gates = 0;
-  long long capA = 0;
-  int capBig = 0;
-  int *h_active = nullptr;
-  GateParam *h_gates = nullptr;
-  GateTot *h_tot = nullptr;
-  GateBase *h_base = nullptr;
-  int *h_err = nullptr;
-  cd *envL = nullptr, *envR = nullptr;
-  double *dP = nullptr, *dTrace = nullptr, *dPhase = nullptr;
-  long long stats[6] = {0, 0, 0, 0, 0, -1};
-  int latched = 0;
-  // profiling: HIP events around each phase of a layer, read at the next sync
-  static constexpr int NPH = 8;
-  bool prof = false;
-  bool prof_pending = false;
-  hipEvent_t ev[2 * NPH] = {};
-  double ph_ms[NPH] = {};
-  long long ph_n[NPH] = {};
-  double work[4] = {};      // svd flops, sector elements, candidates, layers
-  std::vector<void *> allocs;
-};
 
 namespace {
 
+// Growable device buffer.
 template <typename T>
-hipError_t dalloc(gbs_mpo *h, T **p, size_t count) {
-  *p = nullptr;
-  if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void **)p, sizeof(T) * count);
-  if (e == hipSuccess) h->allocs.push_back((void *)*p);
-  return e;
-}
-
-void dfree(gbs_mpo *h, void *p) {
-  if (!p) return;
-  hipFree(p);
-  h->allocs.erase(std::remove(h->allocs.begin(), h->allocs.end(), p), h->allocs.end());
-}
+struct DBuf {
+  T *p = nullptr;
+  size_t cap = 0;
+  // Grows to at least n (by half again, capped at `limit` when that is >= n).
+  hipError_t ensure(size_t n, size_t limit = ~(size_t)0) {
+    if (n <= cap && p) return hipSuccess;
+    size_t nc = std::max<size_t>(n, cap * 3 / 2 + 1);
+    if (limit >= n) nc = std::min(nc, limit);
+    if (p) hipFree(p);
+    p = nullptr;
+    cap = 0;
+    hipError_t e = hipMalloc((void **)&p, sizeof(T) * std::max<size_t>(nc, 1));
+    if (e == hipSuccess) cap = nc;
+    return e;
+  }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
 
 // Internal Fock dimension of the squeezed vacuum: smallest even size whose
 // neglected tail |psi_{2n}|^2 is below 1e-20 and that covers the cutoff d.
@@ -84,69 +67,240 @@ int internal_levels(double r, int d) {
   }
 }
 
-int check_latched(gbs_mpo *h) {
-  if (h->latched) {
-    const int e = h->latched;
-    std::string msg = "device error latched:";
-    if (e & ERR_SVD_NOT_CONVERGED) msg += " Jacobi SVD did not converge;";
-    if (e & ERR_NONFINITE) msg += " non-finite value;";
-    if (e & ERR_BOX_OVERFLOW) msg += " charge box exceeds workspace;";
-    if (e & ERR_TIE_OVERFLOW) msg += " too many tied singular values;";
-    if (e & ERR_WORKSPACE) msg += " sector workspace overflow;";
-    return fail(MPO_ENUMERIC, msg);
-  }
-  return MPO_OK;
-}
-
-// Read the elapsed times of the previous layer's phase events (its work has
-// completed once the stream was synchronised).
-void prof_collect(gbs_mpo *h) {
-  if (!h->prof || !h->prof_pending) return;
-  for (int p = 0; p < gbs_mpo::NPH; ++p) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, h->ev[2 * p], h->ev[2 * p + 1]) == hipSuccess) {
-      h->ph_ms[p] += ms;
-      h->ph_n[p] += 1;
-    }
-  }
-  h->prof_pending = false;
-}
-
-void prof_mark(gbs_mpo *h, int phase, int edge) {
-  if (h->prof) hipEventRecord(h->ev[2 * phase + edge], h->stream);
-}
-
-int sync_and_check(gbs_mpo *h) {
-  HIPCHK(hipMemcpyAsync(h->h_err, h->st.err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  h->latched |= *h->h_err;
-  prof_collect(h);
-  return check_latched(h);
+std::string err_text(int e) {
+  std::string msg = "device error latched:";
+  if (e & ERR_SVD_NOT_CONVERGED) msg += " Jacobi SVD did not converge;";
+  if (e & ERR_NONFINITE) msg += " non-finite value;";
+  if (e & ERR_BOX_OVERFLOW) msg += " charge box too large;";
+  if (e & ERR_TIE_OVERFLOW) msg += " too many tied singular values;";
+  if (e & ERR_WORKSPACE) msg += " sector workspace overflow;";
+  return msg;
 }
 
 }  // namespace
 
-extern "C" const char *mpo_last_error(void) { return g_err.c_str(); }
+// One simulation resident on the device.
+struct Instance {
+  int id = -1;
+  bool live = false;
+  State st{};                      // device pointers; st.err points into the engine's table
+  std::vector<void *> allocs;
+  cd *envL = nullptr, *envR = nullptr;
+  double *dP = nullptr, *dTrace = nullptr, *dPhase = nullptr, *dPart = nullptr;
+  // schedule of beam-splitter layers (engine mode)
+  std::vector<int> lptr, site;
+  std::vector<double> theta, phi;
+  int next_layer = 0;
+  bool done = false;
+  long long bytes = 0;
+  // results of a retired simulation
+  double smax = 0.0, trace = 0.0;
+  std::vector<double> P;
+  int status = MPO_OK;
+  std::string msg;                 // error text of a failed simulation
+};
 
-extern "C" void mpo_free(gbs_mpo *h) {
-  if (!h) return;
-  if (h->stream) hipStreamSynchronize(h->stream);
-  for (void *p : h->allocs) hipFree(p);
-  if (h->h_gates) hipHostFree(h->h_gates);
-  if (h->h_tot) hipHostFree(h->h_tot);
-  if (h->h_base) hipHostFree(h->h_base);
-  if (h->h_err) hipHostFree(h->h_err);
-  if (h->h_active) hipHostFree(h->h_active);
-  for (int i = 0; i < 2 * gbs_mpo::NPH; ++i)
-    if (h->ev[i]) hipEventDestroy(h->ev[i]);
-  if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
-  delete h;
+struct Engine {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int precision = MPO_FP64;
+  long long budget = 0;            // admission budget (bytes)
+  long long committed = 0;         // projected bytes of live simulations
+  std::vector<Instance> inst;      // slots
+  int next_id = 0;
+  // state table
+  DBuf<State> d_states;
+  int *d_errs = nullptr;           // one error word per slot
+  size_t errs_cap = 0;
+  int *h_errs = nullptr;
+  bool states_dirty = true;
+  // gate-level workspace
+  DBuf<GateParam> d_gates;
+  DBuf<GateTot> d_tot;
+  DBuf<GateBase> d_base;
+  DBuf<cd> d_fock;
+  DBuf<int> d_mirL, d_mirR;
+  GateParam *h_gates = nullptr;
+  GateTot *h_tot = nullptr;
+  GateBase *h_base = nullptr;
+  size_t h_cap = 0;
+  // chunk-level workspace
+  DBuf<BlkDesc> d_blk;
+  DBuf<int> d_rows, d_cols, d_bigl, d_perm, d_usize;
+  DBuf<double> d_sv;
+  DBuf<unsigned long long> d_uval, d_ukey;
+  DBuf<cd> d_A, d_A0;
+  DBuf<int> d_rotf;
+  DBuf<int> d_active;
+  DBuf<int> d_eng_err;
+  int *h_small = nullptr;          // pinned: [0] active count, [1] engine error word
+  long long pool_budget = 0;       // sector operand elements per chunk
+  // profiling
+  static constexpr int NPH = 8;
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  size_t ev_next = 0;
+  double ph_ms[NPH] = {};
+  long long ph_n[NPH] = {};
+  double work[4] = {};
+  long long stats[6] = {0, 0, 0, 0, 0, -1};
+  std::vector<BlkDesc> last_blk;   // sector histogram of the last layer (single chunk)
+  std::vector<int> last_blk_gate;
+};
+
+struct gbs_mpo {
+  Engine eng;
+  int slot = 0;
+};
+
+struct gbs_engine {
+  Engine eng;
+};
+
+namespace {
+
+// ------------------------------------------------------------------ profiling
+hipEvent_t next_event(Engine &E) {
+  if (E.ev_next == E.ev_pool.size()) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    E.ev_pool.push_back(ev);
+  }
+  return E.ev_pool[E.ev_next++];
 }
 
-extern "C" int mpo_init_lossy_squeezed(int M, const double *r, double eta, int d, int chi,
-                                       int precision, void *hip_stream, gbs_mpo **out) {
-  if (!out) return fail(MPO_EINVAL, "out is NULL");
-  *out = nullptr;
+// HIP events around one phase on the engine's stream; read at the next sync.
+struct PhaseMark {
+  Engine &E;
+  int ph;
+  hipEvent_t a = nullptr;
+  PhaseMark(Engine &e, int p) : E(e), ph(p) {
+    if (E.prof) {
+      a = next_event(E);
+      if (a) hipEventRecord(a, E.stream);
+    }
+  }
+  ~PhaseMark() {
+    if (E.prof && a) {
+      hipEvent_t b = next_event(E);
+      if (b) {
+        hipEventRecord(b, E.stream);
+        E.pending.push_back({ph, {a, b}});
+      }
+    }
+  }
+};
+
+void prof_collect(Engine &E) {
+  for (auto &pe : E.pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
+      E.ph_ms[pe.first] += ms;
+      E.ph_n[pe.first] += 1;
+    }
+  }
+  E.pending.clear();
+  E.ev_next = 0;
+}
+
+// ------------------------------------------------------------------ errors
+// Synchronises the stream and reads every slot's error word into h_errs.  With
+// check_instances, a latched error of any live simulation is returned.
+int sync_and_check(Engine &E, bool check_instances = true) {
+  const int n = (int)E.inst.size();
+  HIPCHK(hipStreamSynchronize(E.stream));
+  if (n > 0) HIPCHK(hipMemcpy(E.h_errs, E.d_errs, sizeof(int) * n, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(E.h_small + 1, E.d_eng_err.p, sizeof(int), hipMemcpyDeviceToHost));
+  prof_collect(E);
+  int any = E.h_small[1];
+  if (check_instances)
+    for (int i = 0; i < n; ++i)
+      if (E.inst[i].live) any |= E.h_errs[i];
+  if (any) return fail(MPO_ENUMERIC, err_text(any));
+  return MPO_OK;
+}
+
+// ------------------------------------------------------------------ engine setup
+int engine_init(Engine &E, void *hip_stream, int precision, long long budget) {
+  E.precision = precision;
+  if (hip_stream) {
+    E.stream = (hipStream_t)hip_stream;
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&E.stream, hipStreamNonBlocking));
+    E.own_stream = true;
+  }
+  size_t fb = 0, tb = 0;
+  HIPCHK(hipMemGetInfo(&fb, &tb));
+  E.budget = budget > 0 ? budget : (long long)(0.85 * (double)fb);
+  // sector operand pools per chunk (A and A0): at most a quarter of the budget each
+  E.pool_budget = std::max<long long>(1LL << 22, E.budget / 4 / (long long)sizeof(cd));
+  HIPCHK(hipHostMalloc((void **)&E.h_small, sizeof(int) * 4));
+  HIPCHK(E.d_active.ensure(1));
+  HIPCHK(E.d_eng_err.ensure(1));
+  HIPCHK(hipMemsetAsync(E.d_eng_err.p, 0, sizeof(int), E.stream));
+  HIPCHK(hipStreamSynchronize(E.stream));
+  return MPO_OK;
+}
+
+void engine_destroy(Engine &E) {
+  if (E.stream) hipStreamSynchronize(E.stream);
+  for (auto &I : E.inst)
+    for (void *p : I.allocs) hipFree(p);
+  E.d_states.release();
+  if (E.d_errs) hipFree(E.d_errs);
+  E.d_gates.release();
+  E.d_tot.release();
+  E.d_base.release();
+  E.d_fock.release();
+  E.d_mirL.release();
+  E.d_mirR.release();
+  E.d_blk.release();
+  E.d_rows.release();
+  E.d_cols.release();
+  E.d_bigl.release();
+  E.d_perm.release();
+  E.d_usize.release();
+  E.d_sv.release();
+  E.d_uval.release();
+  E.d_ukey.release();
+  E.d_A.release();
+  E.d_A0.release();
+  E.d_rotf.release();
+  E.d_active.release();
+  E.d_eng_err.release();
+  if (E.h_errs) hipHostFree(E.h_errs);
+  if (E.h_gates) hipHostFree(E.h_gates);
+  if (E.h_tot) hipHostFree(E.h_tot);
+  if (E.h_base) hipHostFree(E.h_base);
+  if (E.h_small) hipHostFree(E.h_small);
+  for (hipEvent_t ev : E.ev_pool) hipEventDestroy(ev);
+  if (E.own_stream && E.stream) hipStreamDestroy(E.stream);
+}
+
+template <typename T>
+hipError_t ialloc(Instance &I, T **p, size_t count) {
+  *p = nullptr;
+  hipError_t e = hipMalloc((void **)p, sizeof(T) * std::max<size_t>(count, 1));
+  if (e == hipSuccess) I.allocs.push_back((void *)*p);
+  return e;
+}
+
+// Projected device bytes of one simulation: the state, its readout scratch,
+// and the larger of the one-off initial-state scratch and its share of the
+// per-layer sector workspace (operand + pristine copy, about 2.5 chi^2
+// elements per gate, plus the per-gate lists).
+long long projected_bytes(int M, int d, int chi) {
+  const long long W0 = (long long)M * (d - 1) + 1;
+  const long long state = (long long)M * chi * chi * 16 + (long long)(M + 1) * chi * 60 +
+                          (long long)M * d * ((chi + 3) / 4) * 8;
+  const long long init = (long long)(M + 1) * W0 * W0 * 28;
+  const long long layer = (long long)(M / 2) * (long long)(2.5 * chi * chi) * 32 +
+                          (long long)(M / 2) * d * d * chi * 48;
+  return state + std::max(init, layer);
+}
+
+int validate_args(int M, const double *r, double eta, int d, int chi, int precision) {
   if (M < 2 || M > 4096) return fail(MPO_EINVAL, "M must be in [2, 4096]");
   if (!r) return fail(MPO_EINVAL, "r is NULL");
   for (int j = 0; j < M; ++j)
@@ -158,192 +312,230 @@ extern "C" int mpo_init_lossy_squeezed(int M, const double *r, double eta, int d
   if (precision != MPO_FP64 && precision != MPO_MIXED)
     return fail(MPO_EINVAL, "precision must be MPO_FP64 or MPO_MIXED");
   if ((long long)M * (d - 1) + 1 > 32767) return fail(MPO_EINVAL, "charges exceed 15 bits");
+  return MPO_OK;
+}
 
-  // projected footprint: state + per-layer workspace (sector pools start small)
-  const long long W0 = (long long)M * (d - 1) + 1;
-  const int max_gates = M / 2;
-  const long long cap_g = (long long)d * d * chi;
-  long long need = (long long)M * chi * chi * 16 + (long long)(M + 1) * chi * 12 +
-                   (long long)max_gates * (cap_g * (4 + 4 + 4 + 8 + 4 + 8 + 8 + 4) +
-                                           cap_g * (long long)sizeof(BlkDesc));
-  long long init_need = (long long)(M + 1) * W0 * W0 * 28;
-  size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess)
-    return fail(MPO_EDEVICE, "hipMemGetInfo failed");
-  if ((double)(need + init_need) > 0.9 * (double)free_b)
-    return fail(MPO_ENOMEM, "projected device memory exceeds the free HBM");
+int upload_states(Engine &E) {
+  if (!E.states_dirty) return MPO_OK;
+  const int n = (int)E.inst.size();
+  std::vector<State> tab(std::max(n, 1));
+  for (int i = 0; i < n; ++i) tab[i] = E.inst[i].st;
+  HIPCHK(E.d_states.ensure(std::max(n, 1)));
+  HIPCHK(hipMemcpyAsync(E.d_states.p, tab.data(), sizeof(State) * std::max(n, 1),
+                        hipMemcpyHostToDevice, E.stream));
+  HIPCHK(hipStreamSynchronize(E.stream));
+  E.states_dirty = false;
+  return MPO_OK;
+}
 
-  gbs_mpo *h = new gbs_mpo();
-  h->precision = precision;
-  h->max_gates = max_gates;
-  int rc = MPO_OK;
-  auto bail = [&](int code) {
-    mpo_free(h);
-    return code;
-  };
-#define TRY(x)                                                                        \
-  do {                                                                                \
-    hipError_t e_ = (x);                                                              \
-    if (e_ != hipSuccess) {                                                           \
-      rc = fail(e_ == hipErrorOutOfMemory ? MPO_ENOMEM : MPO_EDEVICE,                 \
-                std::string(#x) + ": " + hipGetErrorString(e_));                      \
-      return bail(rc);                                                                \
-    }                                                                                 \
-  } while (0)
-  if (hip_stream) {
-    h->stream = (hipStream_t)hip_stream;
-  } else {
-    TRY(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
-    h->own_stream = true;
+// A free slot for a new simulation (the error-word table grows by copy).
+int engine_reserve_slot(Engine &E) {
+  for (size_t i = 0; i < E.inst.size(); ++i)
+    if (!E.inst[i].live && E.inst[i].id < 0) return (int)i;
+  const size_t n = E.inst.size() + 1;
+  if (E.errs_cap < n) {
+    const size_t nc = std::max<size_t>(n * 2, 16);
+    int *np = nullptr;
+    if (hipMalloc((void **)&np, sizeof(int) * nc) != hipSuccess) return -1;
+    if (hipMemsetAsync(np, 0, sizeof(int) * nc, E.stream) != hipSuccess) return -1;
+    if (E.d_errs)
+      hipMemcpyAsync(np, E.d_errs, sizeof(int) * E.errs_cap, hipMemcpyDeviceToDevice, E.stream);
+    hipStreamSynchronize(E.stream);
+    if (E.d_errs) hipFree(E.d_errs);
+    E.d_errs = np;
+    E.errs_cap = nc;
+    for (size_t s = 0; s < E.inst.size(); ++s)
+      if (E.inst[s].live) E.inst[s].st.err = np + s;
+    if (E.h_errs) hipHostFree(E.h_errs);
+    E.h_errs = nullptr;
+    if (hipHostMalloc((void **)&E.h_errs, sizeof(int) * nc) != hipSuccess) return -1;
+    E.states_dirty = true;
   }
-  State &st = h->st;
+  E.inst.resize(n);
+  return (int)n - 1;
+}
+
+// Allocates and builds the initial state of a new simulation in `slot`.
+int instance_create(Engine &E, int slot, int M, const double *r, double eta, int d, int chi) {
+  Instance &I = E.inst[slot];
+  I = Instance();
+  I.live = true;
+  State &st = I.st;
   st.M = M;
   st.d = d;
   st.chi = chi;
-  TRY(dalloc(h, &st.gam, (size_t)M * chi * chi));
-  TRY(dalloc(h, &st.lam, (size_t)(M + 1) * chi));
-  TRY(dalloc(h, &st.chg, (size_t)(M + 1) * chi));
-  TRY(dalloc(h, &st.dim, (size_t)(M + 1)));
-  TRY(dalloc(h, &st.ee, (size_t)(M + 1)));
-  TRY(dalloc(h, &st.ee_max, 1));
-  TRY(dalloc(h, &st.err, 1));
-  TRY(hipMemsetAsync(st.ee, 0, sizeof(double) * (M + 1), h->stream));
-  TRY(hipMemsetAsync(st.ee_max, 0, sizeof(unsigned long long), h->stream));
-  TRY(hipMemsetAsync(st.err, 0, sizeof(int), h->stream));
-
-  Layer &ly = h->ly;
-  ly.max_blk = (int)cap_g;
-  ly.box_cap = (int)std::min<long long>(W0 * W0, 1LL << 30);
-  TRY(dalloc(h, &ly.gates, max_gates));
-  TRY(dalloc(h, &ly.fock, (size_t)max_gates * (2 * d - 1) * d * d));
-  TRY(dalloc(h, &ly.blk, (size_t)max_gates * cap_g));
-  TRY(dalloc(h, &ly.tot, max_gates));
-  TRY(dalloc(h, &ly.base, max_gates));
-  TRY(dalloc(h, &ly.bigl, (size_t)max_gates * cap_g));
-  TRY(dalloc(h, &ly.active, 1));
-  h->capBig = 4096;
-  TRY(dalloc(h, &ly.rotf, (size_t)4 * h->capBig));
-  TRY(dalloc(h, &ly.mirL, (size_t)max_gates * chi));
-  TRY(dalloc(h, &ly.mirR, (size_t)max_gates * chi));
-  TRY(dalloc(h, &ly.rows, (size_t)max_gates * cap_g));
-  TRY(dalloc(h, &ly.cols, (size_t)max_gates * cap_g));
-  TRY(dalloc(h, &ly.sv, (size_t)max_gates * cap_g));
-  TRY(dalloc(h, &ly.perm, (size_t)max_gates * cap_g));
-  TRY(dalloc(h, &ly.uval, (size_t)max_gates * cap_g));
-  TRY(dalloc(h, &ly.ukey, (size_t)max_gates * cap_g));
-  TRY(dalloc(h, &ly.usize, (size_t)max_gates * cap_g));
-  h->capA = std::max<long long>(1 << 20, (long long)chi * chi * 4);
-  TRY(dalloc(h, &ly.A, (size_t)h->capA));
-  TRY(dalloc(h, &ly.A0, (size_t)h->capA));
-  TRY(hipHostMalloc((void **)&h->h_gates, sizeof(GateParam) * std::max(max_gates, 1)));
-  TRY(hipHostMalloc((void **)&h->h_tot, sizeof(GateTot) * std::max(max_gates, 1)));
-  TRY(hipHostMalloc((void **)&h->h_base, sizeof(GateBase) * std::max(max_gates, 1)));
-  TRY(hipHostMalloc((void **)&h->h_err, sizeof(int)));
-  TRY(hipHostMalloc((void **)&h->h_active, sizeof(int)));
-  TRY(dalloc(h, &h->envL, (size_t)(M + 1) * chi));
-  TRY(dalloc(h, &h->envR, (size_t)(M + 1) * chi));
-  TRY(dalloc(h, &h->dP, (size_t)M * d));
-  TRY(dalloc(h, &h->dTrace, 1));
-  TRY(dalloc(h, &h->dPhase, (size_t)M));
-
-  // ---- initial state ----
+  HIPCHK(ialloc(I, &st.gam, (size_t)M * chi * chi));
+  HIPCHK(ialloc(I, &st.lam, (size_t)(M + 1) * chi));
+  HIPCHK(ialloc(I, &st.chg, (size_t)(M + 1) * chi));
+  HIPCHK(ialloc(I, &st.dim, (size_t)(M + 1)));
+  HIPCHK(ialloc(I, &st.ee, (size_t)(M + 1)));
+  HIPCHK(ialloc(I, &st.ee_max, 1));
+  HIPCHK(ialloc(I, &I.envL, (size_t)(M + 1) * chi));
+  HIPCHK(ialloc(I, &I.envR, (size_t)(M + 1) * chi));
+  HIPCHK(ialloc(I, &I.dP, (size_t)M * d));
+  HIPCHK(ialloc(I, &I.dTrace, 1));
+  HIPCHK(ialloc(I, &I.dPhase, (size_t)M));
+  HIPCHK(ialloc(I, &I.dPart, marginals_scratch(M, d, chi)));
+  st.err = E.d_errs + slot;
+  HIPCHK(hipMemsetAsync(st.ee, 0, sizeof(double) * (M + 1), E.stream));
+  HIPCHK(hipMemsetAsync(st.ee_max, 0, sizeof(unsigned long long), E.stream));
+  HIPCHK(hipMemsetAsync(st.err, 0, sizeof(int), E.stream));
+  // initial state
   std::vector<int> nint(M);
   for (int j = 0; j < M; ++j) nint[j] = internal_levels(r[j], d);
   std::vector<long long> woff(M + 2, 0);
-  // lay the grids out from bond M upwards
-  {
-    long long acc = 0;
-    for (int b = M; b >= 0; --b) {
-      const long long Wb = (long long)(M - b) * (d - 1) + 1;
-      woff[b] = acc;
-      acc += Wb * Wb;
-    }
-    woff[M + 1] = acc;
+  long long acc = 0;
+  for (int b = M; b >= 0; --b) {
+    const long long Wb = (long long)(M - b) * (d - 1) + 1;
+    woff[b] = acc;
+    acc += Wb * Wb;
   }
+  woff[M + 1] = acc;
+  const long long W0 = (long long)M * (d - 1) + 1;
+  const long long ucap = W0 * W0;
   double *d_r = nullptr, *d_rho = nullptr, *d_A = nullptr, *d_w = nullptr;
-  int *d_nint = nullptr;
+  int *d_nint = nullptr, *d_us = nullptr;
   long long *d_woff = nullptr;
   unsigned long long *d_uv = nullptr, *d_uk = nullptr;
-  int *d_us = nullptr;
-  const long long ucap = W0 * W0;
-  TRY(dalloc(h, &d_r, M));
-  TRY(dalloc(h, &d_nint, M));
-  TRY(dalloc(h, &d_rho, (size_t)M * d * d));
-  TRY(dalloc(h, &d_A, M + 1));
-  TRY(dalloc(h, &d_w, (size_t)woff[M + 1]));
-  TRY(dalloc(h, &d_woff, M + 2));
-  TRY(dalloc(h, &d_uv, (size_t)ucap * (M + 1)));
-  TRY(dalloc(h, &d_uk, (size_t)ucap * (M + 1)));
-  TRY(dalloc(h, &d_us, (size_t)ucap * (M + 1)));
-  TRY(hipMemcpyAsync(d_r, r, sizeof(double) * M, hipMemcpyHostToDevice, h->stream));
-  TRY(hipMemcpyAsync(d_nint, nint.data(), sizeof(int) * M, hipMemcpyHostToDevice, h->stream));
-  TRY(hipMemcpyAsync(d_woff, woff.data(), sizeof(long long) * (M + 2), hipMemcpyHostToDevice,
-                     h->stream));
+  std::vector<void *> tmp;
+  auto cleanup = [&]() {
+    hipStreamSynchronize(E.stream);
+    for (void *p : tmp) hipFree(p);
+    tmp.clear();
+  };
+  hipError_t e = hipSuccess;
+#define TALLOC(p, count)                                                              \
+  if (e == hipSuccess) {                                                              \
+    e = hipMalloc((void **)&p, sizeof(*p) * std::max<size_t>((size_t)(count), 1));    \
+    if (e == hipSuccess) tmp.push_back((void *)p);                                    \
+  }
+  TALLOC(d_r, M);
+  TALLOC(d_nint, M);
+  TALLOC(d_rho, (size_t)M * d * d);
+  TALLOC(d_A, M + 1);
+  TALLOC(d_w, acc);
+  TALLOC(d_woff, M + 2);
+  TALLOC(d_uv, (size_t)ucap * (M + 1));
+  TALLOC(d_uk, (size_t)ucap * (M + 1));
+  TALLOC(d_us, (size_t)ucap * (M + 1));
+#undef TALLOC
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(e == hipErrorOutOfMemory ? MPO_ENOMEM : MPO_EDEVICE,
+                std::string("initial-state scratch: ") + hipGetErrorString(e));
+  }
   const double one = 1.0;
-  TRY(hipMemcpyAsync(d_w + woff[M], &one, sizeof(double), hipMemcpyHostToDevice, h->stream));
-  TRY(launch_init_rho(d_r, d_nint, eta, M, d, d_rho, h->stream));
-  TRY(launch_init_norms(d_rho, M, d, d_A, h->stream));
-  for (int b = M - 1; b >= 0; --b) TRY(launch_init_conv(d_rho, M, d, b, d_woff, d_w, h->stream));
-  TRY(launch_init_select(st, d_w, d_woff, d_A, d_uv, d_uk, d_us, ucap, h->stream));
-  TRY(launch_init_gamma(st, d_rho, d_A, h->stream));
-  TRY(launch_entropy_all(st, h->stream));
-  TRY(hipStreamSynchronize(h->stream));
-  for (void *p : std::vector<void *>{d_r, d_nint, d_rho, d_A, d_w, d_woff, d_uv, d_uk, d_us})
-    dfree(h, p);
-  rc = sync_and_check(h);
-  if (rc != MPO_OK) return bail(rc);
-  *out = h;
+  if (e == hipSuccess) e = hipMemcpyAsync(d_r, r, sizeof(double) * M, hipMemcpyHostToDevice, E.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_nint, nint.data(), sizeof(int) * M, hipMemcpyHostToDevice, E.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_woff, woff.data(), sizeof(long long) * (M + 2), hipMemcpyHostToDevice,
+                       E.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_w + woff[M], &one, sizeof(double), hipMemcpyHostToDevice, E.stream);
+  if (e == hipSuccess) e = launch_init_rho(d_r, d_nint, eta, M, d, d_rho, E.stream);
+  if (e == hipSuccess) e = launch_init_norms(d_rho, M, d, d_A, E.stream);
+  for (int b = M - 1; b >= 0 && e == hipSuccess; --b)
+    e = launch_init_conv(d_rho, M, d, b, d_woff, d_w, E.stream);
+  if (e == hipSuccess) e = launch_init_select(st, d_w, d_woff, d_A, d_uv, d_uk, d_us, ucap, E.stream);
+  if (e == hipSuccess) e = launch_init_gamma(st, d_rho, d_A, E.stream);
+  if (e == hipSuccess) e = launch_entropy_all(st, E.stream);
+  cleanup();
+  if (e != hipSuccess) return fail(MPO_EDEVICE, hipGetErrorString(e));
+  I.bytes = projected_bytes(M, d, chi);
+  E.states_dirty = true;
   return MPO_OK;
-#undef TRY
 }
 
-extern "C" int mpo_apply_bs_layer(gbs_mpo *h, int n_gates, const int *left_site,
-                                  const double *theta, const double *phi) {
-  if (!h) return fail(MPO_EINVAL, "handle is NULL");
-  int rc = check_latched(h);
+// Frees a simulation's device memory (its results stay in the slot).
+void instance_release(Engine &E, int slot) {
+  Instance &I = E.inst[slot];
+  hipStreamSynchronize(E.stream);
+  for (void *p : I.allocs) hipFree(p);
+  I.allocs.clear();
+  if (I.live) E.committed -= I.bytes;
+  I.live = false;
+  I.bytes = 0;
+  E.states_dirty = true;
+}
+
+// ------------------------------------------------------------------ one batched layer
+int ensure_host(Engine &E, size_t n) {
+  if (n <= E.h_cap) return MPO_OK;
+  const size_t nc = std::max(n, E.h_cap * 2 + 16);
+  if (E.h_gates) hipHostFree(E.h_gates);
+  if (E.h_tot) hipHostFree(E.h_tot);
+  if (E.h_base) hipHostFree(E.h_base);
+  E.h_gates = nullptr;
+  E.h_tot = nullptr;
+  E.h_base = nullptr;
+  HIPCHK(hipHostMalloc((void **)&E.h_gates, sizeof(GateParam) * nc));
+  HIPCHK(hipHostMalloc((void **)&E.h_tot, sizeof(GateTot) * nc));
+  HIPCHK(hipHostMalloc((void **)&E.h_base, sizeof(GateBase) * nc));
+  E.h_cap = nc;
+  return MPO_OK;
+}
+
+// Applies one batched layer: the gates (disjoint inside each simulation) of
+// any number of simulations.  Fock tables and the count pass run for all
+// gates at once; the rest runs in chunks of consecutive gates whose sector
+// operands fit the pool budget.  With check_instances, an error latched by
+// any live simulation fails the call; otherwise per-simulation errors are
+// left to the caller (the engine retires the failing simulations only).
+int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_instances) {
+  const int n = (int)gates.size();
+  if (n == 0) return MPO_OK;
+  int rc = upload_states(E);
   if (rc != MPO_OK) return rc;
-  const int M = h->st.M;
-  if (n_gates < 0 || n_gates > h->max_gates) return fail(MPO_EINVAL, "n_gates out of range");
-  if (n_gates == 0) return MPO_OK;
-  if (!left_site || !theta || !phi) return fail(MPO_EINVAL, "NULL gate array");
-  std::vector<char> used(M, 0);
-  for (int g = 0; g < n_gates; ++g) {
-    const int k = left_site[g];
-    if (k < 0 || k > M - 2) return fail(MPO_EINVAL, "left_site out of range");
-    if (used[k] || used[k + 1]) return fail(MPO_EINVAL, "gates of a layer must be disjoint");
-    if (!std::isfinite(theta[g]) || !std::isfinite(phi[g]))
-      return fail(MPO_EINVAL, "non-finite gate angle");
-    used[k] = used[k + 1] = 1;
+  rc = ensure_host(E, n);
+  if (rc != MPO_OK) return rc;
+  long long fk = 0, mr = 0;
+  int max_chi = 1;
+  for (int g = 0; g < n; ++g) {
+    GateParam gp = gates[g];
+    const State &st = E.inst[gp.inst].st;
+    gp.fock0 = fk;
+    gp.mir0 = mr;
+    gp.blk0 = 0;
+    gp.lst0 = 0;
+    fk += (long long)(2 * st.d - 1) * st.d * st.d;
+    mr += st.chi;
+    max_chi = std::max(max_chi, st.chi);
+    E.h_gates[g] = gp;
   }
-  State &st = h->st;
-  Layer &ly = h->ly;
-  for (int g = 0; g < n_gates; ++g) h->h_gates[g] = GateParam{left_site[g], 0, theta[g], phi[g]};
-  ly.ngates = n_gates;
-  HIPCHK(hipMemcpyAsync(ly.gates, h->h_gates, sizeof(GateParam) * n_gates,
-                        hipMemcpyHostToDevice, h->stream));
-  prof_mark(h, 0, 0);
-  HIPCHK(launch_fock(ly, st.d, h->stream));
-  prof_mark(h, 0, 1);
-  prof_mark(h, 1, 0);
-  HIPCHK(launch_plan(st, ly, h->stream));
-  prof_mark(h, 1, 1);
-  HIPCHK(hipMemcpyAsync(h->h_tot, ly.tot, sizeof(GateTot) * n_gates, hipMemcpyDeviceToHost,
-                        h->stream));
-  rc = sync_and_check(h);
+  HIPCHK(E.d_gates.ensure(n));
+  HIPCHK(E.d_tot.ensure(n));
+  HIPCHK(E.d_base.ensure(n));
+  HIPCHK(E.d_fock.ensure(fk));
+  HIPCHK(E.d_mirL.ensure(mr));
+  HIPCHK(E.d_mirR.ensure(mr));
+  HIPCHK(hipMemcpyAsync(E.d_gates.p, E.h_gates, sizeof(GateParam) * n, hipMemcpyHostToDevice,
+                        E.stream));
+  Layer L{};
+  L.states = E.d_states.p;
+  L.fock = E.d_fock.p;
+  L.mirL = E.d_mirL.p;
+  L.mirR = E.d_mirR.p;
+  L.ngates = n;
+  L.gates = E.d_gates.p;
+  L.tot = E.d_tot.p;
+  L.base = E.d_base.p;
+  {
+    PhaseMark pm(E, 0);
+    HIPCHK(launch_fock(L, E.stream));
+  }
+  {
+    PhaseMark pm(E, 1);
+    HIPCHK(launch_plan_count(L, E.stream));
+  }
+  HIPCHK(hipMemcpyAsync(E.h_tot, E.d_tot.p, sizeof(GateTot) * n, hipMemcpyDeviceToHost,
+                        E.stream));
+  rc = sync_and_check(E, check_instances);
   if (rc != MPO_OK) return rc;
-  // global offsets of the sector pools
-  long long e = 0, ch = 0;
-  int blkb = 0, bigb = 0, maxpp = 0;
-  long long st_blk = 0, st_el = 0, st_sv = 0, st_mr = 0, st_mc = 0;
+  long long st_blk = 0, st_el = 0, st_sv = 0, st_mr = 0, st_mc = 0, st_sw = 0;
   double st_fl = 0.0;
-  for (int g = 0; g < n_gates; ++g) {
-    const GateTot &t = h->h_tot[g];
-    h->h_base[g] = GateBase{e, blkb, bigb, ch};
-    e += t.elems;
-    ch += t.chunks;
-    blkb += t.nblk;
-    bigb += t.nbig;
-    maxpp = std::max(maxpp, t.maxpp);
+  for (int g = 0; g < n; ++g) {
+    const GateTot &t = E.h_tot[g];
     st_blk += t.nblk;
     st_el += t.elems;
     st_sv += t.sv;
@@ -351,244 +543,558 @@ extern "C" int mpo_apply_bs_layer(gbs_mpo *h, int n_gates, const int *left_site,
     st_mc = std::max<long long>(st_mc, t.maxc);
     st_fl += t.svd_flops;
   }
-  h->stats[0] = st_blk;
-  h->stats[1] = st_el;
-  h->stats[2] = st_sv;
-  h->stats[3] = st_mr;
-  h->stats[4] = st_mc;
-  h->stats[5] = -1;
-  if (h->prof) {
-    h->work[0] += st_fl;
-    h->work[1] += (double)st_el;
-    h->work[2] += (double)st_sv;
-    h->work[3] += 1.0;
+  if (E.prof) {
+    E.work[0] += st_fl;
+    E.work[1] += (double)st_el;
+    E.work[2] += (double)st_sv;
+    E.work[3] += 1.0;
   }
-  if (e > h->capA) {
-    const long long cap = std::max(e, h->capA * 2);
-    dfree(h, ly.A);
-    dfree(h, ly.A0);
-    ly.A = ly.A0 = nullptr;
-    if (dalloc(h, &ly.A, (size_t)cap) != hipSuccess || dalloc(h, &ly.A0, (size_t)cap) != hipSuccess)
-      return fail(MPO_ENOMEM, "sector operand pool allocation failed");
-    h->capA = cap;
-  }
-  if (bigb > h->capBig) {
-    const int cap = std::max(bigb, h->capBig * 2);
-    dfree(h, ly.rotf);
-    ly.rotf = nullptr;
-    if (dalloc(h, &ly.rotf, (size_t)4 * cap) != hipSuccess)
-      return fail(MPO_ENOMEM, "flag allocation failed");
-    h->capBig = cap;
-  }
-  ly.total_chunks = ch;
-  ly.total_blocks = blkb;
-  ly.total_big = bigb;
-  ly.maxpp = maxpp;
-  HIPCHK(hipMemcpyAsync(ly.base, h->h_base, sizeof(GateBase) * n_gates, hipMemcpyHostToDevice,
-                        h->stream));
-  prof_mark(h, 2, 0);
-  HIPCHK(launch_contract(st, ly, h->stream));
-  prof_mark(h, 2, 1);
-  prof_mark(h, 3, 0);
-  HIPCHK(launch_svd_small(st, ly, h->stream));
-  int sweeps_run = 0;
-  if (bigb > 0) {
-    // panel rounds of the big blocks; convergence is read back every 3 sweeps
-    HIPCHK(launch_svd_big_prep(st, ly, h->stream));
-    const int kMaxSweeps = 60;
-    for (int s = 0; s < kMaxSweeps; ++s) {
-      for (int r = 0; r < maxpp - 1; ++r) HIPCHK(launch_svd_panel_round(st, ly, r, s, h->stream));
-      sweeps_run = s + 1;
-      if (s % 3 == 2 || s == kMaxSweeps - 1) {
-        HIPCHK(launch_svd_count(st, ly, s, h->stream));
-        HIPCHK(hipMemcpyAsync(h->h_active, ly.active, sizeof(int), hipMemcpyDeviceToHost,
-                              h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-        if (*h->h_active == 0) break;
+  E.last_blk.clear();
+  E.last_blk_gate.clear();
+  int c0 = 0;
+  while (c0 < n) {
+    int c1 = c0;
+    long long el = 0;
+    while (c1 < n && (c1 == c0 || el + E.h_tot[c1].elems <= E.pool_budget)) {
+      el += E.h_tot[c1].elems;
+      ++c1;
+    }
+    const int ng = c1 - c0;
+    long long e = 0, ch = 0, blk0 = 0, lst0 = 0;
+    int blkb = 0, bigb = 0, maxpp = 0;
+    for (int g = c0; g < c1; ++g) {
+      const GateTot &t = E.h_tot[g];
+      GateParam &gp = E.h_gates[g];
+      gp.blk0 = blk0;
+      gp.lst0 = lst0;
+      blk0 += std::max(t.nblk, 1);
+      lst0 += std::max(std::max(t.rows, t.cols), std::max(t.sv, 1));
+      E.h_base[g - c0] = GateBase{e, blkb, bigb, ch};
+      e += t.elems;
+      ch += t.chunks;
+      blkb += t.nblk;
+      bigb += t.nbig;
+      maxpp = std::max(maxpp, t.maxpp);
+    }
+    HIPCHK(E.d_blk.ensure(blk0));
+    HIPCHK(E.d_rows.ensure(lst0));
+    HIPCHK(E.d_cols.ensure(lst0));
+    HIPCHK(E.d_bigl.ensure(lst0));
+    HIPCHK(E.d_perm.ensure(lst0));
+    HIPCHK(E.d_usize.ensure(lst0));
+    HIPCHK(E.d_sv.ensure(lst0));
+    HIPCHK(E.d_uval.ensure(lst0));
+    HIPCHK(E.d_ukey.ensure(lst0));
+    HIPCHK(E.d_A.ensure(std::max(e, 1LL), (size_t)E.pool_budget));
+    HIPCHK(E.d_A0.ensure(std::max(e, 1LL), (size_t)E.pool_budget));
+    HIPCHK(E.d_rotf.ensure((size_t)4 * std::max(bigb, 1)));
+    if (bigb > 65535 || maxpp / 2 > 65535)
+      return fail(MPO_EINVAL, "too many large sectors in one layer chunk");
+    HIPCHK(hipMemcpyAsync(E.d_gates.p + c0, E.h_gates + c0, sizeof(GateParam) * ng,
+                          hipMemcpyHostToDevice, E.stream));
+    HIPCHK(hipMemcpyAsync(E.d_base.p, E.h_base, sizeof(GateBase) * ng, hipMemcpyHostToDevice,
+                          E.stream));
+    Layer C = L;
+    C.ngates = ng;
+    C.gates = E.d_gates.p + c0;
+    C.tot = E.d_tot.p + c0;
+    C.base = E.d_base.p;
+    C.blk = E.d_blk.p;
+    C.rows = E.d_rows.p;
+    C.cols = E.d_cols.p;
+    C.bigl = E.d_bigl.p;
+    C.perm = E.d_perm.p;
+    C.usize = E.d_usize.p;
+    C.sv = E.d_sv.p;
+    C.uval = E.d_uval.p;
+    C.ukey = E.d_ukey.p;
+    C.A = E.d_A.p;
+    C.A0 = E.d_A0.p;
+    C.rotf = E.d_rotf.p;
+    C.active = E.d_active.p;
+    C.total_chunks = ch;
+    C.total_blocks = blkb;
+    C.total_big = bigb;
+    C.maxpp = maxpp;
+    {
+      PhaseMark pm(E, 1);
+      HIPCHK(launch_plan_fill(C, E.stream));
+    }
+    {
+      PhaseMark pm(E, 2);
+      HIPCHK(launch_contract(C, E.stream));
+    }
+    int sweeps_run = 0;
+    {
+      PhaseMark pm(E, 3);
+      HIPCHK(launch_svd_small(C, E.stream));
+      if (bigb > 0) {
+        // panel rounds of the big blocks; convergence is read back every 3 sweeps
+        HIPCHK(launch_svd_big_prep(C, E.stream));
+        const int kMaxSweeps = 60;
+        for (int s = 0; s < kMaxSweeps; ++s) {
+          for (int r = 0; r < maxpp - 1; ++r) HIPCHK(launch_svd_panel_round(C, r, s, E.stream));
+          sweeps_run = s + 1;
+          if (s % 3 == 2 || s == kMaxSweeps - 1) {
+            HIPCHK(launch_svd_count(C, s, E.stream));
+            HIPCHK(hipMemcpyAsync(E.h_small, E.d_active.p, sizeof(int), hipMemcpyDeviceToHost,
+                                  E.stream));
+            HIPCHK(hipStreamSynchronize(E.stream));
+            if (E.h_small[0] == 0) break;
+          }
+        }
+        HIPCHK(launch_svd_big_finish(C, sweeps_run, max_chi, E.stream));
       }
     }
-    HIPCHK(launch_svd_big_finish(st, ly, sweeps_run, h->stream));
+    st_sw = std::max<long long>(st_sw, sweeps_run);
+    {
+      PhaseMark pm(E, 4);
+      HIPCHK(launch_select(C, E.stream));
+    }
+    {
+      PhaseMark pm(E, 5);
+      HIPCHK(launch_scatter(C, max_chi, E.stream));
+    }
+    {
+      PhaseMark pm(E, 6);
+      HIPCHK(launch_entropy_layer(C, E.stream));
+    }
+    if (c0 == 0 && c1 == n) {
+      // keep the sector histogram of a single-chunk layer
+      std::vector<BlkDesc> tmp((size_t)blk0);
+      HIPCHK(hipMemcpyAsync(tmp.data(), E.d_blk.p, sizeof(BlkDesc) * blk0, hipMemcpyDeviceToHost,
+                            E.stream));
+      HIPCHK(hipStreamSynchronize(E.stream));
+      for (int g = 0; g < n; ++g)
+        for (int b = 0; b < E.h_tot[g].nblk; ++b) {
+          E.last_blk.push_back(tmp[E.h_gates[g].blk0 + b]);
+          E.last_blk_gate.push_back(g);
+        }
+    }
+    c0 = c1;
   }
-  h->stats[5] = sweeps_run;
-  prof_mark(h, 3, 1);
-  prof_mark(h, 4, 0);
-  HIPCHK(launch_select(st, ly, h->stream));
-  prof_mark(h, 4, 1);
-  prof_mark(h, 5, 0);
-  HIPCHK(launch_scatter(st, ly, h->stream));
-  prof_mark(h, 5, 1);
-  prof_mark(h, 6, 0);
-  HIPCHK(launch_entropy_layer(st, ly, h->stream));
-  prof_mark(h, 6, 1);
-  prof_mark(h, 7, 0);
-  prof_mark(h, 7, 1);
-  if (h->prof) h->prof_pending = true;
+  E.stats[0] = st_blk;
+  E.stats[1] = st_el;
+  E.stats[2] = st_sv;
+  E.stats[3] = st_mr;
+  E.stats[4] = st_mc;
+  E.stats[5] = st_sw;
   return MPO_OK;
 }
 
-extern "C" int mpo_apply_phases(gbs_mpo *h, const double *phase) {
-  if (!h || !phase) return fail(MPO_EINVAL, "NULL argument");
-  int rc = check_latched(h);
-  if (rc != MPO_OK) return rc;
-  for (int j = 0; j < h->st.M; ++j)
-    if (!std::isfinite(phase[j])) return fail(MPO_EINVAL, "non-finite phase");
-  HIPCHK(hipMemcpyAsync(h->dPhase, phase, sizeof(double) * h->st.M, hipMemcpyHostToDevice,
-                        h->stream));
-  HIPCHK(launch_phases(h->st, h->dPhase, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  return MPO_OK;
-}
-
-extern "C" int mpo_sync(gbs_mpo *h) {
-  if (!h) return fail(MPO_EINVAL, "handle is NULL");
-  return sync_and_check(h);
-}
-
-extern "C" int mpo_entropy(gbs_mpo *h, double *S, double *S_max_so_far) {
-  if (!h || !S) return fail(MPO_EINVAL, "NULL argument");
-  const int M = h->st.M;
-  std::vector<double> ee(M + 1);
-  unsigned long long mx = 0;
-  HIPCHK(hipMemcpyAsync(ee.data(), h->st.ee, sizeof(double) * (M + 1), hipMemcpyDeviceToHost,
-                        h->stream));
-  HIPCHK(hipMemcpyAsync(&mx, h->st.ee_max, sizeof(mx), hipMemcpyDeviceToHost, h->stream));
-  int rc = sync_and_check(h);
-  if (rc != MPO_OK) return rc;
-  for (int b = 1; b < M; ++b) S[b - 1] = ee[b];
-  if (S_max_so_far) {
-    double m;
-    std::memcpy(&m, &mx, sizeof(m));
-    for (int b = 1; b < M; ++b) m = std::max(m, ee[b]);
-    *S_max_so_far = m;
-  }
-  return MPO_OK;
-}
-
-extern "C" int mpo_photon_marginals(gbs_mpo *h, double *P, double *trace) {
-  if (!h || !P) return fail(MPO_EINVAL, "NULL argument");
-  int rc = check_latched(h);
-  if (rc != MPO_OK) return rc;
-  const int M = h->st.M, d = h->st.d;
-  HIPCHK(launch_marginals(h->st, h->envL, h->envR, h->dP, h->dTrace, h->stream));
+int readout_marginals(Engine &E, Instance &I, double *P, double *trace) {
+  const int M = I.st.M, d = I.st.d;
+  HIPCHK(launch_marginals(I.st, I.envL, I.envR, I.dPart, I.dP, I.dTrace, E.stream));
   std::vector<double> raw((size_t)M * d);
   double tr = 0.0;
-  HIPCHK(hipMemcpyAsync(raw.data(), h->dP, sizeof(double) * M * d, hipMemcpyDeviceToHost,
-                        h->stream));
-  HIPCHK(hipMemcpyAsync(&tr, h->dTrace, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  rc = sync_and_check(h);
-  if (rc != MPO_OK) return rc;
+  HIPCHK(hipMemcpyAsync(raw.data(), I.dP, sizeof(double) * M * d, hipMemcpyDeviceToHost,
+                        E.stream));
+  HIPCHK(hipMemcpyAsync(&tr, I.dTrace, sizeof(double), hipMemcpyDeviceToHost, E.stream));
+  HIPCHK(hipStreamSynchronize(E.stream));
   if (!(tr > 0.0) || !std::isfinite(tr)) return fail(MPO_ENUMERIC, "non-positive trace");
-  for (size_t i = 0; i < raw.size(); ++i) P[i] = raw[i] / tr;
+  if (P)
+    for (size_t i = 0; i < raw.size(); ++i) P[i] = raw[i] / tr;
   if (trace) *trace = tr;
   return MPO_OK;
 }
 
+int readout_entropy(Engine &E, Instance &I, double *S, double *S_max) {
+  const int M = I.st.M;
+  std::vector<double> ee(M + 1);
+  unsigned long long mx = 0;
+  HIPCHK(hipMemcpyAsync(ee.data(), I.st.ee, sizeof(double) * (M + 1), hipMemcpyDeviceToHost,
+                        E.stream));
+  HIPCHK(hipMemcpyAsync(&mx, I.st.ee_max, sizeof(mx), hipMemcpyDeviceToHost, E.stream));
+  HIPCHK(hipStreamSynchronize(E.stream));
+  if (S)
+    for (int b = 1; b < M; ++b) S[b - 1] = ee[b];
+  if (S_max) {
+    double m;
+    std::memcpy(&m, &mx, sizeof(m));
+    for (int b = 1; b < M; ++b) m = std::max(m, ee[b]);
+    *S_max = m;
+  }
+  return MPO_OK;
+}
+
+bool valid_layer(int M, int n_gates, const int *left_site, const double *theta,
+                 const double *phi) {
+  std::vector<char> used(M, 0);
+  for (int g = 0; g < n_gates; ++g) {
+    const int k = left_site[g];
+    if (k < 0 || k > M - 2) return false;
+    if (used[k] || used[k + 1]) return false;
+    if (!std::isfinite(theta[g]) || !std::isfinite(phi[g])) return false;
+    used[k] = used[k + 1] = 1;
+  }
+  return true;
+}
+
+}  // namespace
+
+// ============================================================================
+// single-simulation C ABI
+// ============================================================================
+extern "C" const char *mpo_last_error(void) { return g_err.c_str(); }
+
+extern "C" void mpo_free(gbs_mpo *h) {
+  if (!h) return;
+  engine_destroy(h->eng);
+  delete h;
+}
+
+extern "C" int mpo_init_lossy_squeezed(int M, const double *r, double eta, int d, int chi,
+                                       int precision, void *hip_stream, gbs_mpo **out) {
+  if (!out) return fail(MPO_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_args(M, r, eta, d, chi, precision);
+  if (rc != MPO_OK) return rc;
+  size_t fb = 0, tb = 0;
+  if (hipMemGetInfo(&fb, &tb) != hipSuccess) return fail(MPO_EDEVICE, "hipMemGetInfo failed");
+  if ((double)projected_bytes(M, d, chi) > 0.9 * (double)fb)
+    return fail(MPO_ENOMEM, "projected device memory exceeds the free HBM");
+  gbs_mpo *h = new gbs_mpo();
+  rc = engine_init(h->eng, hip_stream, precision, 0);
+  if (rc == MPO_OK) {
+    h->slot = engine_reserve_slot(h->eng);
+    if (h->slot < 0) rc = fail(MPO_ENOMEM, "state table allocation failed");
+  }
+  if (rc == MPO_OK) rc = instance_create(h->eng, h->slot, M, r, eta, d, chi);
+  if (rc == MPO_OK) rc = upload_states(h->eng);
+  if (rc == MPO_OK) rc = sync_and_check(h->eng);
+  if (rc != MPO_OK) {
+    mpo_free(h);
+    return rc;
+  }
+  h->eng.inst[h->slot].id = 0;
+  h->eng.committed += h->eng.inst[h->slot].bytes;
+  *out = h;
+  return MPO_OK;
+}
+
+extern "C" int mpo_apply_bs_layer(gbs_mpo *h, int n_gates, const int *left_site,
+                                  const double *theta, const double *phi) {
+  if (!h) return fail(MPO_EINVAL, "handle is NULL");
+  Instance &I = h->eng.inst[h->slot];
+  const int M = I.st.M;
+  if (n_gates < 0 || n_gates > M / 2) return fail(MPO_EINVAL, "n_gates out of range");
+  if (n_gates == 0) return MPO_OK;
+  if (!left_site || !theta || !phi) return fail(MPO_EINVAL, "NULL gate array");
+  if (!valid_layer(M, n_gates, left_site, theta, phi))
+    return fail(MPO_EINVAL, "gates must be disjoint, in range and finite");
+  std::vector<GateParam> gates(n_gates);
+  for (int g = 0; g < n_gates; ++g) {
+    gates[g] = GateParam{};
+    gates[g].site = left_site[g];
+    gates[g].inst = h->slot;
+    gates[g].theta = theta[g];
+    gates[g].phi = phi[g];
+  }
+  return engine_apply(h->eng, gates, true);
+}
+
+extern "C" int mpo_apply_phases(gbs_mpo *h, const double *phase) {
+  if (!h || !phase) return fail(MPO_EINVAL, "NULL argument");
+  Instance &I = h->eng.inst[h->slot];
+  for (int j = 0; j < I.st.M; ++j)
+    if (!std::isfinite(phase[j])) return fail(MPO_EINVAL, "non-finite phase");
+  HIPCHK(hipMemcpyAsync(I.dPhase, phase, sizeof(double) * I.st.M, hipMemcpyHostToDevice,
+                        h->eng.stream));
+  HIPCHK(launch_phases(I.st, I.dPhase, h->eng.stream));
+  return sync_and_check(h->eng);
+}
+
+extern "C" int mpo_sync(gbs_mpo *h) {
+  if (!h) return fail(MPO_EINVAL, "handle is NULL");
+  return sync_and_check(h->eng);
+}
+
+extern "C" int mpo_entropy(gbs_mpo *h, double *S, double *S_max_so_far) {
+  if (!h || !S) return fail(MPO_EINVAL, "NULL argument");
+  int rc = sync_and_check(h->eng);
+  if (rc != MPO_OK) return rc;
+  return readout_entropy(h->eng, h->eng.inst[h->slot], S, S_max_so_far);
+}
+
+extern "C" int mpo_photon_marginals(gbs_mpo *h, double *P, double *trace) {
+  if (!h || !P) return fail(MPO_EINVAL, "NULL argument");
+  int rc = sync_and_check(h->eng);
+  if (rc != MPO_OK) return rc;
+  return readout_marginals(h->eng, h->eng.inst[h->slot], P, trace);
+}
+
 extern "C" int mpo_get_bond(gbs_mpo *h, int b, int *dim, double *lam, int *charges) {
   if (!h || !dim) return fail(MPO_EINVAL, "NULL argument");
-  const int M = h->st.M, chi = h->st.chi;
-  if (b < 0 || b > M) return fail(MPO_EINVAL, "bond out of range");
+  const State &st = h->eng.inst[h->slot].st;
+  if (b < 0 || b > st.M) return fail(MPO_EINVAL, "bond out of range");
+  int rc = sync_and_check(h->eng);
+  if (rc != MPO_OK) return rc;
   int D = 0;
-  HIPCHK(hipMemcpyAsync(&D, h->st.dim + b, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
+  HIPCHK(hipMemcpy(&D, st.dim + b, sizeof(int), hipMemcpyDeviceToHost));
   *dim = D;
   if (D > 0 && lam)
-    HIPCHK(hipMemcpy(lam, h->st.lam + (size_t)b * chi, sizeof(double) * D,
+    HIPCHK(hipMemcpy(lam, st.lam + (size_t)b * st.chi, sizeof(double) * D,
                      hipMemcpyDeviceToHost));
   if (D > 0 && charges) {
     std::vector<int> c(D);
-    HIPCHK(hipMemcpy(c.data(), h->st.chg + (size_t)b * chi, sizeof(int) * D,
+    HIPCHK(hipMemcpy(c.data(), st.chg + (size_t)b * st.chi, sizeof(int) * D,
                      hipMemcpyDeviceToHost));
     for (int i = 0; i < D; ++i) {
       charges[2 * i] = charge_n(c[i]);
       charges[2 * i + 1] = charge_np(c[i]);
     }
   }
-  return sync_and_check(h);
+  return MPO_OK;
 }
 
 extern "C" int mpo_get_site(gbs_mpo *h, int j, double *G) {
   if (!h || !G) return fail(MPO_EINVAL, "NULL argument");
-  const int M = h->st.M, chi = h->st.chi;
-  if (j < 0 || j >= M) return fail(MPO_EINVAL, "site out of range");
+  const State &st = h->eng.inst[h->slot].st;
+  if (j < 0 || j >= st.M) return fail(MPO_EINVAL, "site out of range");
+  int rc = sync_and_check(h->eng);
+  if (rc != MPO_OK) return rc;
   int D[2];
-  HIPCHK(hipMemcpyAsync(D, h->st.dim + j, sizeof(int) * 2, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  std::vector<cd> tmp((size_t)chi * chi);
-  HIPCHK(hipMemcpy(tmp.data(), h->st.gam + (size_t)j * chi * chi, sizeof(cd) * chi * chi,
-                   hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(D, st.dim + j, sizeof(int) * 2, hipMemcpyDeviceToHost));
+  std::vector<cd> tmp((size_t)st.chi * st.chi);
+  HIPCHK(hipMemcpy(tmp.data(), st.gam + (size_t)j * st.chi * st.chi,
+                   sizeof(cd) * st.chi * st.chi, hipMemcpyDeviceToHost));
   for (int a = 0; a < D[0]; ++a)
     for (int b = 0; b < D[1]; ++b) {
-      G[2 * ((size_t)a * D[1] + b)] = tmp[(size_t)a * chi + b].re;
-      G[2 * ((size_t)a * D[1] + b) + 1] = tmp[(size_t)a * chi + b].im;
+      G[2 * ((size_t)a * D[1] + b)] = tmp[(size_t)a * st.chi + b].re;
+      G[2 * ((size_t)a * D[1] + b) + 1] = tmp[(size_t)a * st.chi + b].im;
     }
-  return sync_and_check(h);
+  return MPO_OK;
 }
 
 extern "C" int mpo_layer_stats(gbs_mpo *h, long long *stats) {
   if (!h || !stats) return fail(MPO_EINVAL, "NULL argument");
-  int rc = sync_and_check(h);
+  int rc = sync_and_check(h->eng);
   if (rc != MPO_OK) return rc;
-  for (int i = 0; i < 6; ++i) stats[i] = h->stats[i];
-  return MPO_OK;
-}
-
-extern "C" int mpo_set_profiling(gbs_mpo *h, int enable) {
-  if (!h) return fail(MPO_EINVAL, "handle is NULL");
-  int rc = sync_and_check(h);
-  if (rc != MPO_OK) return rc;
-  if (enable) {
-    for (int i = 0; i < 2 * gbs_mpo::NPH; ++i)
-      if (!h->ev[i]) HIPCHK(hipEventCreate(&h->ev[i]));
-  }
-  h->prof = enable != 0;
-  h->prof_pending = false;
-  for (int p = 0; p < gbs_mpo::NPH; ++p) {
-    h->ph_ms[p] = 0.0;
-    h->ph_n[p] = 0;
-  }
-  for (double &x : h->work) x = 0.0;
-  return MPO_OK;
-}
-
-extern "C" int mpo_get_profile(gbs_mpo *h, double *phase_ms, long long *phase_launches,
-                               double *work) {
-  if (!h) return fail(MPO_EINVAL, "handle is NULL");
-  int rc = sync_and_check(h);
-  if (rc != MPO_OK) return rc;
-  for (int p = 0; p < gbs_mpo::NPH; ++p) {
-    if (phase_ms) phase_ms[p] = h->ph_ms[p];
-    if (phase_launches) phase_launches[p] = h->ph_n[p];
-  }
-  if (work)
-    for (int i = 0; i < 4; ++i) work[i] = h->work[i];
+  for (int i = 0; i < 6; ++i) stats[i] = h->eng.stats[i];
   return MPO_OK;
 }
 
 extern "C" int mpo_layer_blocks(gbs_mpo *h, int max_blocks, int *out) {
   if (!h || max_blocks < 0 || (max_blocks > 0 && !out)) return fail(MPO_EINVAL, "bad argument");
-  int rc = sync_and_check(h);
+  int rc = sync_and_check(h->eng);
   if (rc != MPO_OK) return rc;
-  const Layer &ly = h->ly;
-  int total = 0;
-  std::vector<BlkDesc> tmp;
-  for (int g = 0; g < ly.ngates; ++g) {
-    const int nb = h->h_tot[g].nblk;
-    tmp.resize(nb);
-    if (nb > 0)
-      HIPCHK(hipMemcpy(tmp.data(), ly.blk + (size_t)g * ly.max_blk, sizeof(BlkDesc) * nb,
-                       hipMemcpyDeviceToHost));
-    for (int i = 0; i < nb; ++i, ++total) {
-      if (total >= max_blocks) continue;
-      int *o = out + (size_t)8 * total;
-      o[0] = g;
-      o[1] = charge_n(tmp[i].q);
-      o[2] = charge_np(tmp[i].q);
-      o[3] = tmp[i].r;
-      o[4] = tmp[i].s;
-      o[5] = tmp[i].comp;
-      o[6] = tmp[i].sweeps;
-      o[7] = tmp[i].kq;
-    }
+  const Engine &E = h->eng;
+  const int total = (int)E.last_blk.size();
+  for (int i = 0; i < total && i < max_blocks; ++i) {
+    const BlkDesc &B = E.last_blk[i];
+    int *o = out + (size_t)8 * i;
+    o[0] = E.last_blk_gate[i];
+    o[1] = charge_n(B.q);
+    o[2] = charge_np(B.q);
+    o[3] = B.r;
+    o[4] = B.s;
+    o[5] = B.comp;
+    o[6] = B.sweeps;
+    o[7] = B.kq;
   }
   return total;
+}
+
+static int set_profiling(Engine &E, int enable) {
+  int rc = sync_and_check(E);
+  if (rc != MPO_OK) return rc;
+  E.prof = enable != 0;
+  for (int p = 0; p < Engine::NPH; ++p) {
+    E.ph_ms[p] = 0.0;
+    E.ph_n[p] = 0;
+  }
+  for (double &x : E.work) x = 0.0;
+  return MPO_OK;
+}
+
+static int get_profile(Engine &E, double *phase_ms, long long *phase_launches, double *work) {
+  int rc = sync_and_check(E);
+  if (rc != MPO_OK) return rc;
+  for (int p = 0; p < Engine::NPH; ++p) {
+    if (phase_ms) phase_ms[p] = E.ph_ms[p];
+    if (phase_launches) phase_launches[p] = E.ph_n[p];
+  }
+  if (work)
+    for (int i = 0; i < 4; ++i) work[i] = E.work[i];
+  return MPO_OK;
+}
+
+extern "C" int mpo_set_profiling(gbs_mpo *h, int enable) {
+  if (!h) return fail(MPO_EINVAL, "handle is NULL");
+  return set_profiling(h->eng, enable);
+}
+
+extern "C" int mpo_get_profile(gbs_mpo *h, double *phase_ms, long long *phase_launches,
+                               double *work) {
+  if (!h) return fail(MPO_EINVAL, "handle is NULL");
+  return get_profile(h->eng, phase_ms, phase_launches, work);
+}
+
+// ============================================================================
+// batched / continuous-batching engine C ABI
+// ============================================================================
+extern "C" long long mpo_engine_projected_bytes(int M, int d, int chi) {
+  if (M < 2 || d < 2 || chi < 1) return -1;
+  return projected_bytes(M, d, chi);
+}
+
+extern "C" int mpo_engine_create(void *hip_stream, int precision, long long budget_bytes,
+                                 gbs_engine **out) {
+  if (!out) return fail(MPO_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (precision != MPO_FP64 && precision != MPO_MIXED)
+    return fail(MPO_EINVAL, "precision must be MPO_FP64 or MPO_MIXED");
+  if (budget_bytes < 0) return fail(MPO_EINVAL, "budget must be >= 0");
+  gbs_engine *e = new gbs_engine();
+  int rc = engine_init(e->eng, hip_stream, precision, budget_bytes);
+  if (rc != MPO_OK) {
+    engine_destroy(e->eng);
+    delete e;
+    return rc;
+  }
+  *out = e;
+  return MPO_OK;
+}
+
+extern "C" void mpo_engine_free(gbs_engine *e) {
+  if (!e) return;
+  engine_destroy(e->eng);
+  delete e;
+}
+
+extern "C" int mpo_engine_add(gbs_engine *e, int M, const double *r, double eta, int d, int chi,
+                              const double *U_reim, int *id) {
+  if (!e || !id || !U_reim) return fail(MPO_EINVAL, "NULL argument");
+  Engine &E = e->eng;
+  int rc = validate_args(M, r, eta, d, chi, E.precision);
+  if (rc != MPO_OK) return rc;
+  const long long need = projected_bytes(M, d, chi);
+  if (E.committed + need > E.budget)
+    return fail(MPO_ENOMEM, "projected memory of the request exceeds the free budget");
+  const int G = M * (M - 1) / 2;
+  std::vector<int> lptr(M + 1), site(std::max(G, 1));
+  std::vector<double> theta(std::max(G, 1)), phi(std::max(G, 1)), phase(M);
+  const int nl = gbs_clements_decompose(M, U_reim, lptr.data(), site.data(), theta.data(),
+                                        phi.data(), phase.data());
+  if (nl < 0) return fail(MPO_EINVAL, "interferometer is not unitary");
+  lptr.resize(nl + 1);
+  const int slot = engine_reserve_slot(E);
+  if (slot < 0) return fail(MPO_ENOMEM, "state table allocation failed");
+  rc = instance_create(E, slot, M, r, eta, d, chi);
+  if (rc != MPO_OK) {
+    Instance &I = E.inst[slot];
+    for (void *p : I.allocs) hipFree(p);
+    I = Instance();
+    E.states_dirty = true;
+    return rc;
+  }
+  Instance &I = E.inst[slot];
+  I.lptr = std::move(lptr);
+  I.site = std::move(site);
+  I.theta = std::move(theta);
+  I.phi = std::move(phi);
+  I.next_layer = 0;
+  I.id = E.next_id++;
+  E.committed += I.bytes;
+  if (nl == 0) {
+    I.done = true;
+    I.P.assign((size_t)M * d, 0.0);
+    int rr = readout_entropy(E, I, nullptr, &I.smax);
+    if (rr == MPO_OK) rr = readout_marginals(E, I, I.P.data(), &I.trace);
+    I.status = rr;
+    instance_release(E, slot);
+  }
+  *id = I.id;
+  return MPO_OK;
+}
+
+// Applies the next layer of every live, unfinished simulation in one batched
+// launch sequence; simulations whose last layer was applied are retired
+// (readouts taken, device memory released).
+extern "C" int mpo_engine_step(gbs_engine *e, int *n_active) {
+  if (!e) return fail(MPO_EINVAL, "engine is NULL");
+  Engine &E = e->eng;
+  std::vector<GateParam> gates;
+  std::vector<int> stepped;
+  for (size_t s = 0; s < E.inst.size(); ++s) {
+    Instance &I = E.inst[s];
+    if (!I.live || I.done) continue;
+    const int l = I.next_layer;
+    for (int g = I.lptr[l]; g < I.lptr[l + 1]; ++g) {
+      GateParam gp{};
+      gp.site = I.site[g];
+      gp.inst = (int)s;
+      gp.theta = I.theta[g];
+      gp.phi = I.phi[g];
+      gates.push_back(gp);
+    }
+    stepped.push_back((int)s);
+  }
+  int rc = engine_apply(E, gates, false);
+  if (rc != MPO_OK) return rc;
+  rc = sync_and_check(E, false);
+  if (rc != MPO_OK) return rc;
+  int active = 0;
+  for (int s : stepped) {
+    Instance &I = E.inst[s];
+    ++I.next_layer;
+    const int err = E.h_errs[s];
+    if (err || I.next_layer + 1 >= (int)I.lptr.size()) {
+      // finished, or failed on the device: retire (a failure stays in status)
+      I.done = true;
+      I.P.assign((size_t)I.st.M * I.st.d, 0.0);
+      int rr = err ? fail(MPO_ENUMERIC, err_text(err)) : MPO_OK;
+      if (rr == MPO_OK) rr = readout_entropy(E, I, nullptr, &I.smax);
+      if (rr == MPO_OK) rr = readout_marginals(E, I, I.P.data(), &I.trace);
+      I.status = rr;
+      if (rr != MPO_OK) I.msg = g_err;
+      instance_release(E, s);
+    } else {
+      ++active;
+    }
+  }
+  if (n_active) *n_active = active;
+  return MPO_OK;
+}
+
+extern "C" int mpo_engine_result(gbs_engine *e, int id, int *done, double *S_max, double *trace,
+                                 double *P) {
+  if (!e || !done) return fail(MPO_EINVAL, "NULL argument");
+  Engine &E = e->eng;
+  for (auto &I : E.inst) {
+    if (I.id != id) continue;
+    *done = (I.done && !I.live) ? 1 : 0;
+    if (*done) {
+      if (I.status != MPO_OK) return fail(I.status, "simulation failed: " + I.msg);
+      if (S_max) *S_max = I.smax;
+      if (trace) *trace = I.trace;
+      if (P) std::copy(I.P.begin(), I.P.end(), P);
+    }
+    return MPO_OK;
+  }
+  return fail(MPO_EINVAL, "unknown simulation id");
+}
+
+extern "C" int mpo_engine_release(gbs_engine *e, int id) {
+  if (!e) return fail(MPO_EINVAL, "engine is NULL");
+  Engine &E = e->eng;
+  for (size_t s = 0; s < E.inst.size(); ++s) {
+    Instance &I = E.inst[s];
+    if (I.id != id) continue;
+    if (I.live) return fail(MPO_EBUSY, "simulation still running");
+    I = Instance();
+    return MPO_OK;
+  }
+  return fail(MPO_EINVAL, "unknown simulation id");
+}
+
+extern "C" int mpo_engine_set_profiling(gbs_engine *e, int enable) {
+  if (!e) return fail(MPO_EINVAL, "engine is NULL");
+  return set_profiling(e->eng, enable);
+}
+
+extern "C" int mpo_engine_get_profile(gbs_engine *e, double *phase_ms, long long *phase_launches,
+                                      double *work) {
+  if (!e) return fail(MPO_EINVAL, "engine is NULL");
+  return get_profile(e->eng, phase_ms, phase_launches, work);
 }

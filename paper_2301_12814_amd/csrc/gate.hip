@@ -31,9 +31,10 @@ namespace gbs {
 // where i, j count photons in mode 1 of the output / input.  Stored entries
 // are those with both modes inside the cutoff: tab[n][i][j], i, j, n-i, n-j < d.
 // ----------------------------------------------------------------------------
-__global__ void k_fock(Layer ly, int d) {
+__global__ void k_fock(Layer ly) {
   const int g = blockIdx.x;
   const GateParam gp = ly.gates[g];
+  const int d = ly.states[gp.inst].d;
   const int nmax = 2 * d - 2;
   const int W = nmax + 1;
   __shared__ cd s_b[2][32 * 32];
@@ -42,7 +43,7 @@ __global__ void k_fock(Layer ly, int d) {
   const cd T21 = cmk(cos(gp.phi) * st, sin(gp.phi) * st);
   const cd T12 = cmk(-st, 0.0);
   const cd T22 = cmk(ct, 0.0);
-  cd *tab = ly.fock + (size_t)g * W * d * d;
+  cd *tab = ly.fock + gp.fock0;
   for (int i = threadIdx.x; i < W * d * d; i += blockDim.x) tab[i] = cmk(0.0, 0.0);
   if (threadIdx.x == 0) s_b[0][0] = cmk(1.0, 0.0);
   __syncthreads();
@@ -69,8 +70,8 @@ __global__ void k_fock(Layer ly, int d) {
   }
 }
 
-hipError_t launch_fock(Layer ly, int d, hipStream_t s) {
-  hipLaunchKernelGGL(k_fock, dim3(ly.ngates), dim3(256), 0, s, ly, d);
+hipError_t launch_fock(Layer ly, hipStream_t s) {
+  hipLaunchKernelGGL(k_fock, dim3(ly.ngates), dim3(256), 0, s, ly);
   return hipGetLastError();
 }
 
@@ -93,28 +94,36 @@ constexpr int CHUNK = 256;
 
 // LDS bytes of the one-workgroup Jacobi (operand + column norms) and the
 // widest panel whose pair (2 w columns of m rows) fits in LDS.
-__host__ __device__ inline size_t lds_small_need(int m, int n) {
+__host__ __device__ inline size_t svd_small_need_(int m, int n) {
   return sizeof(cd) * (size_t)m * n + sizeof(double) * (size_t)n;
 }
+size_t svd_small_need(int m, int n) { return svd_small_need_(m, n); }
+#define svd_small_need svd_small_need_
 __host__ __device__ inline int panel_width(int m, int lds_bytes) {
   int w = 8;
   while (w > 1 && 2 * (size_t)w * m * sizeof(cd) > (size_t)lds_bytes) w >>= 1;
   return w;
 }
 
-__global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap, int sv_cap,
-                                               int lds_bytes) {
+// Two passes over the charge box of every gate.  The count pass (FILL =
+// false) builds the mirror maps, decides whether the gate may use Hermiticity
+// and totals the sizes the fill pass needs; the host then places every gate's
+// regions and the fill pass (FILL = true) writes the block descriptors, the
+// offsets and the row / column lists.  With Hermiticity a block with n > n'
+// is derived from its mirror (its mirror exists because both outer bonds are
+// mirror symmetric).
+template <bool FILL>
+__global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes) {
   const int g = blockIdx.x;
+  const GateParam gp = ly.gates[g];
+  const State st = ly.states[gp.inst];
   const int d = st.d, chi = st.chi;
-  const int j = ly.gates[g].site;
+  const int j = gp.site;
   const int *cL = st.chg + (size_t)j * chi;
   const int *cR = st.chg + (size_t)(j + 2) * chi;
   const int DL = st.dim[j], DR = st.dim[j + 2];
-  BlkDesc *blk = ly.blk + (size_t)g * ly.max_blk;
-  int *rows = ly.rows + (size_t)g * rows_cap;
-  int *cols = ly.cols + (size_t)g * rows_cap;
-  int *mirL = ly.mirL + (size_t)g * chi;
-  int *mirR = ly.mirR + (size_t)g * chi;
+  int *mirL = ly.mirL + gp.mir0;
+  int *mirR = ly.mirR + gp.mir0;
   const double *lamL = st.lam + (size_t)j * chi;
   const double *lamR = st.lam + (size_t)(j + 2) * chi;
   __shared__ int s_sym;
@@ -126,27 +135,28 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
     s_sym = 1;
   }
   __syncthreads();
-  // pass 0: mirror index maps.  The mirror of index a (charge (n, n'), rank k
-  // inside its charge run) is the index of charge (n', n) with the same rank.
-  // The gate exploits Hermiticity only when both outer bonds are exactly
-  // mirror symmetric (same charges, bitwise equal Schmidt values).
-  for (int a = threadIdx.x; a < DL; a += blockDim.x) {
-    const int c = cL[a];
-    const int cm = pack_charge(charge_np(c), charge_n(c));
-    const int am = lower_bound(cL, DL, cm) + (a - lower_bound(cL, DL, c));
-    const bool ok = am < DL && cL[am] == cm && lamL[am] == lamL[a];
-    mirL[a] = ok ? am : -1;
-    if (!ok) s_sym = 0;
+  if (!FILL) {
+    // Mirror index maps.  The mirror of index a (charge (n, n'), rank k inside
+    // its charge run) is the index of charge (n', n) with the same rank.  The
+    // gate uses Hermiticity only when both outer bonds are exactly mirror
+    // symmetric (same charges, bitwise equal Schmidt values).
+    for (int a = threadIdx.x; a < DL; a += blockDim.x) {
+      const int c = cL[a];
+      const int cm = pack_charge(charge_np(c), charge_n(c));
+      const int am = lower_bound(cL, DL, cm) + (a - lower_bound(cL, DL, c));
+      const bool ok = am < DL && cL[am] == cm && lamL[am] == lamL[a];
+      mirL[a] = ok ? am : -1;
+      if (!ok) s_sym = 0;
+    }
+    for (int b = threadIdx.x; b < DR; b += blockDim.x) {
+      const int c = cR[b];
+      const int cm = pack_charge(charge_np(c), charge_n(c));
+      const int bm = lower_bound(cR, DR, cm) + (b - lower_bound(cR, DR, c));
+      const bool ok = bm < DR && cR[bm] == cm && lamR[bm] == lamR[b];
+      mirR[b] = ok ? bm : -1;
+      if (!ok) s_sym = 0;
+    }
   }
-  for (int b = threadIdx.x; b < DR; b += blockDim.x) {
-    const int c = cR[b];
-    const int cm = pack_charge(charge_np(c), charge_n(c));
-    const int bm = lower_bound(cR, DR, cm) + (b - lower_bound(cR, DR, c));
-    const bool ok = bm < DR && cR[bm] == cm && lamR[bm] == lamR[b];
-    mirR[b] = ok ? bm : -1;
-    if (!ok) s_sym = 0;
-  }
-  __syncthreads();
   {
     int mn = 1 << 30, mx = -1;
     for (int a = threadIdx.x; a < DL; a += blockDim.x) {
@@ -164,9 +174,11 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
     atomicMax(&s_max1R, mx);
   }
   __syncthreads();
+  const int sym = FILL ? ly.tot[g].sym : s_sym;
   GateTot tot = {};
+  tot.sym = sym;
   if (DL == 0 || DR == 0) {
-    if (threadIdx.x == 0) ly.tot[g] = tot;
+    if (!FILL && threadIdx.x == 0) ly.tot[g] = tot;
     return;
   }
   const int minL0 = charge_n(cL[0]), maxL0 = charge_n(cL[DL - 1]);
@@ -175,19 +187,22 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
   const int lo1 = max(max(s_min1L - (d - 1), s_min1R), 0), hi1 = min(s_max1L, s_max1R + d - 1);
   const int W0 = hi0 - lo0 + 1, W1 = hi1 - lo1 + 1;
   if (W0 <= 0 || W1 <= 0) {
-    if (threadIdx.x == 0) ly.tot[g] = tot;
+    if (!FILL && threadIdx.x == 0) ly.tot[g] = tot;
     return;
   }
   const long long area = (long long)W0 * W1;
-  if (area > ly.box_cap) {
-    if (threadIdx.x == 0) {
+  if (area > (1LL << 26)) {
+    if (!FILL && threadIdx.x == 0) {
       atomicOr(st.err, ERR_BOX_OVERFLOW);
       ly.tot[g] = tot;
     }
     return;
   }
-  // pass 1: compact the non-empty blocks in charge order
-  long long nb = 0;
+  BlkDesc *blk = ly.blk + gp.blk0;
+  // pass 1: the non-empty blocks in charge order (counted, or compacted)
+  long long nb = 0, eb = 0;
+  int svb = 0, rb = 0, cb = 0, chb = 0, bgb = 0, maxr = 0, maxc = 0, maxpp = 0;
+  double fl = 0.0;
   for (long long c0 = 0; c0 < area; c0 += blockDim.x) {
     const long long cell = c0 + threadIdx.x;
     int r = 0, s = 0;
@@ -201,10 +216,32 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
           s += count_window(cR, DR, n, q1 - d + 1, q1);
     }
     const long long flag = (r > 0 && s > 0) ? 1 : 0;
-    long long total;
-    const long long pos = nb + block_exclusive_scan<long long>(flag, s_scan, total);
-    if (flag) {
-      if (pos < ly.max_blk) {
+    if (!FILL) {
+      if (flag) {
+        const bool comp = !(sym && q0 > q1);
+        const int m = max(r, s), n = min(r, s);
+        rb += r;
+        cb += s;
+        maxr = max(maxr, r);
+        maxc = max(maxc, s);
+        if (comp) {
+          eb += (long long)r * s;
+          svb += n;
+          chb += (int)(((long long)r * s + CHUNK - 1) / CHUNK);
+          fl += 16.0 * m * (double)n * n + 36.0 * (double)n * n * n;
+          if (svd_small_need(m, n) > (size_t)lds_bytes) {
+            ++bgb;
+            const int w = panel_width(m, lds_bytes);
+            const int np = (n + w - 1) / w;
+            maxpp = max(maxpp, np + (np & 1));
+          }
+        }
+      }
+      nb += flag;
+    } else {
+      long long total;
+      const long long pos = nb + block_exclusive_scan<long long>(flag, s_scan, total);
+      if (flag) {
         BlkDesc B = {};
         B.q = pack_charge(q0, q1);
         B.r = r;
@@ -214,17 +251,51 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
         B.n = min(r, s);
         B.gate = g;
         blk[pos] = B;
-      } else {
-        atomicOr(st.err, ERR_WORKSPACE);
       }
+      nb += total;
     }
-    nb += total;
+  }
+  if (!FILL) {
+    // block-wide totals
+    __shared__ long long s_nb, s_eb;
+    __shared__ int s_sv, s_rb, s_cb, s_ch, s_bg, s_mr, s_mc, s_pp;
+    __shared__ double s_fl;
+    if (threadIdx.x == 0) {
+      s_nb = 0; s_eb = 0; s_sv = 0; s_rb = 0; s_cb = 0; s_ch = 0; s_bg = 0; s_mr = 0; s_mc = 0;
+      s_pp = 0; s_fl = 0.0;
+    }
+    __syncthreads();
+    atomicAdd((unsigned long long *)&s_nb, (unsigned long long)nb);
+    atomicAdd((unsigned long long *)&s_eb, (unsigned long long)eb);
+    atomicAdd(&s_sv, svb);
+    atomicAdd(&s_rb, rb);
+    atomicAdd(&s_cb, cb);
+    atomicAdd(&s_ch, chb);
+    atomicAdd(&s_bg, bgb);
+    atomicMax(&s_mr, maxr);
+    atomicMax(&s_mc, maxc);
+    atomicMax(&s_pp, maxpp);
+    atomicAdd(&s_fl, fl);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      tot.nblk = (int)s_nb;
+      tot.sv = s_sv;
+      tot.rows = s_rb;
+      tot.cols = s_cb;
+      tot.maxr = s_mr;
+      tot.maxc = s_mc;
+      tot.elems = s_eb;
+      tot.chunks = s_ch;
+      tot.nbig = s_bg;
+      tot.maxpp = s_pp;
+      tot.svd_flops = s_fl;
+      ly.tot[g] = tot;
+    }
+    return;
   }
   __syncthreads();
-  const int nblk = (int)min(nb, (long long)ly.max_blk);
-  const int sym = s_sym;
-  // mirror block by binary search on the sorted charges; with symmetric outer
-  // bonds only canonical (n <= n') blocks are computed, mirrors are derived
+  const int nblk = (int)nb;
+  // mirror block by binary search on the sorted charges
   for (int bi = threadIdx.x; bi < nblk; bi += blockDim.x) {
     BlkDesc &B = blk[bi];
     const int qm = pack_charge(charge_np(B.q), charge_n(B.q));
@@ -234,15 +305,13 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
       if (blk[mid].q < qm) lo = mid + 1; else hi = mid;
     }
     B.mirror = (lo < nblk && blk[lo].q == qm) ? lo : -1;
-    B.comp = !(sym && B.mirror >= 0 && charge_n(B.q) > charge_np(B.q));
+    B.comp = !(sym && charge_n(B.q) > charge_np(B.q));
   }
   __syncthreads();
   // pass 2: offsets; each computed block goes either to the one-workgroup LDS
   // Jacobi (operand fits in LDS) or to the multi-workgroup panel rounds
-  long long eb = 0;
-  int svb = 0, rb = 0, cb = 0, chb = 0, bgb = 0, maxr = 0, maxc = 0, maxpp = 0;
-  double fl = 0.0;
-  int *bigl = ly.bigl + (size_t)g * rows_cap;
+  int *bigl = ly.bigl + gp.lst0;
+  eb = 0; svb = 0; rb = 0; cb = 0; chb = 0; bgb = 0;
   for (int b0 = 0; b0 < nblk; b0 += blockDim.x) {
     const int bi = b0 + threadIdx.x;
     long long e = 0;
@@ -253,18 +322,14 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
         e = (long long)B.r * B.s;
         sv = B.n;
         ch = (int)((e + CHUNK - 1) / CHUNK);
-        fl += 16.0 * B.m * (double)B.n * B.n + 36.0 * (double)B.n * B.n * B.n;
-        if (lds_small_need(B.m, B.n) > (size_t)lds_bytes) {
+        if (svd_small_need(B.m, B.n) > (size_t)lds_bytes) {
           bg = 1;
           w = panel_width(B.m, lds_bytes);
           npan = (B.n + w - 1) / w;
-          maxpp = max(maxpp, npan + (npan & 1));
         }
       }
       r = B.r;
       c = B.s;
-      maxr = max(maxr, B.r);
-      maxc = max(maxc, B.s);
     }
     long long te;
     int tsv, tr, tc, tch, tbg;
@@ -291,12 +356,9 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
     eb += te; svb += tsv; rb += tr; cb += tc; chb += tch; bgb += tbg;
   }
   __syncthreads();
-  if (rb > rows_cap || cb > rows_cap || svb > sv_cap) {
-    if (threadIdx.x == 0) atomicOr(st.err, ERR_WORKSPACE);
-    if (threadIdx.x == 0) ly.tot[g] = tot;
-    return;
-  }
   // pass 3: row / column index lists (ascending)
+  int *rows = ly.rows + gp.lst0;
+  int *cols = ly.cols + gp.lst0;
   for (int bi = threadIdx.x; bi < nblk; bi += blockDim.x) {
     const BlkDesc B = blk[bi];
     const int q0 = charge_n(B.q), q1 = charge_np(B.q);
@@ -313,52 +375,43 @@ __global__ __launch_bounds__(1024) void k_plan(State st, Layer ly, int rows_cap,
       for (int b = b0; b < b1; ++b) cols[B.coff + k++] = b;
     }
   }
-  // block-wide max of maxr / maxc, sum of the SVD work
-  __shared__ int s_mr, s_mc, s_pp;
-  __shared__ double s_fl;
-  if (threadIdx.x == 0) { s_mr = 0; s_mc = 0; s_pp = 0; s_fl = 0.0; }
-  __syncthreads();
-  atomicMax(&s_mr, maxr);
-  atomicMax(&s_mc, maxc);
-  atomicMax(&s_pp, maxpp);
-  atomicAdd(&s_fl, fl);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    tot.nblk = nblk;
-    tot.sv = svb;
-    tot.rows = rb;
-    tot.cols = cb;
-    tot.maxr = s_mr;
-    tot.maxc = s_mc;
-    tot.elems = eb;
-    tot.chunks = chb;
-    tot.nbig = bgb;
-    tot.maxpp = s_pp;
-    tot.sym = sym;
-    tot.svd_flops = s_fl;
-    ly.tot[g] = tot;
-  }
 }
 
-hipError_t launch_plan(State st, Layer ly, hipStream_t s) {
-  const int rows_cap = st.d * st.d * st.chi;
-  hipLaunchKernelGGL(k_plan, dim3(ly.ngates), dim3(1024), 0, s, st, ly, rows_cap, rows_cap,
-                     svd_lds_bytes());
+hipError_t launch_plan_count(Layer ly, hipStream_t s) {
+  hipLaunchKernelGGL(k_plan<false>, dim3(ly.ngates), dim3(1024), 0, s, ly, svd_lds_bytes());
   return hipGetLastError();
 }
 
-hipError_t launch_lists(State, Layer, hipStream_t) { return hipSuccess; }
+hipError_t launch_plan_fill(Layer ly, hipStream_t s) {
+  hipLaunchKernelGGL(k_plan<true>, dim3(ly.ngates), dim3(1024), 0, s, ly, svd_lds_bytes());
+  return hipGetLastError();
+}
 
-// Locate the gate of a flat index given per-gate starts (ascending).
+// Locate the gate of a flat index given per-gate starts (ascending): the last
+// gate whose start is <= flat (binary search; gates may own zero items).
 __device__ inline int find_gate_blk(const GateBase *base, int ng, int flat) {
-  int g = 0;
-  while (g + 1 < ng && base[g + 1].blk <= flat) ++g;
-  return g;
+  int lo = 0, hi = ng;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (base[mid].blk <= flat) lo = mid; else hi = mid;
+  }
+  return lo;
 }
 __device__ inline int find_gate_chunk(const GateBase *base, int ng, long long flat) {
-  int g = 0;
-  while (g + 1 < ng && base[g + 1].echunk <= flat) ++g;
-  return g;
+  int lo = 0, hi = ng;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (base[mid].echunk <= flat) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+__device__ inline int find_gate_big(const GateBase *base, int ng, int flat) {
+  int lo = 0, hi = ng;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (base[mid].big <= flat) lo = mid; else hi = mid;
+  }
+  return lo;
 }
 
 // ----------------------------------------------------------------------------
@@ -368,14 +421,16 @@ __device__ inline int find_gate_chunk(const GateBase *base, int ng, long long fl
 // [max(c_b0, c_a0-d+1), min(c_b0+d-1, c_a0)], same for p1, i.e. one
 // contiguous run of the sorted bond per p0.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(CHUNK) void k_contract(State st, Layer ly, int rows_cap) {
+__global__ __launch_bounds__(CHUNK) void k_contract(Layer ly) {
   const long long chunk = blockIdx.x;
   const int g = find_gate_chunk(ly.base, ly.ngates, chunk);
+  const GateParam gp = ly.gates[g];
+  const State st = ly.states[gp.inst];
   const int d = st.d, chi = st.chi;
-  const int j = ly.gates[g].site;
+  const int j = gp.site;
   const GateBase gb = ly.base[g];
   const int nblk = ly.tot[g].nblk;
-  const BlkDesc *blk = ly.blk + (size_t)g * ly.max_blk;
+  const BlkDesc *blk = ly.blk + gp.blk0;
   // block containing this chunk (chunk offsets stored in uoff)
   const int lc = (int)(chunk - gb.echunk);
   int lo = 0, hi = nblk;
@@ -387,8 +442,8 @@ __global__ __launch_bounds__(CHUNK) void k_contract(State st, Layer ly, int rows
   const long long e = (long long)(lc - B.uoff) * CHUNK + threadIdx.x;
   if (e >= (long long)B.r * B.s) return;
   const int ia = (int)(e / B.s), ib = (int)(e % B.s);
-  const int a = ly.rows[(size_t)g * rows_cap + B.roff + ia];
-  const int b = ly.cols[(size_t)g * rows_cap + B.coff + ib];
+  const int a = ly.rows[gp.lst0 + B.roff + ia];
+  const int b = ly.cols[gp.lst0 + B.coff + ib];
   const int *cL = st.chg + (size_t)j * chi;
   const int *cC = st.chg + (size_t)(j + 1) * chi;
   const int *cR = st.chg + (size_t)(j + 2) * chi;
@@ -398,7 +453,7 @@ __global__ __launch_bounds__(CHUNK) void k_contract(State st, Layer ly, int rows
   const int q0 = charge_n(B.q), q1 = charge_np(B.q);
   const int n0 = ca0 - cb0, n1 = ca1 - cb1;
   const int i0 = ca0 - q0, i1 = ca1 - q1;
-  const cd *tab = ly.fock + (size_t)g * (2 * d - 1) * d * d;
+  const cd *tab = ly.fock + gp.fock0;
   const cd *Ga = st.gam + (size_t)j * chi * chi + (size_t)a * chi;
   const cd *Gb = st.gam + (size_t)(j + 1) * chi * chi + b;
   const double *lC = st.lam + (size_t)(j + 1) * chi;
@@ -425,11 +480,9 @@ __global__ __launch_bounds__(CHUNK) void k_contract(State st, Layer ly, int rows
   ly.A0[gb.e + B.eoff + at] = acc;
 }
 
-hipError_t launch_contract(State st, Layer ly, hipStream_t s) {
+hipError_t launch_contract(Layer ly, hipStream_t s) {
   if (ly.total_chunks == 0) return hipSuccess;
-  const int rows_cap = st.d * st.d * st.chi;
-  hipLaunchKernelGGL(k_contract, dim3((unsigned)ly.total_chunks), dim3(CHUNK), 0, s, st, ly,
-                     rows_cap);
+  hipLaunchKernelGGL(k_contract, dim3((unsigned)ly.total_chunks), dim3(CHUNK), 0, s, ly);
   return hipGetLastError();
 }
 
@@ -553,15 +606,14 @@ __device__ __forceinline__ double block_sum(double v, double *s_red) {
 // non-degenerate singular vector is J-real up to a phase: u[y~] = e^{i phi}
 // conj(u[y]) on the operand's rows.  The bilinear sum s = sum_y u[y] u[y~] =
 // e^{i phi} |u|^2 gives the phase and the column is multiplied by e^{-i phi/2}.
-__device__ __forceinline__ void self_mirror_phase(const State &st, const Layer &ly, int g,
-                                                  const BlkDesc &B, cd *A, int rows_cap) {
+__device__ __forceinline__ void self_mirror_phase(const Layer &ly, const GateParam &gp,
+                                                  const BlkDesc &B, cd *A) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const int m = B.m, n = B.n;
   // operand rows: left-bond indices (stored Theta) or right-bond indices (Theta^T)
-  const int *lst = !B.t ? ly.rows + (size_t)g * rows_cap + B.roff
-                        : ly.cols + (size_t)g * rows_cap + B.coff;
-  const int *my = (!B.t ? ly.mirL : ly.mirR) + (size_t)g * st.chi;
+  const int *lst = !B.t ? ly.rows + gp.lst0 + B.roff : ly.cols + gp.lst0 + B.coff;
+  const int *my = (!B.t ? ly.mirL : ly.mirR) + gp.mir0;
   for (int c = wave; c < n; c += nw) {
     double sr = 0.0, si = 0.0, nr = 0.0;
     for (int y = lane; y < m; y += 64) {
@@ -586,8 +638,8 @@ __device__ __forceinline__ void self_mirror_phase(const State &st, const Layer &
 }
 
 // Singular values = column norms, sorted descending (ties by column).
-__device__ __forceinline__ void sort_values(const State &st, const cd *A, int m, int n,
-                                            double *sig, double *sv, int *perm) {
+__device__ __forceinline__ void sort_values(int *err, const cd *A, int m, int n, double *sig,
+                                            double *sv, int *perm) {
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     double acc = 0.0;
     for (int i = 0; i < m; ++i) acc += cabs2(A[(size_t)c * m + i]);
@@ -603,23 +655,22 @@ __device__ __forceinline__ void sort_values(const State &st, const cd *A, int m,
     }
     sv[rank] = v;
     perm[rank] = c;
-    if (!isfinite(v)) atomicOr(st.err, ERR_NONFINITE);
+    if (!isfinite(v)) atomicOr(err, ERR_NONFINITE);
   }
 }
 
-__device__ inline void big_block_of(const Layer &ly, int flat_big, int rows_cap, int &g,
-                                    int &bi) {
-  g = 0;
-  while (g + 1 < ly.ngates && ly.base[g + 1].big <= flat_big) ++g;
-  bi = ly.bigl[(size_t)g * rows_cap + (flat_big - ly.base[g].big)];
+__device__ inline void big_block_of(const Layer &ly, int flat_big, int &g, int &bi) {
+  g = find_gate_big(ly.base, ly.ngates, flat_big);
+  bi = ly.bigl[ly.gates[g].lst0 + (flat_big - ly.base[g].big)];
 }
 
-__global__ __launch_bounds__(SVD_THREADS) void k_svd_small(State st, Layer ly, int sv_cap,
-                                                           int rows_cap) {
+__global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly) {
   const int flat = blockIdx.x;
   const int g = find_gate_blk(ly.base, ly.ngates, flat);
   const GateBase gb = ly.base[g];
-  BlkDesc *Bp = ly.blk + (size_t)g * ly.max_blk + (flat - gb.blk);
+  const GateParam gp = ly.gates[g];
+  const State st = ly.states[gp.inst];
+  BlkDesc *Bp = ly.blk + gp.blk0 + (flat - gb.blk);
   const BlkDesc B = *Bp;
   if (!B.comp || B.big) return;
   const int m = B.m, n = B.n;
@@ -651,9 +702,8 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(State st, Layer ly, i
     }
     if (sweep == MAX_SWEEPS && threadIdx.x == 0) atomicOr(st.err, ERR_SVD_NOT_CONVERGED);
   }
-  if (charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym) self_mirror_phase(st, ly, g, B, sA, rows_cap);
-  sort_values(st, sA, m, n, sig, ly.sv + (size_t)g * sv_cap + B.svoff,
-              ly.perm + (size_t)g * sv_cap + B.svoff);
+  if (charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym) self_mirror_phase(ly, gp, B, sA);
+  sort_values(st.err, sA, m, n, sig, ly.sv + gp.lst0 + B.svoff, ly.perm + gp.lst0 + B.svoff);
   for (int i = threadIdx.x; i < m * n; i += blockDim.x) A[i] = sA[i];
   if (threadIdx.x == 0) {
     Bp->sweeps = sweep;
@@ -664,10 +714,10 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(State st, Layer ly, i
 // Big blocks: squared Frobenius norm and cleared convergence flags.
 // rotf[4k + (s % 3)]: a rotation happened in sweep s; rotf[4k + 3]: converged
 // at that sweep (0 while running).
-__global__ __launch_bounds__(256) void k_big_prep(State st, Layer ly, int rows_cap) {
+__global__ __launch_bounds__(256) void k_big_prep(Layer ly) {
   int g, bi;
-  big_block_of(ly, blockIdx.x, rows_cap, g, bi);
-  BlkDesc *Bp = ly.blk + (size_t)g * ly.max_blk + bi;
+  big_block_of(ly, blockIdx.x, g, bi);
+  BlkDesc *Bp = ly.blk + ly.gates[g].blk0 + bi;
   const cd *A = ly.A + ly.base[g].e + Bp->eoff;
   __shared__ double s_red[16];
   double f2 = 0.0;
@@ -680,12 +730,11 @@ __global__ __launch_bounds__(256) void k_big_prep(State st, Layer ly, int rows_c
   }
 }
 
-__global__ __launch_bounds__(SVD_THREADS) void k_panel(State st, Layer ly, int round, int sweep,
-                                                       int rows_cap) {
+__global__ __launch_bounds__(SVD_THREADS) void k_panel(Layer ly, int round, int sweep) {
   const int kbig = blockIdx.y;
   int g, bi;
-  big_block_of(ly, kbig, rows_cap, g, bi);
-  const BlkDesc B = ly.blk[(size_t)g * ly.max_blk + bi];
+  big_block_of(ly, kbig, g, bi);
+  const BlkDesc B = ly.blk[ly.gates[g].blk0 + bi];
   const int P = B.npan, Pp = P + (P & 1);
   if (round >= Pp - 1 || (int)blockIdx.x >= Pp / 2) return;
   int *rf = ly.rotf + 4 * (size_t)kbig;
@@ -745,35 +794,39 @@ __global__ __launch_bounds__(SVD_THREADS) void k_panel(State st, Layer ly, int r
   }
 }
 
-// Big blocks still rotating in the given sweep; flags non-convergence on the last.
-__global__ void k_big_count(Layer ly, int sweep, int last, int *err) {
+// Big blocks still rotating in the given sweep; on the last sweep the
+// simulation owning a block that still rotates gets its error latched.
+__global__ void k_big_count(Layer ly, int sweep, int last) {
   __shared__ int s_n;
   if (threadIdx.x == 0) s_n = 0;
   __syncthreads();
   int c = 0;
   for (int k = threadIdx.x; k < ly.total_big; k += blockDim.x) {
     const int *rf = ly.rotf + 4 * (size_t)k;
-    if (!rf[3] && rf[sweep % 3]) ++c;
+    if (!rf[3] && rf[sweep % 3]) {
+      ++c;
+      if (last) {
+        const int g = find_gate_big(ly.base, ly.ngates, k);
+        atomicOr(ly.states[ly.gates[g].inst].err, ERR_SVD_NOT_CONVERGED);
+      }
+    }
   }
   atomicAdd(&s_n, c);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    *ly.active = s_n;
-    if (last && s_n > 0) atomicOr(err, ERR_SVD_NOT_CONVERGED);
-  }
+  if (threadIdx.x == 0) *ly.active = s_n;
 }
 
-__global__ __launch_bounds__(256) void k_big_finish(State st, Layer ly, int sv_cap, int rows_cap,
-                                                   int sweeps_run) {
+__global__ __launch_bounds__(256) void k_big_finish(Layer ly, int sweeps_run) {
   int g, bi;
-  big_block_of(ly, blockIdx.x, rows_cap, g, bi);
-  BlkDesc *Bp = ly.blk + (size_t)g * ly.max_blk + bi;
+  big_block_of(ly, blockIdx.x, g, bi);
+  const GateParam gp = ly.gates[g];
+  const State st = ly.states[gp.inst];
+  BlkDesc *Bp = ly.blk + gp.blk0 + bi;
   const BlkDesc B = *Bp;
   cd *A = ly.A + ly.base[g].e + B.eoff;
   extern __shared__ double s_sig[];
-  if (charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym) self_mirror_phase(st, ly, g, B, A, rows_cap);
-  sort_values(st, A, B.m, B.n, s_sig, ly.sv + (size_t)g * sv_cap + B.svoff,
-              ly.perm + (size_t)g * sv_cap + B.svoff);
+  if (charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym) self_mirror_phase(ly, gp, B, A);
+  sort_values(st.err, A, B.m, B.n, s_sig, ly.sv + gp.lst0 + B.svoff, ly.perm + gp.lst0 + B.svoff);
   if (threadIdx.x == 0) {
     const int done = ly.rotf[4 * (size_t)blockIdx.x + 3];
     Bp->sweeps = done ? done : sweeps_run;
@@ -795,42 +848,37 @@ int svd_lds_bytes() {
   return bytes;
 }
 
-hipError_t launch_svd_small(State st, Layer ly, hipStream_t s) {
+hipError_t launch_svd_small(Layer ly, hipStream_t s) {
   if (ly.total_blocks == 0) return hipSuccess;
-  const int cap = st.d * st.d * st.chi;
   const int lb = svd_lds_bytes();
-  hipLaunchKernelGGL(k_svd_small, dim3(ly.total_blocks), dim3(SVD_THREADS), (size_t)lb, s, st, ly,
-                     cap, cap);
+  hipLaunchKernelGGL(k_svd_small, dim3(ly.total_blocks), dim3(SVD_THREADS), (size_t)lb, s, ly);
   return hipGetLastError();
 }
 
-hipError_t launch_svd_big_prep(State st, Layer ly, hipStream_t s) {
+hipError_t launch_svd_big_prep(Layer ly, hipStream_t s) {
   if (ly.total_big == 0) return hipSuccess;
-  const int cap = st.d * st.d * st.chi;
-  hipLaunchKernelGGL(k_big_prep, dim3(ly.total_big), dim3(256), 0, s, st, ly, cap);
+  hipLaunchKernelGGL(k_big_prep, dim3(ly.total_big), dim3(256), 0, s, ly);
   return hipGetLastError();
 }
 
-hipError_t launch_svd_panel_round(State st, Layer ly, int round, int sweep, hipStream_t s) {
+hipError_t launch_svd_panel_round(Layer ly, int round, int sweep, hipStream_t s) {
   if (ly.total_big == 0) return hipSuccess;
-  const int cap = st.d * st.d * st.chi;
   const int lb = svd_lds_bytes();
   hipLaunchKernelGGL(k_panel, dim3(ly.maxpp / 2, ly.total_big), dim3(SVD_THREADS), (size_t)lb, s,
-                     st, ly, round, sweep, cap);
+                     ly, round, sweep);
   return hipGetLastError();
 }
 
-hipError_t launch_svd_count(State st, Layer ly, int sweep, hipStream_t s) {
+hipError_t launch_svd_count(Layer ly, int sweep, hipStream_t s) {
   hipLaunchKernelGGL(k_big_count, dim3(1), dim3(256), 0, s, ly, sweep,
-                     sweep == MAX_SWEEPS - 1 ? 1 : 0, st.err);
+                     sweep == MAX_SWEEPS - 1 ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_svd_big_finish(State st, Layer ly, int sweeps_run, hipStream_t s) {
+hipError_t launch_svd_big_finish(Layer ly, int sweeps_run, int max_chi, hipStream_t s) {
   if (ly.total_big == 0) return hipSuccess;
-  const int cap = st.d * st.d * st.chi;
-  hipLaunchKernelGGL(k_big_finish, dim3(ly.total_big), dim3(256), sizeof(double) * (size_t)st.chi,
-                     s, st, ly, cap, cap, sweeps_run);
+  hipLaunchKernelGGL(k_big_finish, dim3(ly.total_big), dim3(256), sizeof(double) * (size_t)max_chi,
+                     s, ly, sweeps_run);
   return hipGetLastError();
 }
 
@@ -848,16 +896,18 @@ __device__ inline int count_above(const double *sv, int n, double cut) {
   return lo;
 }
 
-__global__ __launch_bounds__(1024) void k_select(State st, Layer ly, int sv_cap) {
+__global__ __launch_bounds__(1024) void k_select(Layer ly) {
   const int g = blockIdx.x;
+  const GateParam gp = ly.gates[g];
+  const State st = ly.states[gp.inst];
   const int chi = st.chi;
-  const int j = ly.gates[g].site;
+  const int j = gp.site;
   const int nblk = ly.tot[g].nblk;
-  BlkDesc *blk = ly.blk + (size_t)g * ly.max_blk;
-  const double *sv = ly.sv + (size_t)g * sv_cap;
-  unsigned long long *uv = ly.uval + (size_t)g * sv_cap;
-  unsigned long long *uk = ly.ukey + (size_t)g * sv_cap;
-  int *us = ly.usize + (size_t)g * sv_cap;
+  BlkDesc *blk = ly.blk + gp.blk0;
+  const double *sv = ly.sv + gp.lst0;
+  unsigned long long *uv = ly.uval + gp.lst0;
+  unsigned long long *uk = ly.ukey + gp.lst0;
+  int *us = ly.usize + gp.lst0;
   __shared__ double s_max;
   __shared__ int s_iscan[17];
   if (threadIdx.x == 0) s_max = 0.0;
@@ -945,9 +995,8 @@ __global__ __launch_bounds__(1024) void k_select(State st, Layer ly, int sv_cap)
   if (threadIdx.x == 0) st.dim[j + 1] = min(nb, chi);
 }
 
-hipError_t launch_select(State st, Layer ly, hipStream_t s) {
-  const int sv_cap = st.d * st.d * st.chi;
-  hipLaunchKernelGGL(k_select, dim3(ly.ngates), dim3(1024), 0, s, st, ly, sv_cap);
+hipError_t launch_select(Layer ly, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(ly.ngates), dim3(1024), 0, s, ly);
   return hipGetLastError();
 }
 
@@ -965,9 +1014,11 @@ hipError_t launch_select(State st, Layer ly, hipStream_t s) {
 // indices and a self-mirror block is made exactly J-real:
 // x[y] <- (x[y] + conj(x[y~])) / 2.
 // ----------------------------------------------------------------------------
-__global__ void k_zero(State st, Layer ly) {
+__global__ void k_zero(Layer ly) {
   const int g = blockIdx.y;
-  const int j = ly.gates[g].site;
+  const GateParam gp = ly.gates[g];
+  const State st = ly.states[gp.inst];
+  const int j = gp.site;
   const size_t chi2 = (size_t)st.chi * st.chi;
   cd *G0 = st.gam + (size_t)j * chi2;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * chi2;
@@ -982,15 +1033,17 @@ __global__ void k_zero(State st, Layer ly) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_scatter(State st, Layer ly, int sv_cap, int rows_cap) {
+__global__ __launch_bounds__(256) void k_scatter(Layer ly) {
   const int flat = blockIdx.x;
   const int g = find_gate_blk(ly.base, ly.ngates, flat);
   const GateBase gb = ly.base[g];
-  const BlkDesc *blk = ly.blk + (size_t)g * ly.max_blk;
+  const GateParam gp = ly.gates[g];
+  const State st = ly.states[gp.inst];
+  const BlkDesc *blk = ly.blk + gp.blk0;
   const BlkDesc B = blk[flat - gb.blk];
   if (!B.comp || B.kq == 0) return;   // derived blocks are written by their canonical block
   const int chi = st.chi;
-  const int j = ly.gates[g].site;
+  const int j = gp.site;
   const bool sym = ly.tot[g].sym != 0;
   const int q0 = charge_n(B.q), q1 = charge_np(B.q);
   const bool selfm = sym && q0 == q1;
@@ -1000,12 +1053,12 @@ __global__ __launch_bounds__(256) void k_scatter(State st, Layer ly, int sv_cap,
   const int m = B.m, n = B.n;
   const cd *A = ly.A + gb.e + B.eoff;
   const cd *A0 = ly.A0 + gb.e + B.eoff;
-  const double *sv = ly.sv + (size_t)g * sv_cap + B.svoff;
-  const int *perm = ly.perm + (size_t)g * sv_cap + B.svoff;
-  const int *rows = ly.rows + (size_t)g * rows_cap + B.roff;
-  const int *cols = ly.cols + (size_t)g * rows_cap + B.coff;
-  const int *mL = ly.mirL + (size_t)g * chi;
-  const int *mR = ly.mirR + (size_t)g * chi;
+  const double *sv = ly.sv + gp.lst0 + B.svoff;
+  const int *perm = ly.perm + gp.lst0 + B.svoff;
+  const int *rows = ly.rows + gp.lst0 + B.roff;
+  const int *cols = ly.cols + gp.lst0 + B.coff;
+  const int *mL = ly.mirL + gp.mir0;
+  const int *mR = ly.mirR + gp.mir0;
   // operand rows y / columns x as bond indices, their mirror maps and weights
   const int *ly_ = !B.t ? rows : cols, *lx = !B.t ? cols : rows;
   const int *my = !B.t ? mL : mR, *mx = !B.t ? mR : mL;
@@ -1071,13 +1124,12 @@ __global__ __launch_bounds__(256) void k_scatter(State st, Layer ly, int sv_cap,
   }
 }
 
-hipError_t launch_scatter(State st, Layer ly, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero, dim3(64, ly.ngates), dim3(256), 0, s, st, ly);
+hipError_t launch_scatter(Layer ly, int max_chi, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero, dim3(64, ly.ngates), dim3(256), 0, s, ly);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ly.total_blocks == 0) return e;
-  const int sv_cap = st.d * st.d * st.chi;
-  hipLaunchKernelGGL(k_scatter, dim3(ly.total_blocks), dim3(256), sizeof(cd) * (size_t)st.chi, s,
-                     st, ly, sv_cap, sv_cap);
+  hipLaunchKernelGGL(k_scatter, dim3(ly.total_blocks), dim3(256), sizeof(cd) * (size_t)max_chi, s,
+                     ly);
   return hipGetLastError();
 }
 
@@ -1113,12 +1165,13 @@ __device__ inline void bond_entropy(State st, int b) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_entropy_layer(State st, Layer ly) {
-  bond_entropy(st, ly.gates[blockIdx.x].site + 1);
+__global__ __launch_bounds__(256) void k_entropy_layer(Layer ly) {
+  const GateParam gp = ly.gates[blockIdx.x];
+  bond_entropy(ly.states[gp.inst], gp.site + 1);
 }
 
-hipError_t launch_entropy_layer(State st, Layer ly, hipStream_t s) {
-  hipLaunchKernelGGL(k_entropy_layer, dim3(ly.ngates), dim3(256), 0, s, st, ly);
+hipError_t launch_entropy_layer(Layer ly, hipStream_t s) {
+  hipLaunchKernelGGL(k_entropy_layer, dim3(ly.ngates), dim3(256), 0, s, ly);
   return hipGetLastError();
 }
 

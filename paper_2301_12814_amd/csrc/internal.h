@@ -10,11 +10,15 @@
 
 namespace gbs {
 
-// One beam splitter of a layer.
+// One beam splitter of a batched layer.
 struct GateParam {
-  int site;       // acts on modes (site, site + 1)
-  int pad;
+  int site;        // acts on modes (site, site + 1)
+  int inst;        // instance (index into Layer::states)
   double theta, phi;
+  long long fock0; // first entry of the gate's Fock table
+  long long mir0;  // first entry of the gate's mirror maps (chi of the instance)
+  long long blk0;  // first block descriptor of the gate (set per chunk)
+  long long lst0;  // first entry of the gate's list regions (set per chunk)
 };
 
 // One charge sector Theta(q) of one gate (App. D, Eq. theta).
@@ -68,21 +72,21 @@ struct State {
   int *err;         // latched error bits
 };
 
-// Workspace of one layer of gates.
+// Workspace of one chunk of a batched layer: gates of one or many instances.
 struct Layer {
   int ngates;
+  const State *states;   // device table of instance states
   GateParam *gates;
   cd *fock;          // ngates x (2d-1) x d x d, [n][i1][j1]
-  BlkDesc *blk;      // ngates x max_blk, per-gate regions
-  int max_blk;
+  BlkDesc *blk;      // per-gate regions at GateParam::blk0
   int box_cap;       // largest admissible charge box per gate
   GateTot *tot;      // ngates
   GateBase *base;    // ngates
-  int *rows, *cols;  // per-gate row / column index lists
-  int *mirL, *mirR;  // per gate: mirror index on the left / right bond, -1 if none
+  int *rows, *cols;  // per-gate row / column index lists (at lst0)
+  int *mirL, *mirR;  // per gate: mirror index on the left / right bond, -1 if none (at mir0)
   cd *A;             // sector operands (overwritten by U * Sigma)
   cd *A0;            // pristine copies of the operands (right-vector recovery)
-  int *bigl;         // per gate: local indices of its big blocks
+  int *bigl;         // per gate: local indices of its big blocks (at lst0)
   int *rotf;         // per big block: rotation flags of the two latest sweeps
   int *active;       // big blocks still rotating after the latest checked sweep
   int total_big;     // big blocks in the layer
@@ -109,25 +113,27 @@ hipError_t launch_init_select(State st, const double *w, const long long *woff,
                               hipStream_t s);
 hipError_t launch_init_gamma(State st, const double *rho, const double *A, hipStream_t s);
 
-// one layer
-hipError_t launch_fock(Layer ly, int d, hipStream_t s);
-hipError_t launch_plan(State st, Layer ly, hipStream_t s);
-hipError_t launch_lists(State st, Layer ly, hipStream_t s);
-hipError_t launch_contract(State st, Layer ly, hipStream_t s);
-hipError_t launch_svd_small(State st, Layer ly, hipStream_t s);
-hipError_t launch_svd_big_prep(State st, Layer ly, hipStream_t s);
-hipError_t launch_svd_panel_round(State st, Layer ly, int round, int sweep, hipStream_t s);
-hipError_t launch_svd_count(State st, Layer ly, int sweep, hipStream_t s);
-hipError_t launch_svd_big_finish(State st, Layer ly, int sweeps_run, hipStream_t s);
+// one batched layer (chunk)
+hipError_t launch_fock(Layer ly, hipStream_t s);
+hipError_t launch_plan_count(Layer ly, hipStream_t s);
+hipError_t launch_plan_fill(Layer ly, hipStream_t s);
+hipError_t launch_contract(Layer ly, hipStream_t s);
+hipError_t launch_svd_small(Layer ly, hipStream_t s);
+hipError_t launch_svd_big_prep(Layer ly, hipStream_t s);
+hipError_t launch_svd_panel_round(Layer ly, int round, int sweep, hipStream_t s);
+hipError_t launch_svd_count(Layer ly, int sweep, hipStream_t s);
+hipError_t launch_svd_big_finish(Layer ly, int sweeps_run, int max_chi, hipStream_t s);
+hipError_t launch_select(Layer ly, hipStream_t s);
+hipError_t launch_scatter(Layer ly, int max_chi, hipStream_t s);
+hipError_t launch_entropy_layer(Layer ly, hipStream_t s);
 int svd_lds_bytes();
-hipError_t launch_select(State st, Layer ly, hipStream_t s);
-hipError_t launch_scatter(State st, Layer ly, hipStream_t s);
-hipError_t launch_entropy_layer(State st, Layer ly, hipStream_t s);
+size_t svd_small_need(int m, int n);
 
 // readouts
 hipError_t launch_entropy_all(State st, hipStream_t s);
 hipError_t launch_phases(State st, const double *phase, hipStream_t s);
-hipError_t launch_marginals(State st, cd *envL, cd *envR, double *P, double *trace,
-                            hipStream_t s);
+size_t marginals_scratch(int M, int d, int chi);   // doubles
+hipError_t launch_marginals(State st, cd *envL, cd *envR, double *part, double *P,
+                            double *trace, hipStream_t s);
 
 }  // namespace gbs

@@ -62,19 +62,18 @@ __global__ __launch_bounds__(256) void k_env_left(State st, int j, cd *L) {
   L[(size_t)(j + 1) * chi + b] = acc;
 }
 
-__global__ void k_env_init(State st, cd *L, cd *E, double *P) {
+__global__ void k_env_init(State st, cd *L, cd *E) {
   const int chi = st.chi;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < chi; i += gridDim.x * blockDim.x) {
     L[i] = cmk(1.0, 0.0);
     E[(size_t)st.M * chi + i] = cmk(i == 0 ? 1.0 : 0.0, 0.0);
   }
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < st.M * st.d;
-       i += gridDim.x * blockDim.x)
-    P[i] = 0.0;
 }
 
-// one wavefront per row a of site j = blockIdx.y
-__global__ __launch_bounds__(256) void k_marg(State st, const cd *L, const cd *E, double *P) {
+// one wavefront per row a of site j = blockIdx.y; each workgroup writes its
+// per-n partial sums to part[(j * gridDim.x + blockIdx.x) * d + n] (summed in a
+// fixed order by k_marg_reduce, so the result does not depend on scheduling)
+__global__ __launch_bounds__(256) void k_marg(State st, const cd *L, const cd *E, double *part) {
   const int chi = st.chi, d = st.d;
   const int j = blockIdx.y;
   const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -105,7 +104,17 @@ __global__ __launch_bounds__(256) void k_marg(State st, const cd *L, const cd *E
   if (threadIdx.x < d) {
     const double v = s_bin[0][threadIdx.x] + s_bin[1][threadIdx.x] + s_bin[2][threadIdx.x] +
                      s_bin[3][threadIdx.x];
-    if (v != 0.0) atomicAdd(&P[j * d + threadIdx.x], v);
+    part[((size_t)j * gridDim.x + blockIdx.x) * d + threadIdx.x] = v;
+  }
+}
+
+// P[j][n] = sum over the row groups of site j, in order.
+__global__ void k_marg_reduce(State st, const double *part, int nx, double *P) {
+  const int j = blockIdx.x, d = st.d;
+  for (int n = threadIdx.x; n < d; n += blockDim.x) {
+    double acc = 0.0;
+    for (int x = 0; x < nx; ++x) acc += part[((size_t)j * nx + x) * d + n];
+    P[j * d + n] = acc;
   }
 }
 
@@ -119,15 +128,19 @@ __global__ void k_trace(State st, const cd *E, double *trace) {
   if (threadIdx.x == 0) *trace = s[0] + s[1] + s[2] + s[3];
 }
 
-hipError_t launch_marginals(State st, cd *envL, cd *envR, double *P, double *trace,
-                            hipStream_t s) {
+size_t marginals_scratch(int M, int d, int chi) { return (size_t)M * d * ((chi + 3) / 4); }
+
+hipError_t launch_marginals(State st, cd *envL, cd *envR, double *part, double *P,
+                            double *trace, hipStream_t s) {
   const int chi = st.chi;
-  hipLaunchKernelGGL(k_env_init, dim3((chi + 255) / 256), dim3(256), 0, s, st, envL, envR, P);
+  const int nx = (chi + 3) / 4;
+  hipLaunchKernelGGL(k_env_init, dim3((chi + 255) / 256), dim3(256), 0, s, st, envL, envR);
   for (int j = st.M - 1; j >= 0; --j)
     hipLaunchKernelGGL(k_env_right, dim3((chi + 3) / 4), dim3(256), 0, s, st, j, envR);
   for (int j = 0; j < st.M; ++j)
     hipLaunchKernelGGL(k_env_left, dim3((chi + 255) / 256), dim3(256), 0, s, st, j, envL);
-  hipLaunchKernelGGL(k_marg, dim3((chi + 3) / 4, st.M), dim3(256), 0, s, st, envL, envR, P);
+  hipLaunchKernelGGL(k_marg, dim3(nx, st.M), dim3(256), 0, s, st, envL, envR, part);
+  hipLaunchKernelGGL(k_marg_reduce, dim3(st.M), dim3(64), 0, s, st, part, nx, P);
   hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, s, st, envR, trace);
   return hipGetLastError();
 }

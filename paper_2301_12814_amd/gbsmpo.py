@@ -54,6 +54,22 @@ def lib() -> ctypes.CDLL:
         L.mpo_set_profiling.argtypes = [c_void_p, c_int]
         L.mpo_get_profile.argtypes = [c_void_p, pd, pll, pd]
         L.mpo_layer_blocks.argtypes = [c_void_p, c_int, pi]
+        pe = ctypes.POINTER(c_void_p)
+        L.mpo_engine_projected_bytes.argtypes = [c_int, c_int, c_int]
+        L.mpo_engine_projected_bytes.restype = ctypes.c_longlong
+        L.mpo_engine_create.argtypes = [c_void_p, c_int, ctypes.c_longlong, pe]
+        L.mpo_engine_free.argtypes = [c_void_p]
+        L.mpo_engine_free.restype = None
+        L.mpo_engine_add.argtypes = [c_void_p, c_int, pd, c_double, c_int, c_int, pd, pi]
+        L.mpo_engine_step.argtypes = [c_void_p, pi]
+        L.mpo_engine_result.argtypes = [c_void_p, c_int, pi, pd, pd, pd]
+        L.mpo_engine_release.argtypes = [c_void_p, c_int]
+        L.mpo_engine_set_profiling.argtypes = [c_void_p, c_int]
+        L.mpo_engine_get_profile.argtypes = [c_void_p, pd, pll, pd]
+        for name in ("mpo_engine_create", "mpo_engine_add", "mpo_engine_step",
+                     "mpo_engine_result", "mpo_engine_release", "mpo_engine_set_profiling",
+                     "mpo_engine_get_profile"):
+            getattr(L, name).restype = c_int
         for name in ("mpo_layer_blocks", "mpo_set_profiling", "mpo_get_profile", "mpo_init_lossy_squeezed", "mpo_apply_bs_layer", "mpo_apply_phases",
                      "mpo_entropy", "mpo_photon_marginals", "mpo_sync", "mpo_get_bond",
                      "mpo_get_site", "mpo_layer_stats", "gbs_clements_decompose"):
@@ -200,4 +216,84 @@ class MPO:
                                      n.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
                                      _dp(work)))
         return (dict(zip(self.PHASES, ms.tolist())), dict(zip(self.PHASES, n.tolist())),
+                dict(svd_flops=work[0], elements=work[1], candidates=work[2], layers=work[3]))
+
+
+def projected_bytes(M, d, chi) -> int:
+    """Device bytes a simulation is admitted against (state + its workspace share)."""
+    return int(lib().mpo_engine_projected_bytes(int(M), int(d), int(chi)))
+
+
+class Engine:
+    """Continuous-batching engine: every step applies the next beam-splitter
+    layer of every running simulation in one batched launch sequence."""
+
+    def __init__(self, precision=MPO_FP64, budget_bytes=0, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().mpo_engine_create(_stream_handle(stream), int(precision),
+                                       int(budget_bytes), ctypes.byref(h)))
+        self._h = h
+        self.meta = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().mpo_engine_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def add(self, M, r, eta, d, chi, U):
+        """Admit a simulation (raises GbsMpoError MPO_ENOMEM if it does not fit)."""
+        r = np.ascontiguousarray(np.broadcast_to(np.asarray(r, dtype=float), (M,)))
+        U = np.ascontiguousarray(U, dtype=complex)
+        ure = np.ascontiguousarray(np.stack([U.real, U.imag], axis=-1).reshape(-1))
+        sid = ctypes.c_int()
+        _check(lib().mpo_engine_add(self._h, int(M), _dp(r), float(eta), int(d), int(chi),
+                                    _dp(ure), ctypes.byref(sid)))
+        self.meta[sid.value] = (int(M), int(d))
+        return sid.value
+
+    def step(self):
+        n = ctypes.c_int()
+        _check(lib().mpo_engine_step(self._h, ctypes.byref(n)))
+        return n.value
+
+    def result(self, sid):
+        """None while running, else dict(S_max, trace, P)."""
+        M, d = self.meta[sid]
+        done = ctypes.c_int()
+        smax = ctypes.c_double()
+        tr = ctypes.c_double()
+        P = np.zeros(M * d)
+        _check(lib().mpo_engine_result(self._h, int(sid), ctypes.byref(done), ctypes.byref(smax),
+                                       ctypes.byref(tr), _dp(P)))
+        if not done.value:
+            return None
+        return {"S_max": smax.value, "trace": tr.value, "P": P.reshape(M, d)}
+
+    def release(self, sid):
+        _check(lib().mpo_engine_release(self._h, int(sid)))
+        self.meta.pop(sid, None)
+
+    def set_profiling(self, on=True):
+        _check(lib().mpo_engine_set_profiling(self._h, 1 if on else 0))
+
+    def profile(self):
+        ms = np.zeros(8)
+        n = np.zeros(8, dtype=np.int64)
+        work = np.zeros(4)
+        _check(lib().mpo_engine_get_profile(self._h, _dp(ms),
+                                            n.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
+                                            _dp(work)))
+        return (dict(zip(MPO.PHASES, ms.tolist())), dict(zip(MPO.PHASES, n.tolist())),
                 dict(svd_flops=work[0], elements=work[1], candidates=work[2], layers=work[3]))

@@ -63,3 +63,28 @@ def batch_workloads(n: int = 256, base_seed: int = 1000):
         chi = int(rng.choice([64, 128, 256, 512]))
         out.append(Workload(f"batch{i}", M, [r] * M, eta, d, chi, base_seed + i))
     return out
+
+
+LARGE_REQUEST = dict(M=96, r=1.0, eta=0.25, d=10, chi=1024)
+
+
+def serving_requests(n: int, rate: float, seed: int = 5, p_large: float = 0.05,
+                     base_seed: int = 5000):
+    """Poisson request stream: exponential inter-arrival times at `rate`
+    requests/s; each request follows the batched-instance law (Haar seed
+    base_seed + i) or, with probability p_large, is the large request
+    M=96, r=1.0, eta=0.25, d=10, chi=1024.  Returns [(arrival_s, Workload)]."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += float(rng.exponential(1.0 / rate))
+        if rng.uniform() < p_large:
+            L = LARGE_REQUEST
+            w = Workload(f"req{i}-large", L["M"], [L["r"]] * L["M"], L["eta"], L["d"], L["chi"],
+                         base_seed + i)
+        else:
+            w = batch_workloads(1, base_seed + i)[0]
+            w.name = f"req{i}"
+        out.append((t, w))
+    return out

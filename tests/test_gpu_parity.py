@@ -228,3 +228,55 @@ def test_gpu_edge_cases():
         gbsmpo.MPO(4, 0.5, 1.5, 4, 8)                             # eta > 1
     with pytest.raises(gbsmpo.GbsMpoError):
         gbsmpo.MPO(4, -0.1, 0.5, 4, 8)                            # r < 0
+
+
+def _batch_specs():
+    specs = []
+    for i, (M, r, eta, d, chi) in enumerate([(6, 0.6, 0.5, 4, 16), (8, 0.5, 0.5, 4, 32),
+                                              (5, 0.9, 0.4, 5, 24), (10, 0.7, 0.3, 4, 16),
+                                              (7, 0.4, 0.6, 6, 20)]):
+        specs.append((M, r, eta, d, chi, inputs.haar_unitary(M, 50 + i)))
+    return specs
+
+
+def test_gpu_engine_same_alone_and_in_the_mix():
+    """Continuous batching: every simulation's results are bitwise the same
+    run alone (single-simulation API) and run inside a batch whose members
+    join at different steps and have different M, d and chi."""
+    specs = _batch_specs()
+    alone = []
+    for (M, r, eta, d, chi, U) in specs:
+        layers, _ = gbsmpo.clements(U)
+        with gbsmpo.MPO(M, r, eta, d, chi) as g:
+            for L in layers:
+                g.apply_layer(*L)
+            _, smax = g.entropy()
+            P, tr = g.marginals()
+        alone.append((smax, tr, P))
+    with gbsmpo.Engine() as eng:
+        ids = {}
+        pending = list(range(len(specs)))
+        step = 0
+        while pending or any(eng.result(s) is None for s in ids.values()):
+            if pending and step % 2 == 0:          # a new request every other step
+                k = pending.pop(0)
+                M, r, eta, d, chi, U = specs[k]
+                ids[k] = eng.add(M, r, eta, d, chi, U)
+            eng.step()
+            step += 1
+            assert step < 200
+        for k, sid in ids.items():
+            res = eng.result(sid)
+            smax, tr, P = alone[k]
+            assert res["S_max"] == smax, (k, res["S_max"], smax)
+            assert res["trace"] == tr, (k, res["trace"], tr)
+            assert np.array_equal(res["P"], P), k
+
+
+def test_gpu_engine_admission_refuses_oversized_request():
+    U = inputs.haar_unitary(8, 1)
+    with gbsmpo.Engine(budget_bytes=gbsmpo.projected_bytes(8, 4, 32) + 1000) as eng:
+        eng.add(8, 0.5, 0.5, 4, 32, U)
+        with pytest.raises(gbsmpo.GbsMpoError) as ei:
+            eng.add(8, 0.5, 0.5, 4, 32, U)
+        assert ei.value.code == gbsmpo.MPO_ENOMEM
