@@ -164,6 +164,15 @@ int mpo_get_profile(gbs_mpo *h, double *phase_ms, long long *phase_launches, dou
  */
 int mpo_layer_blocks(gbs_mpo *h, int max_blocks, int *out);
 
+/* Process-wide routing of the block SVDs (App. D: every charge block is
+ * SVD'd; these knobs only choose which kernels do it, the results agree to
+ * rounding).  lds_limit_bytes > 0 lowers the LDS budget below the device's:
+ * a block whose Jacobi operand exceeds it takes the multi-workgroup panel
+ * rounds, and a block exceeding it with at least 1.2x more rows than columns
+ * is first reduced by a Householder QR when qr_enable != 0.  0 restores the
+ * device budget.  Affects layers planned after the call; not thread-safe. */
+int gbs_set_svd_route(int lds_limit_bytes, int qr_enable);
+
 /* Releases every device allocation of the handle (NULL is a no-op). */
 void mpo_free(gbs_mpo *h);
 

@@ -129,7 +129,7 @@ struct Engine {
   DBuf<int> d_rows, d_cols, d_bigl, d_perm, d_usize;
   DBuf<double> d_sv;
   DBuf<unsigned long long> d_uval, d_ukey;
-  DBuf<cd> d_A, d_A0;
+  DBuf<cd> d_A, d_A0, d_R, d_U, d_tau;
   DBuf<int> d_rotf;
   DBuf<int> d_active;
   DBuf<int> d_eng_err;
@@ -266,6 +266,9 @@ void engine_destroy(Engine &E) {
   E.d_ukey.release();
   E.d_A.release();
   E.d_A0.release();
+  E.d_R.release();
+  E.d_U.release();
+  E.d_tau.release();
   E.d_rotf.release();
   E.d_active.release();
   E.d_eng_err.release();
@@ -288,14 +291,14 @@ hipError_t ialloc(Instance &I, T **p, size_t count) {
 
 // Projected device bytes of one simulation: the state, its readout scratch,
 // and the larger of the one-off initial-state scratch and its share of the
-// per-layer sector workspace (operand + pristine copy, about 2.5 chi^2
-// elements per gate, plus the per-gate lists).
+// per-layer sector workspace (operand, pristine copy, left vectors and R
+// factors: about 2.5 chi^2 elements per gate for each, plus the per-gate lists).
 long long projected_bytes(int M, int d, int chi) {
   const long long W0 = (long long)M * (d - 1) + 1;
   const long long state = (long long)M * chi * chi * 16 + (long long)(M + 1) * chi * 60 +
                           (long long)M * d * ((chi + 3) / 4) * 8;
   const long long init = (long long)(M + 1) * W0 * W0 * 28;
-  const long long layer = (long long)(M / 2) * (long long)(2.5 * chi * chi) * 32 +
+  const long long layer = (long long)(M / 2) * (long long)(2.5 * chi * chi) * 56 +
                           (long long)(M / 2) * d * d * chi * 48;
   return state + std::max(init, layer);
 }
@@ -555,12 +558,12 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
   while (c0 < n) {
     int c1 = c0;
     long long el = 0;
-    while (c1 < n && (c1 == c0 || el + E.h_tot[c1].elems <= E.pool_budget)) {
-      el += E.h_tot[c1].elems;
+    while (c1 < n && (c1 == c0 || el + E.h_tot[c1].elems + E.h_tot[c1].relems <= E.pool_budget)) {
+      el += E.h_tot[c1].elems + E.h_tot[c1].relems;
       ++c1;
     }
     const int ng = c1 - c0;
-    long long e = 0, ch = 0, blk0 = 0, lst0 = 0;
+    long long e = 0, ch = 0, blk0 = 0, lst0 = 0, re = 0;
     int blkb = 0, bigb = 0, maxpp = 0;
     for (int g = c0; g < c1; ++g) {
       const GateTot &t = E.h_tot[g];
@@ -569,8 +572,9 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
       gp.lst0 = lst0;
       blk0 += std::max(t.nblk, 1);
       lst0 += std::max(std::max(t.rows, t.cols), std::max(t.sv, 1));
-      E.h_base[g - c0] = GateBase{e, blkb, bigb, ch};
+      E.h_base[g - c0] = GateBase{e, blkb, bigb, ch, re};
       e += t.elems;
+      re += t.relems;
       ch += t.chunks;
       blkb += t.nblk;
       bigb += t.nbig;
@@ -587,6 +591,9 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     HIPCHK(E.d_ukey.ensure(lst0));
     HIPCHK(E.d_A.ensure(std::max(e, 1LL), (size_t)E.pool_budget));
     HIPCHK(E.d_A0.ensure(std::max(e, 1LL), (size_t)E.pool_budget));
+    HIPCHK(E.d_U.ensure(std::max(e, 1LL), (size_t)E.pool_budget));
+    HIPCHK(E.d_R.ensure(std::max(re, 1LL), (size_t)E.pool_budget));
+    HIPCHK(E.d_tau.ensure(lst0));
     HIPCHK(E.d_rotf.ensure((size_t)4 * std::max(bigb, 1)));
     if (bigb > 65535 || maxpp / 2 > 65535)
       return fail(MPO_EINVAL, "too many large sectors in one layer chunk");
@@ -610,6 +617,9 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     C.ukey = E.d_ukey.p;
     C.A = E.d_A.p;
     C.A0 = E.d_A0.p;
+    C.R = E.d_R.p;
+    C.U = E.d_U.p;
+    C.tau = E.d_tau.p;
     C.rotf = E.d_rotf.p;
     C.active = E.d_active.p;
     C.total_chunks = ch;
@@ -627,6 +637,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     int sweeps_run = 0;
     {
       PhaseMark pm(E, 3);
+      HIPCHK(launch_qr(C, max_chi, E.stream));
       HIPCHK(launch_svd_small(C, E.stream));
       if (bigb > 0) {
         // panel rounds of the big blocks; convergence is read back every 3 sweeps
@@ -653,6 +664,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     }
     {
       PhaseMark pm(E, 5);
+      HIPCHK(launch_leftvec(C, E.stream));
       HIPCHK(launch_scatter(C, max_chi, E.stream));
     }
     {
@@ -736,6 +748,12 @@ bool valid_layer(int M, int n_gates, const int *left_site, const double *theta,
 // single-simulation C ABI
 // ============================================================================
 extern "C" const char *mpo_last_error(void) { return g_err.c_str(); }
+
+extern "C" int gbs_set_svd_route(int lds_limit_bytes, int qr_enable) {
+  if (lds_limit_bytes < 0) return fail(MPO_EINVAL, "LDS limit must be >= 0");
+  set_svd_route(lds_limit_bytes, qr_enable);
+  return MPO_OK;
+}
 
 extern "C" void mpo_free(gbs_mpo *h) {
   if (!h) return;

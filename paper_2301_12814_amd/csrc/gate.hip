@@ -105,6 +105,22 @@ __host__ __device__ inline int panel_width(int m, int lds_bytes) {
   return w;
 }
 
+// Route of a computed block's SVD.  A block whose operand does not fit in LDS
+// and has at least 1.2x more rows than columns is first reduced by a
+// Householder QR (A = Q R, the Jacobi then rotates the n x n factor R: the
+// work per sweep drops by m / n); the Jacobi runs in one workgroup from LDS
+// when its operand fits there, otherwise as multi-workgroup panel rounds.
+__host__ __device__ inline void svd_route(int m, int n, int lds_bytes, int qr_ok, int &qr,
+                                          int &big, int &mj) {
+  qr = 0;
+  mj = m;
+  if (qr_ok && svd_small_need(m, n) > (size_t)lds_bytes && 5LL * m >= 6LL * n) {
+    qr = 1;
+    mj = n;
+  }
+  big = svd_small_need(mj, n) > (size_t)lds_bytes ? 1 : 0;
+}
+
 // Two passes over the charge box of every gate.  The count pass (FILL =
 // false) builds the mirror maps, decides whether the gate may use Hermiticity
 // and totals the sizes the fill pass needs; the host then places every gate's
@@ -113,7 +129,7 @@ __host__ __device__ inline int panel_width(int m, int lds_bytes) {
 // is derived from its mirror (its mirror exists because both outer bonds are
 // mirror symmetric).
 template <bool FILL>
-__global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes) {
+__global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int lds_alloc, int qr_ok) {
   const int g = blockIdx.x;
   const GateParam gp = ly.gates[g];
   const State st = ly.states[gp.inst];
@@ -200,7 +216,7 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes) {
   }
   BlkDesc *blk = ly.blk + gp.blk0;
   // pass 1: the non-empty blocks in charge order (counted, or compacted)
-  long long nb = 0, eb = 0;
+  long long nb = 0, eb = 0, reb = 0;
   int svb = 0, rb = 0, cb = 0, chb = 0, bgb = 0, maxr = 0, maxc = 0, maxpp = 0;
   double fl = 0.0;
   for (long long c0 = 0; c0 < area; c0 += blockDim.x) {
@@ -229,9 +245,13 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes) {
           svb += n;
           chb += (int)(((long long)r * s + CHUNK - 1) / CHUNK);
           fl += 16.0 * m * (double)n * n + 36.0 * (double)n * n * n;
-          if (svd_small_need(m, n) > (size_t)lds_bytes) {
+          int qr, big, mj;
+          svd_route(m, n, lds_bytes, qr_ok, qr, big, mj);
+          if (qr) reb += (long long)n * n;
+          if (big && 2LL * mj * (long long)sizeof(cd) > lds_alloc) atomicOr(st.err, ERR_WORKSPACE);
+          if (big) {
             ++bgb;
-            const int w = panel_width(m, lds_bytes);
+            const int w = panel_width(mj, lds_bytes);
             const int np = (n + w - 1) / w;
             maxpp = max(maxpp, np + (np & 1));
           }
@@ -257,16 +277,17 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes) {
   }
   if (!FILL) {
     // block-wide totals
-    __shared__ long long s_nb, s_eb;
+    __shared__ long long s_nb, s_eb, s_re;
     __shared__ int s_sv, s_rb, s_cb, s_ch, s_bg, s_mr, s_mc, s_pp;
     __shared__ double s_fl;
     if (threadIdx.x == 0) {
-      s_nb = 0; s_eb = 0; s_sv = 0; s_rb = 0; s_cb = 0; s_ch = 0; s_bg = 0; s_mr = 0; s_mc = 0;
+      s_nb = 0; s_eb = 0; s_re = 0; s_sv = 0; s_rb = 0; s_cb = 0; s_ch = 0; s_bg = 0; s_mr = 0; s_mc = 0;
       s_pp = 0; s_fl = 0.0;
     }
     __syncthreads();
     atomicAdd((unsigned long long *)&s_nb, (unsigned long long)nb);
     atomicAdd((unsigned long long *)&s_eb, (unsigned long long)eb);
+    atomicAdd((unsigned long long *)&s_re, (unsigned long long)reb);
     atomicAdd(&s_sv, svb);
     atomicAdd(&s_rb, rb);
     atomicAdd(&s_cb, cb);
@@ -285,6 +306,7 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes) {
       tot.maxr = s_mr;
       tot.maxc = s_mc;
       tot.elems = s_eb;
+      tot.relems = s_re;
       tot.chunks = s_ch;
       tot.nbig = s_bg;
       tot.maxpp = s_pp;
@@ -311,29 +333,32 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes) {
   // pass 2: offsets; each computed block goes either to the one-workgroup LDS
   // Jacobi (operand fits in LDS) or to the multi-workgroup panel rounds
   int *bigl = ly.bigl + gp.lst0;
-  eb = 0; svb = 0; rb = 0; cb = 0; chb = 0; bgb = 0;
+  eb = 0; reb = 0; svb = 0; rb = 0; cb = 0; chb = 0; bgb = 0;
   for (int b0 = 0; b0 < nblk; b0 += blockDim.x) {
     const int bi = b0 + threadIdx.x;
-    long long e = 0;
-    int sv = 0, r = 0, c = 0, ch = 0, bg = 0, w = 0, npan = 0;
+    long long e = 0, re = 0;
+    int sv = 0, r = 0, c = 0, ch = 0, bg = 0, w = 0, npan = 0, qr = 0, mj = 0;
     if (bi < nblk) {
       const BlkDesc &B = blk[bi];
+      mj = B.m;
       if (B.comp) {
         e = (long long)B.r * B.s;
         sv = B.n;
         ch = (int)((e + CHUNK - 1) / CHUNK);
-        if (svd_small_need(B.m, B.n) > (size_t)lds_bytes) {
-          bg = 1;
-          w = panel_width(B.m, lds_bytes);
+        svd_route(B.m, B.n, lds_bytes, qr_ok, qr, bg, mj);
+        if (qr) re = (long long)B.n * B.n;
+        if (bg) {
+          w = panel_width(mj, lds_bytes);
           npan = (B.n + w - 1) / w;
         }
       }
       r = B.r;
       c = B.s;
     }
-    long long te;
+    long long te, tre;
     int tsv, tr, tc, tch, tbg;
     const long long pe = eb + block_exclusive_scan<long long>(e, s_scan, te);
+    const long long pre = reb + block_exclusive_scan<long long>(re, s_scan, tre);
     const int psv = svb + block_exclusive_scan<int>(sv, s_iscan, tsv);
     const int pr = rb + block_exclusive_scan<int>(r, s_iscan, tr);
     const int pc = cb + block_exclusive_scan<int>(c, s_iscan, tc);
@@ -350,10 +375,13 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes) {
       B.w = w;
       B.npan = npan;
       B.bigi = bg ? pbg : -1;
+      B.qr = qr;
+      B.mj = mj;
+      B.joff = pre;
       B.sweeps = 0;
       if (bg) bigl[pbg] = bi;
     }
-    eb += te; svb += tsv; rb += tr; cb += tc; chb += tch; bgb += tbg;
+    eb += te; reb += tre; svb += tsv; rb += tr; cb += tc; chb += tch; bgb += tbg;
   }
   __syncthreads();
   // pass 3: row / column index lists (ascending)
@@ -377,13 +405,31 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes) {
   }
 }
 
+// Routing knobs (process-wide): an LDS budget below the device's for the
+// one-workgroup Jacobi and the panel width, and whether rectangular large
+// blocks are QR-reduced first.  They change only which kernels a block takes.
+static int g_route_lds = 0;
+static int g_qr_enable = 1;
+
+void set_svd_route(int lds_limit_bytes, int qr_enable) {
+  g_route_lds = lds_limit_bytes > 0 ? lds_limit_bytes : 0;
+  g_qr_enable = qr_enable ? 1 : 0;
+}
+
+static int svd_route_bytes() {
+  const int a = svd_lds_bytes();
+  return g_route_lds > 0 && g_route_lds < a ? g_route_lds : a;
+}
+
 hipError_t launch_plan_count(Layer ly, hipStream_t s) {
-  hipLaunchKernelGGL(k_plan<false>, dim3(ly.ngates), dim3(1024), 0, s, ly, svd_lds_bytes());
+  hipLaunchKernelGGL(k_plan<false>, dim3(ly.ngates), dim3(1024), 0, s, ly, svd_route_bytes(),
+                     svd_lds_bytes(), g_qr_enable);
   return hipGetLastError();
 }
 
 hipError_t launch_plan_fill(Layer ly, hipStream_t s) {
-  hipLaunchKernelGGL(k_plan<true>, dim3(ly.ngates), dim3(1024), 0, s, ly, svd_lds_bytes());
+  hipLaunchKernelGGL(k_plan<true>, dim3(ly.ngates), dim3(1024), 0, s, ly, svd_route_bytes(),
+                     svd_lds_bytes(), g_qr_enable);
   return hipGetLastError();
 }
 
@@ -487,6 +533,99 @@ hipError_t launch_contract(Layer ly, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------------------
+// Householder QR of the rectangular large blocks: A = Q R with
+// Q = H_0 H_1 ... H_{n-1}, H_k = I - tau_k v_k v_k^H, v_k[0] = 1.  For the
+// column x below the diagonal, beta = -sign(Re x_0) |x|, tau = (beta - x_0) /
+// beta and v = x / (x_0 - beta) give H_k^H x = beta e_1 with beta real; the
+// trailing columns are multiplied by H_k^H.  One workgroup per block; the
+// reflectors stay below the diagonal of the operand, R (upper triangle, zeros
+// below) is copied to the R pool where the Jacobi rotates it.
+// ----------------------------------------------------------------------------
+constexpr int QR_THREADS = 512;
+
+__device__ __forceinline__ double block_sum(double v, double *s_red);
+
+__global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly) {
+  const int flat = blockIdx.x;
+  const int g = find_gate_blk(ly.base, ly.ngates, flat);
+  const GateBase gb = ly.base[g];
+  const GateParam gp = ly.gates[g];
+  const BlkDesc B = ly.blk[gp.blk0 + (flat - gb.blk)];
+  if (!B.comp || !B.qr) return;
+  const int m = B.m, n = B.n;
+  cd *A = ly.A + gb.e + B.eoff;
+  cd *tau = ly.tau + gp.lst0 + B.svoff;
+  extern __shared__ double s_dyn[];
+  cd *v = reinterpret_cast<cd *>(s_dyn);   // the current reflector, m - k entries
+  __shared__ double s_red[16];
+  __shared__ cd s_tau, s_scale;
+  __shared__ int s_skip;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int k = 0; k < n; ++k) {
+    cd *x = A + (size_t)k * m + k;
+    const int len = m - k;
+    double s2 = 0.0;
+    for (int y = 1 + threadIdx.x; y < len; y += blockDim.x) s2 += cabs2(x[y]);
+    s2 = block_sum(s2, s_red);
+    if (threadIdx.x == 0) {
+      const cd al = x[0];
+      if (s2 == 0.0 && al.im == 0.0) {
+        s_skip = 1;
+        tau[k] = cmk(0.0, 0.0);
+      } else {
+        const double nrm = sqrt(al.re * al.re + al.im * al.im + s2);
+        const double beta = al.re >= 0.0 ? -nrm : nrm;
+        const cd t = cmk((beta - al.re) / beta, -al.im / beta);
+        const cd dn = cmk(al.re - beta, al.im);
+        const double dd = cabs2(dn);
+        s_tau = t;
+        s_scale = cmk(dn.re / dd, -dn.im / dd);
+        tau[k] = t;
+        x[0] = cmk(beta, 0.0);
+        s_skip = 0;
+      }
+    }
+    __syncthreads();
+    if (s_skip) continue;
+    const cd sc = s_scale;
+    for (int y = 1 + threadIdx.x; y < len; y += blockDim.x) {
+      const cd t = cmul(x[y], sc);
+      x[y] = t;
+      v[y] = t;
+    }
+    if (threadIdx.x == 0) v[0] = cmk(1.0, 0.0);
+    __syncthreads();
+    const cd ct = cconj(s_tau);
+    for (int j = k + 1 + wave; j < n; j += nw) {
+      cd *a = A + (size_t)j * m + k;
+      double wr = 0.0, wi = 0.0;
+      for (int y = lane; y < len; y += 64) {
+        const cd p = cmulc(v[y], a[y]);
+        wr += p.re;
+        wi += p.im;
+      }
+      wr = wave_sum(wr);
+      wi = wave_sum(wi);
+      const cd f = cmul(ct, cmk(wr, wi));    // conj(tau) v^H a
+      for (int y = lane; y < len; y += 64) a[y] = csub(a[y], cmul(f, v[y]));
+    }
+    __syncthreads();
+  }
+  cd *R = ly.R + gb.r + B.joff;
+  for (long long idx = threadIdx.x; idx < (long long)n * n; idx += blockDim.x) {
+    const int c = (int)(idx / n), i = (int)(idx % n);
+    R[idx] = i <= c ? A[(size_t)c * m + i] : cmk(0.0, 0.0);
+  }
+}
+
+hipError_t launch_qr(Layer ly, int max_chi, hipStream_t s) {
+  if (ly.total_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_qr, dim3(ly.total_blocks), dim3(QR_THREADS), sizeof(cd) * (size_t)max_chi,
+                     s, ly);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
 // One-sided (Hestenes) Jacobi SVD of every computed block.  For columns x, y of
 // the operand with x^H y = |g| e^{i psi}:
 //   zeta = (|y|^2 - |x|^2) / (2 |g|),  t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
@@ -567,6 +706,12 @@ __device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, int m, int lane, dou
 }
 
 __device__ __forceinline__ double jacobi_tol(int m) { return fmax(1e-15, 2.3e-16 * m); }
+
+// The Jacobi operand of a computed block: R of a QR'd block, else the block.
+__device__ __forceinline__ cd *jacobi_operand(const Layer &ly, const GateBase &gb,
+                                              const BlkDesc &B) {
+  return B.qr ? ly.R + gb.r + B.joff : ly.A + gb.e + B.eoff;
+}
 
 // One round-robin pass over all pairs of the nc columns at A (column stride m).
 __device__ __forceinline__ void round_robin_pass(cd *A, int m, int nc, double tol, double tiny,
@@ -673,13 +818,13 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly) {
   BlkDesc *Bp = ly.blk + gp.blk0 + (flat - gb.blk);
   const BlkDesc B = *Bp;
   if (!B.comp || B.big) return;
-  const int m = B.m, n = B.n;
+  const int m = B.mj, n = B.n;
   extern __shared__ double s_dyn[];
   cd *sA = reinterpret_cast<cd *>(s_dyn);
   double *sig = reinterpret_cast<double *>(sA + (size_t)m * n);
   __shared__ int s_rot;
   __shared__ double s_red[16];
-  cd *A = ly.A + gb.e + B.eoff;
+  cd *A = jacobi_operand(ly, gb, B);
   double f2 = 0.0;
   for (int i = threadIdx.x; i < m * n; i += blockDim.x) {
     sA[i] = A[i];
@@ -702,7 +847,7 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly) {
     }
     if (sweep == MAX_SWEEPS && threadIdx.x == 0) atomicOr(st.err, ERR_SVD_NOT_CONVERGED);
   }
-  if (charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym) self_mirror_phase(ly, gp, B, sA);
+  if (!B.qr && charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym) self_mirror_phase(ly, gp, B, sA);
   sort_values(st.err, sA, m, n, sig, ly.sv + gp.lst0 + B.svoff, ly.perm + gp.lst0 + B.svoff);
   for (int i = threadIdx.x; i < m * n; i += blockDim.x) A[i] = sA[i];
   if (threadIdx.x == 0) {
@@ -718,10 +863,11 @@ __global__ __launch_bounds__(256) void k_big_prep(Layer ly) {
   int g, bi;
   big_block_of(ly, blockIdx.x, g, bi);
   BlkDesc *Bp = ly.blk + ly.gates[g].blk0 + bi;
-  const cd *A = ly.A + ly.base[g].e + Bp->eoff;
+  const GateBase gb = ly.base[g];
+  const cd *A = jacobi_operand(ly, gb, *Bp);
   __shared__ double s_red[16];
   double f2 = 0.0;
-  for (long long i = threadIdx.x; i < (long long)Bp->m * Bp->n; i += blockDim.x) f2 += cabs2(A[i]);
+  for (long long i = threadIdx.x; i < (long long)Bp->mj * Bp->n; i += blockDim.x) f2 += cabs2(A[i]);
   f2 = block_sum(f2, s_red);
   if (threadIdx.x == 0) {
     Bp->fro2 = f2;
@@ -753,7 +899,7 @@ __global__ __launch_bounds__(SVD_THREADS) void k_panel(Layer ly, int round, int 
     I = (round + k) % (Pp - 1);
     J = (round - k + Pp - 1) % (Pp - 1);
   }
-  const int m = B.m, n = B.n, w = B.w;
+  const int m = B.mj, n = B.n, w = B.w;
   const bool hasI = I < P, hasJ = J < P;
   if (!(hasI && hasJ) && round != 0) return;     // a lone panel only rotates in round 0
   if (!hasI && !hasJ) return;
@@ -762,7 +908,7 @@ __global__ __launch_bounds__(SVD_THREADS) void k_panel(Layer ly, int round, int 
   const int nc = wI + wJ;
   extern __shared__ double s_dyn[];
   cd *sA = reinterpret_cast<cd *>(s_dyn);
-  cd *A = ly.A + ly.base[g].e + B.eoff;
+  cd *A = jacobi_operand(ly, ly.base[g], B);
   for (int idx = threadIdx.x; idx < nc * m; idx += blockDim.x) {
     const int c = idx / m, i = idx % m;
     const int col = c < wI ? i0 + c : j0 + (c - wI);
@@ -823,10 +969,10 @@ __global__ __launch_bounds__(256) void k_big_finish(Layer ly, int sweeps_run) {
   const State st = ly.states[gp.inst];
   BlkDesc *Bp = ly.blk + gp.blk0 + bi;
   const BlkDesc B = *Bp;
-  cd *A = ly.A + ly.base[g].e + B.eoff;
+  cd *A = jacobi_operand(ly, ly.base[g], B);
   extern __shared__ double s_sig[];
-  if (charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym) self_mirror_phase(ly, gp, B, A);
-  sort_values(st.err, A, B.m, B.n, s_sig, ly.sv + gp.lst0 + B.svoff, ly.perm + gp.lst0 + B.svoff);
+  if (!B.qr && charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym) self_mirror_phase(ly, gp, B, A);
+  sort_values(st.err, A, B.mj, B.n, s_sig, ly.sv + gp.lst0 + B.svoff, ly.perm + gp.lst0 + B.svoff);
   if (threadIdx.x == 0) {
     const int done = ly.rotf[4 * (size_t)blockIdx.x + 3];
     Bp->sweeps = done ? done : sweeps_run;
@@ -1001,6 +1147,92 @@ hipError_t launch_select(Layer ly, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------------------
+// Left singular vectors of the kept ranks of QR'd blocks: u_i = Q [x_i; 0],
+// x_i = (column perm[i] of the rotated R) / sigma_i, the reflectors applied
+// from the last to the first; one wavefront per vector, each lane owning the
+// rows y = lane (mod 64).  For a self-mirror block of a Hermitian state the
+// phase of u_i is then fixed as for unreduced blocks (bilinear sum over the
+// mirrored rows).
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_leftvec(Layer ly) {
+  const int flat = blockIdx.x;
+  const int g = find_gate_blk(ly.base, ly.ngates, flat);
+  const GateBase gb = ly.base[g];
+  const GateParam gp = ly.gates[g];
+  const BlkDesc B = ly.blk[gp.blk0 + (flat - gb.blk)];
+  if (!B.comp || !B.qr || B.kq == 0) return;
+  const int m = B.m, n = B.n;
+  const cd *A = ly.A + gb.e + B.eoff;
+  const cd *tau = ly.tau + gp.lst0 + B.svoff;
+  const cd *R = ly.R + gb.r + B.joff;
+  const double *sv = ly.sv + gp.lst0 + B.svoff;
+  const int *perm = ly.perm + gp.lst0 + B.svoff;
+  cd *U = ly.U + gb.e + B.eoff;
+  const bool selfm = ly.tot[g].sym && charge_n(B.q) == charge_np(B.q);
+  const int *lst = !B.t ? ly.rows + gp.lst0 + B.roff : ly.cols + gp.lst0 + B.coff;
+  const int *my = (!B.t ? ly.mirL : ly.mirR) + gp.mir0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int i0 = 0; i0 < B.kq; i0 += nw) {
+    const int i = i0 + wave;
+    if (i < B.kq) {
+      cd *u = U + (size_t)i * m;
+      const cd *x = R + (size_t)perm[i] * n;
+      const double s1 = 1.0 / sv[i];
+      for (int y = lane; y < m; y += 64) u[y] = y < n ? cscale(x[y], s1) : cmk(0.0, 0.0);
+      for (int k = n - 1; k >= 0; --k) {
+        const cd tk = tau[k];
+        if (tk.re == 0.0 && tk.im == 0.0) continue;
+        const cd *vk = A + (size_t)k * m;
+        double wr = 0.0, wi = 0.0;
+        for (int y = lane; y < m; y += 64) {
+          if (y < k) continue;
+          const cd vy = y == k ? cmk(1.0, 0.0) : vk[y];
+          const cd p = cmulc(vy, u[y]);
+          wr += p.re;
+          wi += p.im;
+        }
+        wr = wave_sum(wr);
+        wi = wave_sum(wi);
+        const cd f = cmul(tk, cmk(wr, wi));    // tau v^H u
+        for (int y = lane; y < m; y += 64) {
+          if (y < k) continue;
+          const cd vy = y == k ? cmk(1.0, 0.0) : vk[y];
+          u[y] = csub(u[y], cmul(f, vy));
+        }
+      }
+    }
+    __syncthreads();
+    if (selfm && i < B.kq) {
+      cd *u = U + (size_t)i * m;
+      double sr = 0.0, si = 0.0, nr = 0.0;
+      for (int y = lane; y < m; y += 64) {
+        const int ym = lower_bound(lst, m, my[lst[y]]);
+        const cd p = cmul(u[y], u[ym]);
+        sr += p.re;
+        si += p.im;
+        nr += cabs2(u[y]);
+      }
+      sr = wave_sum(sr);
+      si = wave_sum(si);
+      nr = wave_sum(nr);
+      const double sa = sqrt(sr * sr + si * si);
+      if (sa > 0.5 * nr && sa > 0.0) {
+        const double ang = -0.5 * atan2(si, sr);
+        const cd f = cmk(cos(ang), sin(ang));
+        for (int y = lane; y < m; y += 64) u[y] = cmul(u[y], f);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_leftvec(Layer ly, hipStream_t s) {
+  if (ly.total_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_leftvec, dim3(ly.total_blocks), dim3(256), 0, s, ly);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
 // New tensors: zero Gamma_j, Gamma_{j+1} and the new bond, then for the kept
 // ranks i of every computed block (beta = boff + i, sigma_i, operand column
 // c = perm[i]):
@@ -1078,14 +1310,15 @@ __global__ __launch_bounds__(256) void k_scatter(Layer ly) {
     }
   }
   for (int i = 0; i < B.kq; ++i) {
-    const int c = perm[i];
-    const double s1 = 1.0 / sv[i], s2 = s1 * s1;
-    const cd *Ac = A + (size_t)c * m;
+    // u = Ac * s1: column perm[i] of U Sigma scaled, or the QR'd block's u_i
+    const double s1 = B.qr ? 1.0 : 1.0 / sv[i];
+    const double s2 = s1 / sv[i];
+    const cd *Ac = B.qr ? ly.U + gb.e + B.eoff + (size_t)i * m : A + (size_t)perm[i] * m;
     for (int x = wave; x < n; x += nw) {
       const cd *A0x = A0 + (size_t)x * m;
       double re = 0.0, im = 0.0;
       for (int y = lane; y < m; y += 64) {
-        const cd p = cmulc(Ac[y], A0x[y]);     // A0[y, x] conj(A[y, c])
+        const cd p = cmulc(Ac[y], A0x[y]);     // A0[y, x] conj(Ac[y])
         re += p.re;
         im += p.im;
       }

@@ -42,6 +42,9 @@ struct BlkDesc {
   int roff, coff; // offsets of the row / column index lists
   int gate;       // gate index inside the layer
   int comp;       // 1: contracted and SVD'd here; 0: derived from its mirror block
+  int qr;         // 1: Householder QR first, the Jacobi runs on the n x n factor R
+  int mj;         // rows of the Jacobi operand (n with QR, else m)
+  long long joff; // offset of R (local to the gate) in the R pool
 };
 
 // Per-gate plan totals (device -> host).
@@ -49,6 +52,7 @@ struct GateTot {
   int nblk, sv, rows, cols, maxr, maxc, chunks, sym;
   int nbig, maxpp;    // big blocks, largest even panel count among them
   long long elems;
+  long long relems;   // R factors of the QR'd blocks (sum of n^2)
   double svd_flops;   // sum over blocks of 16 m n^2 + 36 n^3 (complex SVD convention)
 };
 
@@ -58,6 +62,7 @@ struct GateBase {
   int blk;            // first block (flat over the layer)
   int big;            // first big block (flat over the layer)
   long long echunk;   // first 256-element chunk of the gate
+  long long r;        // first element of the gate in the R pool
 };
 
 // Device-resident state of one simulation (App. D Vidal form with charges).
@@ -86,6 +91,9 @@ struct Layer {
   int *mirL, *mirR;  // per gate: mirror index on the left / right bond, -1 if none (at mir0)
   cd *A;             // sector operands (overwritten by U * Sigma)
   cd *A0;            // pristine copies of the operands (right-vector recovery)
+  cd *R;             // n x n triangular factors of QR'd blocks (then U_R Sigma)
+  cd *tau;           // Householder scalars (n per computed block, at lst0 + svoff)
+  cd *U;             // kept left singular vectors of QR'd blocks (at the A offset)
   int *bigl;         // per gate: local indices of its big blocks (at lst0)
   int *rotf;         // per big block: rotation flags of the two latest sweeps
   int *active;       // big blocks still rotating after the latest checked sweep
@@ -118,6 +126,8 @@ hipError_t launch_fock(Layer ly, hipStream_t s);
 hipError_t launch_plan_count(Layer ly, hipStream_t s);
 hipError_t launch_plan_fill(Layer ly, hipStream_t s);
 hipError_t launch_contract(Layer ly, hipStream_t s);
+hipError_t launch_qr(Layer ly, int max_chi, hipStream_t s);
+hipError_t launch_leftvec(Layer ly, hipStream_t s);
 hipError_t launch_svd_small(Layer ly, hipStream_t s);
 hipError_t launch_svd_big_prep(Layer ly, hipStream_t s);
 hipError_t launch_svd_panel_round(Layer ly, int round, int sweep, hipStream_t s);
@@ -127,6 +137,7 @@ hipError_t launch_select(Layer ly, hipStream_t s);
 hipError_t launch_scatter(Layer ly, int max_chi, hipStream_t s);
 hipError_t launch_entropy_layer(Layer ly, hipStream_t s);
 int svd_lds_bytes();
+void set_svd_route(int lds_limit_bytes, int qr_enable);
 size_t svd_small_need(int m, int n);
 
 // readouts

@@ -54,6 +54,8 @@ def lib() -> ctypes.CDLL:
         L.mpo_set_profiling.argtypes = [c_void_p, c_int]
         L.mpo_get_profile.argtypes = [c_void_p, pd, pll, pd]
         L.mpo_layer_blocks.argtypes = [c_void_p, c_int, pi]
+        L.gbs_set_svd_route.argtypes = [c_int, c_int]
+        L.gbs_set_svd_route.restype = c_int
         pe = ctypes.POINTER(c_void_p)
         L.mpo_engine_projected_bytes.argtypes = [c_int, c_int, c_int]
         L.mpo_engine_projected_bytes.restype = ctypes.c_longlong
@@ -217,6 +219,11 @@ class MPO:
                                      _dp(work)))
         return (dict(zip(self.PHASES, ms.tolist())), dict(zip(self.PHASES, n.tolist())),
                 dict(svd_flops=work[0], elements=work[1], candidates=work[2], layers=work[3]))
+
+
+def set_svd_route(lds_limit_bytes=0, qr_enable=True):
+    """Routing of the block SVDs (LDS budget, QR reduction); 0 = device budget."""
+    _check(lib().gbs_set_svd_route(int(lds_limit_bytes), 1 if qr_enable else 0))
 
 
 def projected_bytes(M, d, chi) -> int:

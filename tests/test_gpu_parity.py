@@ -54,9 +54,22 @@ def test_gpu_init_small_matches_oracle():
         assert np.abs(P - oP).max() < 1e-13
 
 
-def test_gpu_small_workload_full_run():
+@pytest.fixture
+def svd_route():
+    """Sets a block-SVD route for one test and restores the default after."""
+    def set_route(lds, qr):
+        gbsmpo.set_svd_route(lds, qr)
+    yield set_route
+    gbsmpo.set_svd_route(0, True)
+
+
+@pytest.mark.parametrize("lds,qr", [(0, True), (3000, True), (3000, False), (9000, True)])
+def test_gpu_small_workload_full_run(svd_route, lds, qr):
     """Whole small-workload run (8 modes, 28 beam splitters, chi=32): every bond
-    after every layer, then marginals and trace, against the oracle."""
+    after every layer, then marginals and trace, against the oracle.  A lowered
+    LDS budget sends the blocks through the Householder-QR and multi-workgroup
+    panel SVD paths that the full-size workloads take."""
+    svd_route(lds, qr)
     w = inputs.workload("small")
     U = inputs.haar_unitary(w.M, w.seed)
     layers, phase = gbsmpo.clements(U)
@@ -105,9 +118,12 @@ def test_gpu_untruncated_matches_brute_force(M, d, r, eta, seed):
     assert np.abs(P - bP).max() < 1e-12
 
 
-def test_gpu_medium_shape_reduced_chi_matches_oracle():
+@pytest.mark.parametrize("lds", [0, 2500])
+def test_gpu_medium_shape_reduced_chi_matches_oracle(svd_route, lds):
     """Medium shape (M=32, d=8, r=0.8, sqrt-scaling eta) at chi=16 so that the
-    dense oracle stays fast: the first four layers, bond by bond."""
+    dense oracle stays fast: the first four layers, bond by bond (also with the
+    QR / panel SVD paths forced by a lowered LDS budget)."""
+    svd_route(lds, True)
     w = inputs.workload("medium")
     chi = 16
     U = inputs.haar_unitary(w.M, w.seed)
@@ -280,3 +296,24 @@ def test_gpu_engine_admission_refuses_oversized_request():
         with pytest.raises(gbsmpo.GbsMpoError) as ei:
             eng.add(8, 0.5, 0.5, 4, 32, U)
         assert ei.value.code == gbsmpo.MPO_ENOMEM
+
+
+def test_gpu_large_qr_route_matches_unreduced(svd_route):
+    """Large workload (chi=1024), first two layers: the Householder-QR route
+    and the unreduced panel route give the same charges and Schmidt values
+    (to 1e-10 relative plus 1e-12 of the bond maximum) and entropies."""
+    w = inputs.workload("large")
+    U = inputs.haar_unitary(w.M, w.seed)
+    layers, _ = gbsmpo.clements(U)
+    res = []
+    for qr in (True, False):
+        svd_route(0, qr)
+        say("large, qr", qr)
+        with gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi) as g:
+            for li in range(2):
+                g.apply_layer(*layers[li])
+            res.append(([g.bond(b) for b in range(w.M + 1)], g.entropy()[0]))
+    (b1, S1), (b2, S2) = res
+    for b in range(w.M + 1):
+        assert_bond_equal(b1[b][0], b1[b][1], b2[b][0], b2[b][1], f"bond {b}")
+    assert np.abs(S1 - S2).max() < 1e-10
