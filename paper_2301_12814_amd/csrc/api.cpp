@@ -129,7 +129,7 @@ struct Engine {
   DBuf<int> d_rows, d_cols, d_bigl, d_perm, d_usize;
   DBuf<double> d_sv;
   DBuf<unsigned long long> d_uval, d_ukey;
-  DBuf<cd> d_A, d_A0, d_R, d_U, d_tau;
+  DBuf<cd> d_A, d_A0, d_R, d_U, d_V, d_tau;
   DBuf<int> d_rotf;
   DBuf<int> d_active;
   DBuf<int> d_eng_err;
@@ -268,6 +268,7 @@ void engine_destroy(Engine &E) {
   E.d_A0.release();
   E.d_R.release();
   E.d_U.release();
+  E.d_V.release();
   E.d_tau.release();
   E.d_rotf.release();
   E.d_active.release();
@@ -593,6 +594,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     HIPCHK(E.d_A0.ensure(std::max(e, 1LL), (size_t)E.pool_budget));
     HIPCHK(E.d_U.ensure(std::max(e, 1LL), (size_t)E.pool_budget));
     HIPCHK(E.d_R.ensure(std::max(re, 1LL), (size_t)E.pool_budget));
+    HIPCHK(E.d_V.ensure(std::max(re, 1LL), (size_t)E.pool_budget));
     HIPCHK(E.d_tau.ensure(lst0));
     HIPCHK(E.d_rotf.ensure((size_t)4 * std::max(bigb, 1)));
     if (bigb > 65535 || maxpp / 2 > 65535)
@@ -619,6 +621,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     C.A0 = E.d_A0.p;
     C.R = E.d_R.p;
     C.U = E.d_U.p;
+    C.V = E.d_V.p;
     C.tau = E.d_tau.p;
     C.rotf = E.d_rotf.p;
     C.active = E.d_active.p;

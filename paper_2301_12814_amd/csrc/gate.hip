@@ -100,21 +100,22 @@ __host__ __device__ inline size_t svd_small_need_(int m, int n) {
 size_t svd_small_need(int m, int n) { return svd_small_need_(m, n); }
 #define svd_small_need svd_small_need_
 __host__ __device__ inline int panel_width(int m, int lds_bytes) {
-  int w = 8;
+  int w = 32;
   while (w > 1 && 2 * (size_t)w * m * sizeof(cd) > (size_t)lds_bytes) w >>= 1;
   return w;
 }
 
 // Route of a computed block's SVD.  A block whose operand does not fit in LDS
-// and has at least 1.2x more rows than columns is first reduced by a
-// Householder QR (A = Q R, the Jacobi then rotates the n x n factor R: the
-// work per sweep drops by m / n); the Jacobi runs in one workgroup from LDS
-// when its operand fits there, otherwise as multi-workgroup panel rounds.
+// is first reduced by a Householder QR, A = Q R, and the Jacobi rotates the
+// n x n operand X = R^H: its columns are far closer to orthogonal than those
+// of A (the Jacobi needs about a third of the sweeps) and the work per sweep
+// drops by m / n.  The Jacobi runs in one workgroup from LDS when its operand
+// fits there, otherwise as multi-workgroup panel rounds.
 __host__ __device__ inline void svd_route(int m, int n, int lds_bytes, int qr_ok, int &qr,
                                           int &big, int &mj) {
   qr = 0;
   mj = m;
-  if (qr_ok && svd_small_need(m, n) > (size_t)lds_bytes && 5LL * m >= 6LL * n) {
+  if (qr_ok && svd_small_need(m, n) > (size_t)lds_bytes) {
     qr = 1;
     mj = n;
   }
@@ -538,8 +539,8 @@ hipError_t launch_contract(Layer ly, hipStream_t s) {
 // column x below the diagonal, beta = -sign(Re x_0) |x|, tau = (beta - x_0) /
 // beta and v = x / (x_0 - beta) give H_k^H x = beta e_1 with beta real; the
 // trailing columns are multiplied by H_k^H.  One workgroup per block; the
-// reflectors stay below the diagonal of the operand, R (upper triangle, zeros
-// below) is copied to the R pool where the Jacobi rotates it.
+// operand is overwritten (its pristine copy stays in A0) and X = R^H (lower
+// triangle, zeros above) is written to the R pool where the Jacobi rotates it.
 // ----------------------------------------------------------------------------
 constexpr int QR_THREADS = 512;
 
@@ -611,10 +612,10 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly) {
     }
     __syncthreads();
   }
-  cd *R = ly.R + gb.r + B.joff;
+  cd *X = ly.R + gb.r + B.joff;    // X[i, c] = conj(R[c, i]), column-major
   for (long long idx = threadIdx.x; idx < (long long)n * n; idx += blockDim.x) {
     const int c = (int)(idx / n), i = (int)(idx % n);
-    R[idx] = i <= c ? A[(size_t)c * m + i] : cmk(0.0, 0.0);
+    X[idx] = c <= i ? cconj(A[(size_t)i * m + c]) : cmk(0.0, 0.0);
   }
 }
 
@@ -647,9 +648,15 @@ constexpr int SVD_THREADS = 512;
 constexpr int MAX_SWEEPS = 60;
 constexpr int RPL = 8;          // column rows cached per lane (m <= 512)
 
-__device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, int m, int lane, double tol,
-                                            double tiny, int &rot) {
-  double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+// One rotation of the column pair (x, y) by one wavefront.  The squared
+// norms al = |x|^2, be = |y|^2 are tracked in LDS: a rotation with tangent t
+// changes them exactly to al - t |g| and be + t |g|; when either loses more
+// than half it is recomputed from the rotated column instead.
+__device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, double *nx, double *ny, int m,
+                                            int lane, double tol, double tiny, int &rot) {
+  const double al = *nx, be = *ny;
+  if (al <= tiny && be <= tiny) return;
+  double gr = 0.0, gi = 0.0;
   const bool cached = m <= 64 * RPL;
   cd rx[RPL], ry[RPL];
   if (cached) {
@@ -658,25 +665,18 @@ __device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, int m, int lane, dou
       const int i = lane + 64 * k;
       rx[k] = i < m ? xp[i] : cmk(0.0, 0.0);
       ry[k] = i < m ? xq[i] : cmk(0.0, 0.0);
-      al += cabs2(rx[k]);
-      be += cabs2(ry[k]);
       gr += rx[k].re * ry[k].re + rx[k].im * ry[k].im;
       gi += rx[k].re * ry[k].im - rx[k].im * ry[k].re;
     }
   } else {
     for (int i = lane; i < m; i += 64) {
       const cd x = xp[i], y = xq[i];
-      al += cabs2(x);
-      be += cabs2(y);
       gr += x.re * y.re + x.im * y.im;
       gi += x.re * y.im - x.im * y.re;
     }
   }
-  al = wave_sum(al);
-  be = wave_sum(be);
   gr = wave_sum(gr);
   gi = wave_sum(gi);
-  if (al <= tiny && be <= tiny) return;
   const double ga = sqrt(gr * gr + gi * gi);
   if (!(ga > tol * sqrt(al * be)) || ga < 1e-300) return;
   const double zeta = (be - al) / (2.0 * ga);
@@ -684,25 +684,57 @@ __device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, int m, int lane, dou
   const double c = 1.0 / sqrt(1.0 + t * t);
   const double s = c * t;
   const cd e = cmk(gr / ga, -gi / ga);      // e^{-i psi}
+  double al2 = al - t * ga, be2 = be + t * ga;
+  const bool exact = !(al2 >= 0.5 * al) || !(be2 >= 0.5 * be);
+  double na = 0.0, nb = 0.0;
   if (cached) {
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
       const int i = lane + 64 * k;
       if (i < m) {
         const cd y = cmul(e, ry[k]);
-        xp[i] = csub(cscale(rx[k], c), cscale(y, s));
-        xq[i] = cadd(cscale(rx[k], s), cscale(y, c));
+        const cd x2 = csub(cscale(rx[k], c), cscale(y, s));
+        const cd y2 = cadd(cscale(rx[k], s), cscale(y, c));
+        xp[i] = x2;
+        xq[i] = y2;
+        na += cabs2(x2);
+        nb += cabs2(y2);
       }
     }
   } else {
     for (int i = lane; i < m; i += 64) {
       const cd x = xp[i];
       const cd y = cmul(e, xq[i]);
-      xp[i] = csub(cscale(x, c), cscale(y, s));
-      xq[i] = cadd(cscale(x, s), cscale(y, c));
+      const cd x2 = csub(cscale(x, c), cscale(y, s));
+      const cd y2 = cadd(cscale(x, s), cscale(y, c));
+      xp[i] = x2;
+      xq[i] = y2;
+      na += cabs2(x2);
+      nb += cabs2(y2);
     }
   }
+  if (exact) {               // wave-uniform
+    al2 = wave_sum(na);
+    be2 = wave_sum(nb);
+  }
+  if (lane == 0) {
+    *nx = al2;
+    *ny = be2;
+  }
   rot = 1;
+}
+
+// Squared norms of the nc columns at A (column stride m) into nrm.
+__device__ __forceinline__ void column_norms(const cd *A, int m, int nc, double *nrm) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  for (int c = wave; c < nc; c += nw) {
+    double acc = 0.0;
+    for (int i = lane; i < m; i += 64) acc += cabs2(A[(size_t)c * m + i]);
+    acc = wave_sum(acc);
+    if (lane == 0) nrm[c] = acc;
+  }
+  __syncthreads();
 }
 
 __device__ __forceinline__ double jacobi_tol(int m) { return fmax(1e-15, 2.3e-16 * m); }
@@ -713,9 +745,10 @@ __device__ __forceinline__ cd *jacobi_operand(const Layer &ly, const GateBase &g
   return B.qr ? ly.R + gb.r + B.joff : ly.A + gb.e + B.eoff;
 }
 
-// One round-robin pass over all pairs of the nc columns at A (column stride m).
-__device__ __forceinline__ void round_robin_pass(cd *A, int m, int nc, double tol, double tiny,
-                                                 int &rot) {
+// One round-robin pass over all pairs of the nc columns at A (column stride m,
+// squared norms in nrm).
+__device__ __forceinline__ void round_robin_pass(cd *A, double *nrm, int m, int nc, double tol,
+                                                 double tiny, int &rot) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const int np = nc + (nc & 1);
@@ -730,7 +763,7 @@ __device__ __forceinline__ void round_robin_pass(cd *A, int m, int nc, double to
         q = (round - k + np - 1) % (np - 1);
       }
       if (p >= nc || q >= nc) continue;
-      jacobi_pair(A + (size_t)p * m, A + (size_t)q * m, m, lane, tol, tiny, rot);
+      jacobi_pair(A + (size_t)p * m, A + (size_t)q * m, nrm + p, nrm + q, m, lane, tol, tiny, rot);
     }
     __syncthreads();
   }
@@ -809,7 +842,9 @@ __device__ inline void big_block_of(const Layer &ly, int flat_big, int &g, int &
   bi = ly.bigl[ly.gates[g].lst0 + (flat_big - ly.base[g].big)];
 }
 
-__global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly) {
+// One workgroup per block whose LDS need lies in (lo, hi] (the launches are
+// split by size so that small blocks do not reserve a whole CU's LDS).
+__global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly, int lo, int hi) {
   const int flat = blockIdx.x;
   const int g = find_gate_blk(ly.base, ly.ngates, flat);
   const GateBase gb = ly.base[g];
@@ -818,6 +853,10 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly) {
   BlkDesc *Bp = ly.blk + gp.blk0 + (flat - gb.blk);
   const BlkDesc B = *Bp;
   if (!B.comp || B.big) return;
+  {
+    const long long need = (long long)svd_small_need(B.mj, B.n);
+    if (need <= lo || need > hi) return;
+  }
   const int m = B.mj, n = B.n;
   extern __shared__ double s_dyn[];
   cd *sA = reinterpret_cast<cd *>(s_dyn);
@@ -836,9 +875,9 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly) {
   if (n > 1) {
     for (sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
       if (threadIdx.x == 0) s_rot = 0;
-      __syncthreads();
+      column_norms(sA, m, n, sig);
       int rot = 0;
-      round_robin_pass(sA, m, n, tol, tiny, rot);
+      round_robin_pass(sA, sig, m, n, tol, tiny, rot);
       if (rot) s_rot = 1;
       __syncthreads();
       const int any = s_rot;
@@ -876,7 +915,9 @@ __global__ __launch_bounds__(256) void k_big_prep(Layer ly) {
   }
 }
 
-__global__ __launch_bounds__(SVD_THREADS) void k_panel(Layer ly, int round, int sweep) {
+constexpr int PANEL_THREADS = 1024;
+
+__global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int round, int sweep) {
   const int kbig = blockIdx.y;
   int g, bi;
   big_block_of(ly, kbig, g, bi);
@@ -916,9 +957,11 @@ __global__ __launch_bounds__(SVD_THREADS) void k_panel(Layer ly, int round, int 
   }
   __syncthreads();
   const double tol = jacobi_tol(m), tiny = 1e-30 * B.fro2;
+  __shared__ double s_nrm[64];
+  column_norms(sA, m, nc, s_nrm);
   int rot = 0;
   if (round == 0) {
-    round_robin_pass(sA, m, nc, tol, tiny, rot);
+    round_robin_pass(sA, s_nrm, m, nc, tol, tiny, rot);
   } else {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
@@ -926,7 +969,8 @@ __global__ __launch_bounds__(SVD_THREADS) void k_panel(Layer ly, int round, int 
       for (int t = wave; t < wI; t += nw) {
         const int u = (t + sr) % w;
         if (u >= wJ) continue;
-        jacobi_pair(sA + (size_t)t * m, sA + (size_t)(wI + u) * m, m, lane, tol, tiny, rot);
+        jacobi_pair(sA + (size_t)t * m, sA + (size_t)(wI + u) * m, s_nrm + t, s_nrm + wI + u, m,
+                    lane, tol, tiny, rot);
       }
       __syncthreads();
     }
@@ -997,8 +1041,19 @@ int svd_lds_bytes() {
 hipError_t launch_svd_small(Layer ly, hipStream_t s) {
   if (ly.total_blocks == 0) return hipSuccess;
   const int lb = svd_lds_bytes();
-  hipLaunchKernelGGL(k_svd_small, dim3(ly.total_blocks), dim3(SVD_THREADS), (size_t)lb, s, ly);
-  return hipGetLastError();
+  // size classes: (LDS bound, threads)
+  const int cap[4] = {16384, 40960, 81920, lb};
+  const int thr[4] = {256, 256, 512, 512};
+  int lo = 0;
+  for (int k = 0; k < 4; ++k) {
+    const int hi = cap[k] < lb ? cap[k] : lb;
+    if (hi <= lo) continue;
+    hipLaunchKernelGGL(k_svd_small, dim3(ly.total_blocks), dim3(thr[k]), (size_t)hi, s, ly, lo, hi);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    lo = hi;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_svd_big_prep(Layer ly, hipStream_t s) {
@@ -1010,7 +1065,7 @@ hipError_t launch_svd_big_prep(Layer ly, hipStream_t s) {
 hipError_t launch_svd_panel_round(Layer ly, int round, int sweep, hipStream_t s) {
   if (ly.total_big == 0) return hipSuccess;
   const int lb = svd_lds_bytes();
-  hipLaunchKernelGGL(k_panel, dim3(ly.maxpp / 2, ly.total_big), dim3(SVD_THREADS), (size_t)lb, s,
+  hipLaunchKernelGGL(k_panel, dim3(ly.maxpp / 2, ly.total_big), dim3(PANEL_THREADS), (size_t)lb, s,
                      ly, round, sweep);
   return hipGetLastError();
 }
@@ -1147,12 +1202,15 @@ hipError_t launch_select(Layer ly, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------------------
-// Left singular vectors of the kept ranks of QR'd blocks: u_i = Q [x_i; 0],
-// x_i = (column perm[i] of the rotated R) / sigma_i, the reflectors applied
-// from the last to the first; one wavefront per vector, each lane owning the
-// rows y = lane (mod 64).  For a self-mirror block of a Hermitian state the
-// phase of u_i is then fixed as for unreduced blocks (bilinear sum over the
-// mirrored rows).
+// Singular vectors of the kept ranks of QR'd blocks.  With A = Q R, R = X^H
+// and the Jacobi result X W = Y (orthogonal columns of norms sigma), A =
+// (Q W) Sigma (Y Sigma^-1)^H: the right singular vectors are the normalised
+// columns of Y, v_i = Y[:, perm[i]] / sigma_i, and u_i = A0 v_i / sigma_i
+// from the pristine operand.  For a self-mirror block of a Hermitian state
+// the phase of v_i is fixed first (v J-real up to a phase: bilinear sum over
+// the mirrored operand columns), which makes u_i J-real too.  One wavefront
+// per vector; u_i goes to the U pool (at the operand offset), conj(v_i) to
+// the V pool (at the R offset), each lane owning fixed rows.
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_leftvec(Layer ly) {
   const int flat = blockIdx.x;
@@ -1162,55 +1220,37 @@ __global__ __launch_bounds__(256) void k_leftvec(Layer ly) {
   const BlkDesc B = ly.blk[gp.blk0 + (flat - gb.blk)];
   if (!B.comp || !B.qr || B.kq == 0) return;
   const int m = B.m, n = B.n;
-  const cd *A = ly.A + gb.e + B.eoff;
-  const cd *tau = ly.tau + gp.lst0 + B.svoff;
-  const cd *R = ly.R + gb.r + B.joff;
+  const cd *A0 = ly.A0 + gb.e + B.eoff;
+  const cd *Y = ly.R + gb.r + B.joff;
   const double *sv = ly.sv + gp.lst0 + B.svoff;
   const int *perm = ly.perm + gp.lst0 + B.svoff;
   cd *U = ly.U + gb.e + B.eoff;
+  cd *V = ly.V + gb.r + B.joff;
   const bool selfm = ly.tot[g].sym && charge_n(B.q) == charge_np(B.q);
-  const int *lst = !B.t ? ly.rows + gp.lst0 + B.roff : ly.cols + gp.lst0 + B.coff;
-  const int *my = (!B.t ? ly.mirL : ly.mirR) + gp.mir0;
+  // operand columns: right-bond indices (stored Theta) or left-bond indices (Theta^T)
+  const int *lst = !B.t ? ly.cols + gp.lst0 + B.coff : ly.rows + gp.lst0 + B.roff;
+  const int *mx = (!B.t ? ly.mirR : ly.mirL) + gp.mir0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int i0 = 0; i0 < B.kq; i0 += nw) {
     const int i = i0 + wave;
+    cd f = cmk(1.0, 0.0);
     if (i < B.kq) {
-      cd *u = U + (size_t)i * m;
-      const cd *x = R + (size_t)perm[i] * n;
+      const cd *y = Y + (size_t)perm[i] * n;
       const double s1 = 1.0 / sv[i];
-      for (int y = lane; y < m; y += 64) u[y] = y < n ? cscale(x[y], s1) : cmk(0.0, 0.0);
-      for (int k = n - 1; k >= 0; --k) {
-        const cd tk = tau[k];
-        if (tk.re == 0.0 && tk.im == 0.0) continue;
-        const cd *vk = A + (size_t)k * m;
-        double wr = 0.0, wi = 0.0;
-        for (int y = lane; y < m; y += 64) {
-          if (y < k) continue;
-          const cd vy = y == k ? cmk(1.0, 0.0) : vk[y];
-          const cd p = cmulc(vy, u[y]);
-          wr += p.re;
-          wi += p.im;
-        }
-        wr = wave_sum(wr);
-        wi = wave_sum(wi);
-        const cd f = cmul(tk, cmk(wr, wi));    // tau v^H u
-        for (int y = lane; y < m; y += 64) {
-          if (y < k) continue;
-          const cd vy = y == k ? cmk(1.0, 0.0) : vk[y];
-          u[y] = csub(u[y], cmul(f, vy));
-        }
-      }
+      cd *v = V + (size_t)i * n;
+      for (int x = lane; x < n; x += 64) v[x] = cconj(cscale(y[x], s1));   // conj(v)
     }
     __syncthreads();
     if (selfm && i < B.kq) {
-      cd *u = U + (size_t)i * m;
+      // conj(v) is J-real up to a phase exactly when v is; fix it on conj(v)
+      cd *v = V + (size_t)i * n;
       double sr = 0.0, si = 0.0, nr = 0.0;
-      for (int y = lane; y < m; y += 64) {
-        const int ym = lower_bound(lst, m, my[lst[y]]);
-        const cd p = cmul(u[y], u[ym]);
+      for (int x = lane; x < n; x += 64) {
+        const int xm = lower_bound(lst, n, mx[lst[x]]);
+        const cd p = cmul(v[x], v[xm]);
         sr += p.re;
         si += p.im;
-        nr += cabs2(u[y]);
+        nr += cabs2(v[x]);
       }
       sr = wave_sum(sr);
       si = wave_sum(si);
@@ -1218,11 +1258,30 @@ __global__ __launch_bounds__(256) void k_leftvec(Layer ly) {
       const double sa = sqrt(sr * sr + si * si);
       if (sa > 0.5 * nr && sa > 0.0) {
         const double ang = -0.5 * atan2(si, sr);
-        const cd f = cmk(cos(ang), sin(ang));
-        for (int y = lane; y < m; y += 64) u[y] = cmul(u[y], f);
+        f = cmk(cos(ang), sin(ang));
       }
     }
     __syncthreads();
+    if (i < B.kq) {
+      cd *v = V + (size_t)i * n;
+      if (selfm)
+        for (int x = lane; x < n; x += 64) v[x] = cmul(v[x], f);
+    }
+    __syncthreads();
+    if (i < B.kq) {
+      const cd *v = V + (size_t)i * n;
+      cd *u = U + (size_t)i * m;
+      const double s1 = 1.0 / sv[i];
+      for (int yy = lane; yy < m; yy += 64) {
+        double re = 0.0, im = 0.0;
+        for (int x = 0; x < n; ++x) {
+          const cd p = cmulc(v[x], A0[(size_t)x * m + yy]);   // A0[y, x] v[x]
+          re += p.re;
+          im += p.im;
+        }
+        u[yy] = cmk(re * s1, im * s1);
+      }
+    }
   }
 }
 
@@ -1314,6 +1373,10 @@ __global__ __launch_bounds__(256) void k_scatter(Layer ly) {
     const double s1 = B.qr ? 1.0 : 1.0 / sv[i];
     const double s2 = s1 / sv[i];
     const cd *Ac = B.qr ? ly.U + gb.e + B.eoff + (size_t)i * m : A + (size_t)perm[i] * m;
+    if (B.qr) {
+      const cd *vc = ly.V + gb.r + B.joff + (size_t)i * n;
+      for (int x = threadIdx.x; x < n; x += blockDim.x) sv_x[x] = vc[x];
+    } else
     for (int x = wave; x < n; x += nw) {
       const cd *A0x = A0 + (size_t)x * m;
       double re = 0.0, im = 0.0;

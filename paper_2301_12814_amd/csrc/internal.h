@@ -42,7 +42,7 @@ struct BlkDesc {
   int roff, coff; // offsets of the row / column index lists
   int gate;       // gate index inside the layer
   int comp;       // 1: contracted and SVD'd here; 0: derived from its mirror block
-  int qr;         // 1: Householder QR first, the Jacobi runs on the n x n factor R
+  int qr;         // 1: Householder QR first, the Jacobi runs on X = R^H (n x n)
   int mj;         // rows of the Jacobi operand (n with QR, else m)
   long long joff; // offset of R (local to the gate) in the R pool
 };
@@ -91,9 +91,10 @@ struct Layer {
   int *mirL, *mirR;  // per gate: mirror index on the left / right bond, -1 if none (at mir0)
   cd *A;             // sector operands (overwritten by U * Sigma)
   cd *A0;            // pristine copies of the operands (right-vector recovery)
-  cd *R;             // n x n triangular factors of QR'd blocks (then U_R Sigma)
+  cd *R;             // X = R^H of QR'd blocks, n x n (rotated by the Jacobi)
   cd *tau;           // Householder scalars (n per computed block, at lst0 + svoff)
   cd *U;             // kept left singular vectors of QR'd blocks (at the A offset)
+  cd *V;             // conjugated kept right singular vectors of QR'd blocks (at the R offset)
   int *bigl;         // per gate: local indices of its big blocks (at lst0)
   int *rotf;         // per big block: rotation flags of the two latest sweeps
   int *active;       // big blocks still rotating after the latest checked sweep
