@@ -648,35 +648,61 @@ constexpr int SVD_THREADS = 512;
 constexpr int MAX_SWEEPS = 60;
 constexpr int RPL = 8;          // column rows cached per lane (m <= 512)
 
-// One rotation of the column pair (x, y) by one wavefront.  The squared
-// norms al = |x|^2, be = |y|^2 are tracked in LDS: a rotation with tangent t
-// changes them exactly to al - t |g| and be + t |g|; when either loses more
-// than half it is recomputed from the rotated column instead.
+// Column pairs are rotated by groups of 16 lanes (one DPP row): a wavefront
+// works on four pairs at once and the dot products reduce with four DPP
+// steps inside the row instead of cross-lane permutes over the whole wave.
+constexpr int GL = 16;   // lanes per column pair
+constexpr int CE = 8;    // elements per lane kept in registers (m <= GL * CE)
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(h2, l2);
+}
+
+// Sum over the 16 lanes of a DPP row: xor 1 and xor 2 inside each quad, then
+// the row mirror (quad q with quad 3 - q) and the half-row mirror (quad 0 with
+// 1, 2 with 3).  Every step adds two values in an order-independent way, so
+// all 16 lanes end with bitwise the same sum (the callers branch on it).
+__device__ __forceinline__ double group_sum(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x140>(v);
+  v += dpp_d<0x141>(v);
+  return v;
+}
+
+// One rotation of the column pair (x, y) by one 16-lane group (gl = lane in
+// the group).  The squared norms al = |x|^2, be = |y|^2 are tracked in LDS: a
+// rotation with tangent t changes them exactly to al - t |g| and be + t |g|;
+// when either loses more than half it is recomputed from the rotated column.
 __device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, double *nx, double *ny, int m,
-                                            int lane, double tol, double tiny, int &rot) {
+                                            int gl, double tol, double tiny, int &rot) {
   const double al = *nx, be = *ny;
   if (al <= tiny && be <= tiny) return;
   double gr = 0.0, gi = 0.0;
-  const bool cached = m <= 64 * RPL;
-  cd rx[RPL], ry[RPL];
+  const bool cached = m <= GL * CE;
+  cd rx[CE], ry[CE];
   if (cached) {
 #pragma unroll
-    for (int k = 0; k < RPL; ++k) {
-      const int i = lane + 64 * k;
+    for (int k = 0; k < CE; ++k) {
+      const int i = gl + GL * k;
       rx[k] = i < m ? xp[i] : cmk(0.0, 0.0);
       ry[k] = i < m ? xq[i] : cmk(0.0, 0.0);
       gr += rx[k].re * ry[k].re + rx[k].im * ry[k].im;
       gi += rx[k].re * ry[k].im - rx[k].im * ry[k].re;
     }
   } else {
-    for (int i = lane; i < m; i += 64) {
+    for (int i = gl; i < m; i += GL) {
       const cd x = xp[i], y = xq[i];
       gr += x.re * y.re + x.im * y.im;
       gi += x.re * y.im - x.im * y.re;
     }
   }
-  gr = wave_sum(gr);
-  gi = wave_sum(gi);
+  gr = group_sum(gr);
+  gi = group_sum(gi);
   const double ga = sqrt(gr * gr + gi * gi);
   if (!(ga > tol * sqrt(al * be)) || ga < 1e-300) return;
   const double zeta = (be - al) / (2.0 * ga);
@@ -689,8 +715,8 @@ __device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, double *nx, double *
   double na = 0.0, nb = 0.0;
   if (cached) {
 #pragma unroll
-    for (int k = 0; k < RPL; ++k) {
-      const int i = lane + 64 * k;
+    for (int k = 0; k < CE; ++k) {
+      const int i = gl + GL * k;
       if (i < m) {
         const cd y = cmul(e, ry[k]);
         const cd x2 = csub(cscale(rx[k], c), cscale(y, s));
@@ -702,7 +728,7 @@ __device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, double *nx, double *
       }
     }
   } else {
-    for (int i = lane; i < m; i += 64) {
+    for (int i = gl; i < m; i += GL) {
       const cd x = xp[i];
       const cd y = cmul(e, xq[i]);
       const cd x2 = csub(cscale(x, c), cscale(y, s));
@@ -713,11 +739,11 @@ __device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, double *nx, double *
       nb += cabs2(y2);
     }
   }
-  if (exact) {               // wave-uniform
-    al2 = wave_sum(na);
-    be2 = wave_sum(nb);
+  if (exact) {               // uniform over the group
+    al2 = group_sum(na);
+    be2 = group_sum(nb);
   }
-  if (lane == 0) {
+  if (gl == 0) {
     *nx = al2;
     *ny = be2;
   }
@@ -726,13 +752,13 @@ __device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, double *nx, double *
 
 // Squared norms of the nc columns at A (column stride m) into nrm.
 __device__ __forceinline__ void column_norms(const cd *A, int m, int nc, double *nrm) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
-  for (int c = wave; c < nc; c += nw) {
+  const int gl = threadIdx.x & (GL - 1), slot = threadIdx.x / GL;
+  const int ns = blockDim.x / GL;
+  for (int c = slot; c < nc; c += ns) {
     double acc = 0.0;
-    for (int i = lane; i < m; i += 64) acc += cabs2(A[(size_t)c * m + i]);
-    acc = wave_sum(acc);
-    if (lane == 0) nrm[c] = acc;
+    for (int i = gl; i < m; i += GL) acc += cabs2(A[(size_t)c * m + i]);
+    acc = group_sum(acc);
+    if (gl == 0) nrm[c] = acc;
   }
   __syncthreads();
 }
@@ -749,11 +775,11 @@ __device__ __forceinline__ cd *jacobi_operand(const Layer &ly, const GateBase &g
 // squared norms in nrm).
 __device__ __forceinline__ void round_robin_pass(cd *A, double *nrm, int m, int nc, double tol,
                                                  double tiny, int &rot) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
+  const int gl = threadIdx.x & (GL - 1), slot = threadIdx.x / GL;
+  const int ns = blockDim.x / GL;
   const int np = nc + (nc & 1);
   for (int round = 0; round < np - 1; ++round) {
-    for (int k = wave; k < np / 2; k += nw) {
+    for (int k = slot; k < np / 2; k += ns) {
       int p, q;
       if (k == 0) {
         p = round;
@@ -763,7 +789,7 @@ __device__ __forceinline__ void round_robin_pass(cd *A, double *nrm, int m, int 
         q = (round - k + np - 1) % (np - 1);
       }
       if (p >= nc || q >= nc) continue;
-      jacobi_pair(A + (size_t)p * m, A + (size_t)q * m, nrm + p, nrm + q, m, lane, tol, tiny, rot);
+      jacobi_pair(A + (size_t)p * m, A + (size_t)q * m, nrm + p, nrm + q, m, gl, tol, tiny, rot);
     }
     __syncthreads();
   }
@@ -963,14 +989,14 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int round, in
   if (round == 0) {
     round_robin_pass(sA, s_nrm, m, nc, tol, tiny, rot);
   } else {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
+    const int gl = threadIdx.x & (GL - 1), slot = threadIdx.x / GL;
+    const int ns = blockDim.x / GL;
     for (int sr = 0; sr < w; ++sr) {
-      for (int t = wave; t < wI; t += nw) {
+      for (int t = slot; t < wI; t += ns) {
         const int u = (t + sr) % w;
         if (u >= wJ) continue;
         jacobi_pair(sA + (size_t)t * m, sA + (size_t)(wI + u) * m, s_nrm + t, s_nrm + wI + u, m,
-                    lane, tol, tiny, rot);
+                    gl, tol, tiny, rot);
       }
       __syncthreads();
     }
