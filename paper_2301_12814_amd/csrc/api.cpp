@@ -126,7 +126,7 @@ struct Engine {
   size_t h_cap = 0;
   // chunk-level workspace
   DBuf<BlkDesc> d_blk;
-  DBuf<int> d_rows, d_cols, d_bigl, d_perm, d_usize;
+  DBuf<int> d_rows, d_cols, d_bigl, d_perm, d_usize, d_piv;
   DBuf<double> d_sv;
   DBuf<unsigned long long> d_uval, d_ukey;
   DBuf<cd> d_A, d_A0, d_R, d_U, d_V, d_tau;
@@ -260,6 +260,7 @@ void engine_destroy(Engine &E) {
   E.d_cols.release();
   E.d_bigl.release();
   E.d_perm.release();
+  E.d_piv.release();
   E.d_usize.release();
   E.d_sv.release();
   E.d_uval.release();
@@ -596,6 +597,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     HIPCHK(E.d_R.ensure(std::max(re, 1LL), (size_t)E.pool_budget));
     HIPCHK(E.d_V.ensure(std::max(re, 1LL), (size_t)E.pool_budget));
     HIPCHK(E.d_tau.ensure(lst0));
+    HIPCHK(E.d_piv.ensure(lst0));
     HIPCHK(E.d_rotf.ensure((size_t)4 * std::max(bigb, 1)));
     if (bigb > 65535 || maxpp / 2 > 65535)
       return fail(MPO_EINVAL, "too many large sectors in one layer chunk");
@@ -623,6 +625,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     C.U = E.d_U.p;
     C.V = E.d_V.p;
     C.tau = E.d_tau.p;
+    C.piv = E.d_piv.p;
     C.rotf = E.d_rotf.p;
     C.active = E.d_active.p;
     C.total_chunks = ch;

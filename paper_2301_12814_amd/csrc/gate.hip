@@ -534,13 +534,17 @@ hipError_t launch_contract(Layer ly, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------------------
-// Householder QR of the rectangular large blocks: A = Q R with
-// Q = H_0 H_1 ... H_{n-1}, H_k = I - tau_k v_k v_k^H, v_k[0] = 1.  For the
-// column x below the diagonal, beta = -sign(Re x_0) |x|, tau = (beta - x_0) /
-// beta and v = x / (x_0 - beta) give H_k^H x = beta e_1 with beta real; the
-// trailing columns are multiplied by H_k^H.  One workgroup per block; the
-// operand is overwritten (its pristine copy stays in A0) and X = R^H (lower
-// triangle, zeros above) is written to the R pool where the Jacobi rotates it.
+// Householder QR with column pivoting of the large blocks: A P = Q R with
+// Q = H_0 H_1 ... H_{n-1}, H_k = I - tau_k v_k v_k^H, v_k[0] = 1.  Step k
+// brings the remaining column of largest norm (rows k..m-1; ties to the
+// lowest index) to position k; for that column's part x below the diagonal,
+// beta = -sign(Re x_0) |x|, tau = (beta - x_0) / beta and v = x / (x_0 - beta)
+// give H_k^H x = beta e_1 with beta real, and the trailing columns are
+// multiplied by H_k^H (their norms over rows k+1.. are recomputed exactly in
+// the same pass).  One workgroup per block; the operand is overwritten (its
+// pristine copy stays in A0), X = R^H (lower triangle) goes to the R pool
+// and the pivot order to piv (piv[k] = original column at position k).
+// The column pivoting grades R, so that the Jacobi on X needs few sweeps.
 // ----------------------------------------------------------------------------
 constexpr int QR_THREADS = 512;
 
@@ -556,13 +560,59 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly) {
   const int m = B.m, n = B.n;
   cd *A = ly.A + gb.e + B.eoff;
   cd *tau = ly.tau + gp.lst0 + B.svoff;
+  int *piv = ly.piv + gp.lst0 + B.svoff;
   extern __shared__ double s_dyn[];
-  cd *v = reinterpret_cast<cd *>(s_dyn);   // the current reflector, m - k entries
+  cd *v = reinterpret_cast<cd *>(s_dyn);             // current reflector, m - k entries
+  double *cn = reinterpret_cast<double *>(v + m);    // remaining column norms^2
   __shared__ double s_red[16];
+  __shared__ double s_bv[16];
+  __shared__ int s_bi[16];
   __shared__ cd s_tau, s_scale;
-  __shared__ int s_skip;
+  __shared__ int s_skip, s_piv;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int c = wave; c < n; c += nw) {
+    double acc = 0.0;
+    for (int y = lane; y < m; y += 64) acc += cabs2(A[(size_t)c * m + y]);
+    acc = wave_sum(acc);
+    if (lane == 0) cn[c] = acc;
+  }
+  for (int c = threadIdx.x; c < n; c += blockDim.x) piv[c] = c;
+  __syncthreads();
   for (int k = 0; k < n; ++k) {
+    // pivot: largest remaining norm, lowest index on ties
+    double bv = -1.0;
+    int bi = n;
+    for (int c = k + threadIdx.x; c < n; c += blockDim.x)
+      if (cn[c] > bv) { bv = cn[c]; bi = c; }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { s_bv[wave] = bv; s_bi[wave] = bi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double b = s_bv[0];
+      int p = s_bi[0];
+      for (int w2 = 1; w2 < nw; ++w2)
+        if (s_bv[w2] > b || (s_bv[w2] == b && s_bi[w2] < p)) { b = s_bv[w2]; p = s_bi[w2]; }
+      s_piv = p < n ? p : k;
+    }
+    __syncthreads();
+    const int p = s_piv;
+    if (p != k) {
+      for (int y = threadIdx.x; y < m; y += blockDim.x) {
+        const cd t = A[(size_t)k * m + y];
+        A[(size_t)k * m + y] = A[(size_t)p * m + y];
+        A[(size_t)p * m + y] = t;
+      }
+      if (threadIdx.x == 0) {
+        const double t = cn[k]; cn[k] = cn[p]; cn[p] = t;
+        const int ti = piv[k]; piv[k] = piv[p]; piv[p] = ti;
+      }
+      __syncthreads();
+    }
     cd *x = A + (size_t)k * m + k;
     const int len = m - k;
     double s2 = 0.0;
@@ -587,28 +637,39 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly) {
       }
     }
     __syncthreads();
-    if (s_skip) continue;
-    const cd sc = s_scale;
-    for (int y = 1 + threadIdx.x; y < len; y += blockDim.x) {
-      const cd t = cmul(x[y], sc);
-      x[y] = t;
-      v[y] = t;
+    const bool skip = s_skip != 0;
+    if (!skip) {
+      const cd sc = s_scale;
+      for (int y = 1 + threadIdx.x; y < len; y += blockDim.x) {
+        const cd t = cmul(x[y], sc);
+        x[y] = t;
+        v[y] = t;
+      }
+      if (threadIdx.x == 0) v[0] = cmk(1.0, 0.0);
     }
-    if (threadIdx.x == 0) v[0] = cmk(1.0, 0.0);
     __syncthreads();
-    const cd ct = cconj(s_tau);
+    const cd ct = skip ? cmk(0.0, 0.0) : cconj(s_tau);
     for (int j = k + 1 + wave; j < n; j += nw) {
       cd *a = A + (size_t)j * m + k;
       double wr = 0.0, wi = 0.0;
-      for (int y = lane; y < len; y += 64) {
-        const cd p = cmulc(v[y], a[y]);
-        wr += p.re;
-        wi += p.im;
+      if (!skip) {
+        for (int y = lane; y < len; y += 64) {
+          const cd q = cmulc(v[y], a[y]);
+          wr += q.re;
+          wi += q.im;
+        }
+        wr = wave_sum(wr);
+        wi = wave_sum(wi);
       }
-      wr = wave_sum(wr);
-      wi = wave_sum(wi);
       const cd f = cmul(ct, cmk(wr, wi));    // conj(tau) v^H a
-      for (int y = lane; y < len; y += 64) a[y] = csub(a[y], cmul(f, v[y]));
+      double nb = 0.0;
+      for (int y = lane; y < len; y += 64) {
+        const cd an = skip ? a[y] : csub(a[y], cmul(f, v[y]));
+        if (!skip) a[y] = an;
+        if (y >= 1) nb += cabs2(an);
+      }
+      nb = wave_sum(nb);
+      if (lane == 0) cn[j] = nb;
     }
     __syncthreads();
   }
@@ -621,8 +682,8 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly) {
 
 hipError_t launch_qr(Layer ly, int max_chi, hipStream_t s) {
   if (ly.total_blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_qr, dim3(ly.total_blocks), dim3(QR_THREADS), sizeof(cd) * (size_t)max_chi,
-                     s, ly);
+  hipLaunchKernelGGL(k_qr, dim3(ly.total_blocks), dim3(QR_THREADS),
+                     (sizeof(cd) + sizeof(double)) * (size_t)max_chi, s, ly);
   return hipGetLastError();
 }
 
@@ -1228,10 +1289,11 @@ hipError_t launch_select(Layer ly, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------------------
-// Singular vectors of the kept ranks of QR'd blocks.  With A = Q R, R = X^H
+// Singular vectors of the kept ranks of QR'd blocks.  With A P = Q R, R = X^H
 // and the Jacobi result X W = Y (orthogonal columns of norms sigma), A =
-// (Q W) Sigma (Y Sigma^-1)^H: the right singular vectors are the normalised
-// columns of Y, v_i = Y[:, perm[i]] / sigma_i, and u_i = A0 v_i / sigma_i
+// (Q W) Sigma (P Y Sigma^-1)^H: the right singular vectors are the normalised
+// columns of Y put back in the original column order, v_i[piv[x]] =
+// Y[x, perm[i]] / sigma_i, and u_i = A0 v_i / sigma_i
 // from the pristine operand.  For a self-mirror block of a Hermitian state
 // the phase of v_i is fixed first (v J-real up to a phase: bilinear sum over
 // the mirrored operand columns), which makes u_i J-real too.  One wavefront
@@ -1257,14 +1319,16 @@ __global__ __launch_bounds__(256) void k_leftvec(Layer ly) {
   const int *lst = !B.t ? ly.cols + gp.lst0 + B.coff : ly.rows + gp.lst0 + B.roff;
   const int *mx = (!B.t ? ly.mirR : ly.mirL) + gp.mir0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int *piv = ly.piv + gp.lst0 + B.svoff;
   for (int i0 = 0; i0 < B.kq; i0 += nw) {
     const int i = i0 + wave;
     cd f = cmk(1.0, 0.0);
     if (i < B.kq) {
+      // right vector of A P is Y[:, perm[i]] / sigma; of A: v[piv[x]] = that[x]
       const cd *y = Y + (size_t)perm[i] * n;
       const double s1 = 1.0 / sv[i];
       cd *v = V + (size_t)i * n;
-      for (int x = lane; x < n; x += 64) v[x] = cconj(cscale(y[x], s1));   // conj(v)
+      for (int x = lane; x < n; x += 64) v[piv[x]] = cconj(cscale(y[x], s1));   // conj(v)
     }
     __syncthreads();
     if (selfm && i < B.kq) {

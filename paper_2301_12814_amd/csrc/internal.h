@@ -93,6 +93,7 @@ struct Layer {
   cd *A0;            // pristine copies of the operands (right-vector recovery)
   cd *R;             // X = R^H of QR'd blocks, n x n (rotated by the Jacobi)
   cd *tau;           // Householder scalars (n per computed block, at lst0 + svoff)
+  int *piv;          // QR column pivots (n per computed block, at lst0 + svoff)
   cd *U;             // kept left singular vectors of QR'd blocks (at the A offset)
   cd *V;             // conjugated kept right singular vectors of QR'd blocks (at the R offset)
   int *bigl;         // per gate: local indices of its big blocks (at lst0)
