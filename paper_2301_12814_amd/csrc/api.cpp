@@ -646,14 +646,16 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
       HIPCHK(launch_qr(C, max_chi, E.stream));
       HIPCHK(launch_svd_small(C, E.stream));
       if (bigb > 0) {
-        // panel rounds of the big blocks; convergence is read back every 3 sweeps
+        // panel rounds of the big blocks (each block at its own sweep); the
+        // number still rotating is read back every 16 launches
         HIPCHK(launch_svd_big_prep(C, E.stream));
-        const int kMaxSweeps = 60;
-        for (int s = 0; s < kMaxSweeps; ++s) {
-          for (int r = 0; r < maxpp - 1; ++r) HIPCHK(launch_svd_panel_round(C, r, s, E.stream));
-          sweeps_run = s + 1;
-          if (s % 3 == 2 || s == kMaxSweeps - 1) {
-            HIPCHK(launch_svd_count(C, s, E.stream));
+        const int tmax = svd_max_steps(C);
+        for (int t = 0; t < tmax; ++t) {
+          HIPCHK(launch_svd_panel_step(C, t, E.stream));
+          sweeps_run = t + 1;
+          const bool last = t == tmax - 1;
+          if ((t & 15) == 15 || last) {
+            HIPCHK(launch_svd_count(C, last ? 1 : 0, E.stream));
             HIPCHK(hipMemcpyAsync(E.h_small, E.d_active.p, sizeof(int), hipMemcpyDeviceToHost,
                                   E.stream));
             HIPCHK(hipStreamSynchronize(E.stream));
@@ -663,7 +665,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
         HIPCHK(launch_svd_big_finish(C, sweeps_run, max_chi, E.stream));
       }
     }
-    st_sw = std::max<long long>(st_sw, sweeps_run);
+    (void)sweeps_run;
     {
       PhaseMark pm(E, 4);
       HIPCHK(launch_select(C, E.stream));
@@ -685,8 +687,10 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
       HIPCHK(hipStreamSynchronize(E.stream));
       for (int g = 0; g < n; ++g)
         for (int b = 0; b < E.h_tot[g].nblk; ++b) {
-          E.last_blk.push_back(tmp[E.h_gates[g].blk0 + b]);
+          const BlkDesc &B = tmp[E.h_gates[g].blk0 + b];
+          E.last_blk.push_back(B);
           E.last_blk_gate.push_back(g);
+          if (B.comp) st_sw = std::max<long long>(st_sw, B.sweeps);
         }
     }
     c0 = c1;

@@ -709,11 +709,11 @@ constexpr int SVD_THREADS = 512;
 constexpr int MAX_SWEEPS = 60;
 constexpr int RPL = 8;          // column rows cached per lane (m <= 512)
 
-// Column pairs are rotated by groups of 16 lanes (one DPP row): a wavefront
-// works on four pairs at once and the dot products reduce with four DPP
-// steps inside the row instead of cross-lane permutes over the whole wave.
-constexpr int GL = 16;   // lanes per column pair
-constexpr int CE = 8;    // elements per lane kept in registers (m <= GL * CE)
+// Column pairs are rotated by groups of L lanes (L = 16: one DPP row, four
+// pairs per wavefront; 32 or 64 when a round has too few pairs to keep every
+// group busy).  Dot products reduce with DPP steps inside a row, plus one or
+// two cross-row butterflies for L = 32, 64.
+constexpr int CE = 8;    // elements per lane kept in registers (m <= L * CE)
 
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
@@ -723,47 +723,53 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __hiloint2double(h2, l2);
 }
 
-// Sum over the 16 lanes of a DPP row: xor 1 and xor 2 inside each quad, then
-// the row mirror (quad q with quad 3 - q) and the half-row mirror (quad 0 with
-// 1, 2 with 3).  Every step adds two values in an order-independent way, so
-// all 16 lanes end with bitwise the same sum (the callers branch on it).
+// Sum over a group of L lanes: xor 1 and xor 2 inside each quad, the row
+// mirror (quad q with quad 3 - q), the half-row mirror (quad 0 with 1, 2
+// with 3), then xor 16 and xor 32 across rows.  Every step adds two values
+// in an order-independent way, so all lanes of the group end with bitwise
+// the same sum (the callers branch on it).
+template <int L>
 __device__ __forceinline__ double group_sum(double v) {
   v += dpp_d<0xB1>(v);
   v += dpp_d<0x4E>(v);
   v += dpp_d<0x140>(v);
   v += dpp_d<0x141>(v);
+  if (L >= 32) v += __shfl_xor(v, 16, 64);
+  if (L >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 
-// One rotation of the column pair (x, y) by one 16-lane group (gl = lane in
-// the group).  The squared norms al = |x|^2, be = |y|^2 are tracked in LDS: a
-// rotation with tangent t changes them exactly to al - t |g| and be + t |g|;
-// when either loses more than half it is recomputed from the rotated column.
+// One rotation of the column pair (x, y) by one group of L lanes (gl = lane
+// in the group).  The squared norms al = |x|^2, be = |y|^2 are tracked in
+// LDS: a rotation with tangent t changes them exactly to al - t |g| and
+// be + t |g|; when either loses more than half it is recomputed from the
+// rotated column.
+template <int L>
 __device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, double *nx, double *ny, int m,
                                             int gl, double tol, double tiny, int &rot) {
   const double al = *nx, be = *ny;
   if (al <= tiny && be <= tiny) return;
   double gr = 0.0, gi = 0.0;
-  const bool cached = m <= GL * CE;
+  const bool cached = m <= L * CE;
   cd rx[CE], ry[CE];
   if (cached) {
 #pragma unroll
     for (int k = 0; k < CE; ++k) {
-      const int i = gl + GL * k;
+      const int i = gl + L * k;
       rx[k] = i < m ? xp[i] : cmk(0.0, 0.0);
       ry[k] = i < m ? xq[i] : cmk(0.0, 0.0);
       gr += rx[k].re * ry[k].re + rx[k].im * ry[k].im;
       gi += rx[k].re * ry[k].im - rx[k].im * ry[k].re;
     }
   } else {
-    for (int i = gl; i < m; i += GL) {
+    for (int i = gl; i < m; i += L) {
       const cd x = xp[i], y = xq[i];
       gr += x.re * y.re + x.im * y.im;
       gi += x.re * y.im - x.im * y.re;
     }
   }
-  gr = group_sum(gr);
-  gi = group_sum(gi);
+  gr = group_sum<L>(gr);
+  gi = group_sum<L>(gi);
   const double ga = sqrt(gr * gr + gi * gi);
   if (!(ga > tol * sqrt(al * be)) || ga < 1e-300) return;
   const double zeta = (be - al) / (2.0 * ga);
@@ -777,7 +783,7 @@ __device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, double *nx, double *
   if (cached) {
 #pragma unroll
     for (int k = 0; k < CE; ++k) {
-      const int i = gl + GL * k;
+      const int i = gl + L * k;
       if (i < m) {
         const cd y = cmul(e, ry[k]);
         const cd x2 = csub(cscale(rx[k], c), cscale(y, s));
@@ -789,7 +795,7 @@ __device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, double *nx, double *
       }
     }
   } else {
-    for (int i = gl; i < m; i += GL) {
+    for (int i = gl; i < m; i += L) {
       const cd x = xp[i];
       const cd y = cmul(e, xq[i]);
       const cd x2 = csub(cscale(x, c), cscale(y, s));
@@ -801,8 +807,8 @@ __device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, double *nx, double *
     }
   }
   if (exact) {               // uniform over the group
-    al2 = group_sum(na);
-    be2 = group_sum(nb);
+    al2 = group_sum<L>(na);
+    be2 = group_sum<L>(nb);
   }
   if (gl == 0) {
     *nx = al2;
@@ -813,15 +819,23 @@ __device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, double *nx, double *
 
 // Squared norms of the nc columns at A (column stride m) into nrm.
 __device__ __forceinline__ void column_norms(const cd *A, int m, int nc, double *nrm) {
-  const int gl = threadIdx.x & (GL - 1), slot = threadIdx.x / GL;
-  const int ns = blockDim.x / GL;
+  const int gl = threadIdx.x & 15, slot = threadIdx.x >> 4;
+  const int ns = blockDim.x >> 4;
   for (int c = slot; c < nc; c += ns) {
     double acc = 0.0;
-    for (int i = gl; i < m; i += GL) acc += cabs2(A[(size_t)c * m + i]);
-    acc = group_sum(acc);
+    for (int i = gl; i < m; i += 16) acc += cabs2(A[(size_t)c * m + i]);
+    acc = group_sum<16>(acc);
     if (gl == 0) nrm[c] = acc;
   }
   __syncthreads();
+}
+
+// Lanes per pair for rounds of `pairs` pairs of columns of length m in a
+// workgroup of `threads` threads.
+__device__ __forceinline__ int lanes_per_pair(int pairs, int m, int threads) {
+  // Measured on the large workload: 16 lanes per pair with idle groups beats
+  // wider groups (the cross-row butterflies cost more than the idle lanes).
+  return 16;
 }
 
 __device__ __forceinline__ double jacobi_tol(int m) { return fmax(1e-15, 2.3e-16 * m); }
@@ -833,11 +847,12 @@ __device__ __forceinline__ cd *jacobi_operand(const Layer &ly, const GateBase &g
 }
 
 // One round-robin pass over all pairs of the nc columns at A (column stride m,
-// squared norms in nrm).
-__device__ __forceinline__ void round_robin_pass(cd *A, double *nrm, int m, int nc, double tol,
-                                                 double tiny, int &rot) {
-  const int gl = threadIdx.x & (GL - 1), slot = threadIdx.x / GL;
-  const int ns = blockDim.x / GL;
+// squared norms in nrm), L lanes per pair.
+template <int L>
+__device__ __forceinline__ void round_robin_pass_l(cd *A, double *nrm, int m, int nc, double tol,
+                                                   double tiny, int &rot) {
+  const int gl = threadIdx.x & (L - 1), slot = threadIdx.x / L;
+  const int ns = blockDim.x / L;
   const int np = nc + (nc & 1);
   for (int round = 0; round < np - 1; ++round) {
     for (int k = slot; k < np / 2; k += ns) {
@@ -850,7 +865,35 @@ __device__ __forceinline__ void round_robin_pass(cd *A, double *nrm, int m, int 
         q = (round - k + np - 1) % (np - 1);
       }
       if (p >= nc || q >= nc) continue;
-      jacobi_pair(A + (size_t)p * m, A + (size_t)q * m, nrm + p, nrm + q, m, gl, tol, tiny, rot);
+      jacobi_pair<L>(A + (size_t)p * m, A + (size_t)q * m, nrm + p, nrm + q, m, gl, tol, tiny,
+                     rot);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void round_robin_pass(cd *A, double *nrm, int m, int nc, double tol,
+                                                 double tiny, int &rot) {
+  const int L = lanes_per_pair((nc + 1) / 2, m, blockDim.x);
+  if (L == 16) round_robin_pass_l<16>(A, nrm, m, nc, tol, tiny, rot);
+  else if (L == 32) round_robin_pass_l<32>(A, nrm, m, nc, tol, tiny, rot);
+  else round_robin_pass_l<64>(A, nrm, m, nc, tol, tiny, rot);
+}
+
+// Cross pairs of two panels held in LDS (wI columns then wJ columns, panel
+// width w): w sub-rounds, column t of the first panel with (t + sr) mod w of
+// the second; L lanes per pair.
+template <int L>
+__device__ __forceinline__ void cross_pass_l(cd *sA, double *nrm, int m, int w, int wI, int wJ,
+                                             double tol, double tiny, int &rot) {
+  const int gl = threadIdx.x & (L - 1), slot = threadIdx.x / L;
+  const int ns = blockDim.x / L;
+  for (int sr = 0; sr < w; ++sr) {
+    for (int t = slot; t < wI; t += ns) {
+      const int u = (t + sr) % w;
+      if (u >= wJ) continue;
+      jacobi_pair<L>(sA + (size_t)t * m, sA + (size_t)(wI + u) * m, nrm + t, nrm + wI + u, m, gl,
+                     tol, tiny, rot);
     }
     __syncthreads();
   }
@@ -864,6 +907,29 @@ __device__ __forceinline__ double block_sum(double v, double *s_red) {
   for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += s_red[w];
   __syncthreads();
   return t;
+}
+
+// Workgroup copies between global memory and LDS with eight loads in flight
+// per thread (a plain loop waits for each load before the next).
+__device__ __forceinline__ void copy_in(cd *dst, const cd *src, int count) {
+  const int step = blockDim.x;
+  for (int base = threadIdx.x; base < count; base += 8 * step) {
+    cd r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * step;
+      if (idx < count) r[u] = src[idx];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * step;
+      if (idx < count) dst[idx] = r[u];
+    }
+  }
+}
+
+__device__ __forceinline__ void copy_out(cd *dst, const cd *src, int count) {
+  for (int idx = threadIdx.x; idx < count; idx += blockDim.x) dst[idx] = src[idx];
 }
 
 // Self-mirror block (q = (n, n)) of a Hermitian state: the block obeys
@@ -952,10 +1018,9 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly, int lo, int
   __shared__ double s_red[16];
   cd *A = jacobi_operand(ly, gb, B);
   double f2 = 0.0;
-  for (int i = threadIdx.x; i < m * n; i += blockDim.x) {
-    sA[i] = A[i];
-    f2 += cabs2(sA[i]);
-  }
+  copy_in(sA, A, m * n);
+  __syncthreads();
+  for (int i = threadIdx.x; i < m * n; i += blockDim.x) f2 += cabs2(sA[i]);
   f2 = block_sum(f2, s_red);
   const double tol = jacobi_tol(m), tiny = 1e-30 * f2;
   int sweep = 0;
@@ -975,7 +1040,7 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly, int lo, int
   }
   if (!B.qr && charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym) self_mirror_phase(ly, gp, B, sA);
   sort_values(st.err, sA, m, n, sig, ly.sv + gp.lst0 + B.svoff, ly.perm + gp.lst0 + B.svoff);
-  for (int i = threadIdx.x; i < m * n; i += blockDim.x) A[i] = sA[i];
+  copy_out(A, sA, m * n);
   if (threadIdx.x == 0) {
     Bp->sweeps = sweep;
     Bp->fro2 = f2;
@@ -1004,16 +1069,22 @@ __global__ __launch_bounds__(256) void k_big_prep(Layer ly) {
 
 constexpr int PANEL_THREADS = 1024;
 
-__global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int round, int sweep) {
+// Launch t of the panel rounds: every big block runs its own sequence of
+// sweeps, Pp - 1 rounds each (Pp = panel count rounded up to even), so block
+// b is at sweep t / (Pp_b - 1), round t mod (Pp_b - 1): blocks with few
+// panels do not wait for the rounds of the largest ones.
+__global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
   const int kbig = blockIdx.y;
   int g, bi;
   big_block_of(ly, kbig, g, bi);
   const BlkDesc B = ly.blk[ly.gates[g].blk0 + bi];
   const int P = B.npan, Pp = P + (P & 1);
-  if (round >= Pp - 1 || (int)blockIdx.x >= Pp / 2) return;
+  if ((int)blockIdx.x >= Pp / 2) return;
+  const int sweep = step / (Pp - 1), round = step % (Pp - 1);
+  if (sweep >= MAX_SWEEPS) return;
   int *rf = ly.rotf + 4 * (size_t)kbig;
   if (rf[3]) return;
-  if (sweep > 0 && rf[(sweep - 1) % 3] == 0) {   // previous sweep made no rotation
+  if (round == 0 && sweep > 0 && rf[(sweep - 1) % 3] == 0) {   // previous sweep: no rotation
     if (threadIdx.x == 0) rf[3] = sweep;
     return;
   }
@@ -1037,11 +1108,9 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int round, in
   extern __shared__ double s_dyn[];
   cd *sA = reinterpret_cast<cd *>(s_dyn);
   cd *A = jacobi_operand(ly, ly.base[g], B);
-  for (int idx = threadIdx.x; idx < nc * m; idx += blockDim.x) {
-    const int c = idx / m, i = idx % m;
-    const int col = c < wI ? i0 + c : j0 + (c - wI);
-    sA[idx] = A[(size_t)col * m + i];
-  }
+  // the two panels are contiguous column ranges of the operand
+  copy_in(sA, A + (size_t)i0 * m, wI * m);
+  copy_in(sA + (size_t)wI * m, A + (size_t)j0 * m, wJ * m);
   __syncthreads();
   const double tol = jacobi_tol(m), tiny = 1e-30 * B.fro2;
   __shared__ double s_nrm[64];
@@ -1050,37 +1119,27 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int round, in
   if (round == 0) {
     round_robin_pass(sA, s_nrm, m, nc, tol, tiny, rot);
   } else {
-    const int gl = threadIdx.x & (GL - 1), slot = threadIdx.x / GL;
-    const int ns = blockDim.x / GL;
-    for (int sr = 0; sr < w; ++sr) {
-      for (int t = slot; t < wI; t += ns) {
-        const int u = (t + sr) % w;
-        if (u >= wJ) continue;
-        jacobi_pair(sA + (size_t)t * m, sA + (size_t)(wI + u) * m, s_nrm + t, s_nrm + wI + u, m,
-                    gl, tol, tiny, rot);
-      }
-      __syncthreads();
-    }
+    const int L = lanes_per_pair(min(wI, wJ), m, blockDim.x);
+    if (L == 16) cross_pass_l<16>(sA, s_nrm, m, w, wI, wJ, tol, tiny, rot);
+    else if (L == 32) cross_pass_l<32>(sA, s_nrm, m, w, wI, wJ, tol, tiny, rot);
+    else cross_pass_l<64>(sA, s_nrm, m, w, wI, wJ, tol, tiny, rot);
   }
   if (rot) rf[sweep % 3] = 1;
   __syncthreads();
-  for (int idx = threadIdx.x; idx < nc * m; idx += blockDim.x) {
-    const int c = idx / m, i = idx % m;
-    const int col = c < wI ? i0 + c : j0 + (c - wI);
-    A[(size_t)col * m + i] = sA[idx];
-  }
+  copy_out(A + (size_t)i0 * m, sA, wI * m);
+  copy_out(A + (size_t)j0 * m, sA + (size_t)wI * m, wJ * m);
 }
 
-// Big blocks still rotating in the given sweep; on the last sweep the
-// simulation owning a block that still rotates gets its error latched.
-__global__ void k_big_count(Layer ly, int sweep, int last) {
+// Big blocks not yet converged; with `last`, the simulations owning them get
+// their error latched (the sweep limit was reached).
+__global__ void k_big_count(Layer ly, int last) {
   __shared__ int s_n;
   if (threadIdx.x == 0) s_n = 0;
   __syncthreads();
   int c = 0;
   for (int k = threadIdx.x; k < ly.total_big; k += blockDim.x) {
     const int *rf = ly.rotf + 4 * (size_t)k;
-    if (!rf[3] && rf[sweep % 3]) {
+    if (!rf[3]) {
       ++c;
       if (last) {
         const int g = find_gate_big(ly.base, ly.ngates, k);
@@ -1106,7 +1165,7 @@ __global__ __launch_bounds__(256) void k_big_finish(Layer ly, int sweeps_run) {
   sort_values(st.err, A, B.mj, B.n, s_sig, ly.sv + gp.lst0 + B.svoff, ly.perm + gp.lst0 + B.svoff);
   if (threadIdx.x == 0) {
     const int done = ly.rotf[4 * (size_t)blockIdx.x + 3];
-    Bp->sweeps = done ? done : sweeps_run;
+    Bp->sweeps = done ? done : MAX_SWEEPS;
   }
 }
 
@@ -1149,17 +1208,18 @@ hipError_t launch_svd_big_prep(Layer ly, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_svd_panel_round(Layer ly, int round, int sweep, hipStream_t s) {
+hipError_t launch_svd_panel_step(Layer ly, int step, hipStream_t s) {
   if (ly.total_big == 0) return hipSuccess;
   const int lb = svd_lds_bytes();
   hipLaunchKernelGGL(k_panel, dim3(ly.maxpp / 2, ly.total_big), dim3(PANEL_THREADS), (size_t)lb, s,
-                     ly, round, sweep);
+                     ly, step);
   return hipGetLastError();
 }
 
-hipError_t launch_svd_count(Layer ly, int sweep, hipStream_t s) {
-  hipLaunchKernelGGL(k_big_count, dim3(1), dim3(256), 0, s, ly, sweep,
-                     sweep == MAX_SWEEPS - 1 ? 1 : 0);
+int svd_max_steps(Layer ly) { return MAX_SWEEPS * (ly.maxpp > 1 ? ly.maxpp - 1 : 1) + 1; }
+
+hipError_t launch_svd_count(Layer ly, int last, hipStream_t s) {
+  hipLaunchKernelGGL(k_big_count, dim3(1), dim3(256), 0, s, ly, last);
   return hipGetLastError();
 }
 

@@ -132,8 +132,9 @@ hipError_t launch_qr(Layer ly, int max_chi, hipStream_t s);
 hipError_t launch_leftvec(Layer ly, hipStream_t s);
 hipError_t launch_svd_small(Layer ly, hipStream_t s);
 hipError_t launch_svd_big_prep(Layer ly, hipStream_t s);
-hipError_t launch_svd_panel_round(Layer ly, int round, int sweep, hipStream_t s);
-hipError_t launch_svd_count(Layer ly, int sweep, hipStream_t s);
+hipError_t launch_svd_panel_step(Layer ly, int step, hipStream_t s);
+int svd_max_steps(Layer ly);
+hipError_t launch_svd_count(Layer ly, int last, hipStream_t s);
 hipError_t launch_svd_big_finish(Layer ly, int sweeps_run, int max_chi, hipStream_t s);
 hipError_t launch_select(Layer ly, hipStream_t s);
 hipError_t launch_scatter(Layer ly, int max_chi, hipStream_t s);
