@@ -107,6 +107,9 @@ int mpo_entropy(gbs_mpo *h, double *S, double *S_max_so_far);
  * Tr rho (nullable), whose deficit 1 - Tr rho is the paper's error proxy
  * (Sec. III; App. A).  The trace contracts every site with the identity and
  * the auxiliary leg with the all-ones vector.  P: host array [M*d].
+ * A truncated MPO need not be positive: at very small chi the trace can reach
+ * zero or below, and P is then Tr(rho Pi) / Tr rho as computed (unnormalised
+ * when Tr rho == 0).  MPO_ENUMERIC only for a non-finite trace.
  * Synchronises the handle's stream.
  */
 int mpo_photon_marginals(gbs_mpo *h, double *P, double *trace);
@@ -156,7 +159,8 @@ int mpo_set_profiling(gbs_mpo *h, int enable);
 int mpo_get_profile(gbs_mpo *h, double *phase_ms, long long *phase_launches, double *work);
 
 /*
- * Sector histogram of the last applied layer (synchronises).  For each block
+ * Sector histogram of the last applied layer (synchronises; still answers
+ * after a latched numeric error, which it does not report).  For each block
  * Theta(q) of every gate, 8 ints: gate index in the layer, q = (n, n'), rows r,
  * cols s, computed here (1) or derived from its mirror (0), Jacobi sweeps,
  * singular vectors kept.  out: host [8 * max_blocks]; returns the total number

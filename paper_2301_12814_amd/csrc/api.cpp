@@ -525,6 +525,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
   L.gates = E.d_gates.p;
   L.tot = E.d_tot.p;
   L.base = E.d_base.p;
+  L.panel_lds = panel_lds_bytes(max_chi);
   {
     PhaseMark pm(E, 0);
     HIPCHK(launch_fock(L, E.stream));
@@ -713,9 +714,11 @@ int readout_marginals(Engine &E, Instance &I, double *P, double *trace) {
                         E.stream));
   HIPCHK(hipMemcpyAsync(&tr, I.dTrace, sizeof(double), hipMemcpyDeviceToHost, E.stream));
   HIPCHK(hipStreamSynchronize(E.stream));
-  if (!(tr > 0.0) || !std::isfinite(tr)) return fail(MPO_ENUMERIC, "non-positive trace");
+  // A truncated MPO need not be positive: at very small chi its trace can
+  // reach zero or below; the marginals are then reported unnormalised.
+  if (!std::isfinite(tr)) return fail(MPO_ENUMERIC, "non-finite trace");
   if (P)
-    for (size_t i = 0; i < raw.size(); ++i) P[i] = raw[i] / tr;
+    for (size_t i = 0; i < raw.size(); ++i) P[i] = tr != 0.0 ? raw[i] / tr : raw[i];
   if (trace) *trace = tr;
   return MPO_OK;
 }
@@ -904,7 +907,7 @@ extern "C" int mpo_layer_stats(gbs_mpo *h, long long *stats) {
 
 extern "C" int mpo_layer_blocks(gbs_mpo *h, int max_blocks, int *out) {
   if (!h || max_blocks < 0 || (max_blocks > 0 && !out)) return fail(MPO_EINVAL, "bad argument");
-  int rc = sync_and_check(h->eng);
+  int rc = sync_and_check(h->eng, false);   // diagnostics stay readable after a numeric error
   if (rc != MPO_OK) return rc;
   const Engine &E = h->eng;
   const int total = (int)E.last_blk.size();

@@ -130,7 +130,8 @@ __host__ __device__ inline void svd_route(int m, int n, int lds_bytes, int qr_ok
 // is derived from its mirror (its mirror exists because both outer bonds are
 // mirror symmetric).
 template <bool FILL>
-__global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int lds_alloc, int qr_ok) {
+__global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_ok) {
+  const int panel_lds = ly.panel_lds;
   const int g = blockIdx.x;
   const GateParam gp = ly.gates[g];
   const State st = ly.states[gp.inst];
@@ -249,10 +250,10 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int lds_
           int qr, big, mj;
           svd_route(m, n, lds_bytes, qr_ok, qr, big, mj);
           if (qr) reb += (long long)n * n;
-          if (big && 2LL * mj * (long long)sizeof(cd) > lds_alloc) atomicOr(st.err, ERR_WORKSPACE);
+          if (big && 2LL * mj * (long long)sizeof(cd) > panel_lds) atomicOr(st.err, ERR_WORKSPACE);
           if (big) {
             ++bgb;
-            const int w = panel_width(mj, lds_bytes);
+            const int w = panel_width(mj, min(lds_bytes, panel_lds));
             const int np = (n + w - 1) / w;
             maxpp = max(maxpp, np + (np & 1));
           }
@@ -349,7 +350,7 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int lds_
         svd_route(B.m, B.n, lds_bytes, qr_ok, qr, bg, mj);
         if (qr) re = (long long)B.n * B.n;
         if (bg) {
-          w = panel_width(mj, lds_bytes);
+          w = panel_width(mj, min(lds_bytes, panel_lds));
           npan = (B.n + w - 1) / w;
         }
       }
@@ -424,13 +425,13 @@ static int svd_route_bytes() {
 
 hipError_t launch_plan_count(Layer ly, hipStream_t s) {
   hipLaunchKernelGGL(k_plan<false>, dim3(ly.ngates), dim3(1024), 0, s, ly, svd_route_bytes(),
-                     svd_lds_bytes(), g_qr_enable);
+                     g_qr_enable);
   return hipGetLastError();
 }
 
 hipError_t launch_plan_fill(Layer ly, hipStream_t s) {
   hipLaunchKernelGGL(k_plan<true>, dim3(ly.ngates), dim3(1024), 0, s, ly, svd_route_bytes(),
-                     svd_lds_bytes(), g_qr_enable);
+                     g_qr_enable);
   return hipGetLastError();
 }
 
@@ -696,9 +697,7 @@ hipError_t launch_qr(Layer ly, int max_chi, hipStream_t s) {
 // At convergence the operand is U Sigma with orthogonal columns.  The right
 // factor is not accumulated: the kept right singular vectors are recovered in
 // the scatter from the pristine operand, V[:, i] = A0^H u_i / sigma_i.
-// Pairs of columns whose squared norms are both below 1e-30 of the block's
-// squared Frobenius norm are left alone (their singular values lie far below
-// the 1e-14 rank cut).
+// Pairs with a column at the rounding floor are left alone (jacobi_floor).
 //   * k_svd_small: the whole operand in LDS, one workgroup, round-robin pairs;
 //   * big blocks: column panels of width w; each sweep is a round-robin
 //     tournament of panel pairs, one launch per round, one workgroup per panel
@@ -748,7 +747,7 @@ template <int L>
 __device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, double *nx, double *ny, int m,
                                             int gl, double tol, double tiny, int &rot) {
   const double al = *nx, be = *ny;
-  if (al <= tiny && be <= tiny) return;
+  if (fmin(al, be) <= tiny) return;
   double gr = 0.0, gi = 0.0;
   const bool cached = m <= L * CE;
   cd rx[CE], ry[CE];
@@ -830,15 +829,17 @@ __device__ __forceinline__ void column_norms(const cd *A, int m, int nc, double 
   __syncthreads();
 }
 
-// Lanes per pair for rounds of `pairs` pairs of columns of length m in a
-// workgroup of `threads` threads.
-__device__ __forceinline__ int lanes_per_pair(int pairs, int m, int threads) {
-  // Measured on the large workload: 16 lanes per pair with idle groups beats
-  // wider groups (the cross-row butterflies cost more than the idle lanes).
-  return 16;
-}
-
 __device__ __forceinline__ double jacobi_tol(int m) { return fmax(1e-15, 2.3e-16 * m); }
+
+// Rounding floor of a column's squared norm: a column of an operand with
+// squared Frobenius norm fro2 whose own squared norm is below 16 m eps^2 fro2
+// holds nothing but rounding noise, and its orthogonality to any other column
+// cannot be resolved to the relative tolerance (rotating such pairs never
+// settles).  Pairs with either column below the floor are left alone; their
+// singular values lie far below the 1e-14 rank cut.
+__device__ __forceinline__ double jacobi_floor(int m, double fro2) {
+  return 16.0 * m * (1.11e-16 * 1.11e-16) * fro2;
+}
 
 // The Jacobi operand of a computed block: R of a QR'd block, else the block.
 __device__ __forceinline__ cd *jacobi_operand(const Layer &ly, const GateBase &gb,
@@ -872,13 +873,13 @@ __device__ __forceinline__ void round_robin_pass_l(cd *A, double *nrm, int m, in
   }
 }
 
-__device__ __forceinline__ void round_robin_pass(cd *A, double *nrm, int m, int nc, double tol,
-                                                 double tiny, int &rot) {
-  const int L = lanes_per_pair((nc + 1) / 2, m, blockDim.x);
-  if (L == 16) round_robin_pass_l<16>(A, nrm, m, nc, tol, tiny, rot);
-  else if (L == 32) round_robin_pass_l<32>(A, nrm, m, nc, tol, tiny, rot);
-  else round_robin_pass_l<64>(A, nrm, m, nc, tol, tiny, rot);
-}
+// Lanes per column pair in the one-workgroup Jacobi and in the panel rounds.
+#ifndef GBS_SMALL_LANES
+#define GBS_SMALL_LANES 16
+#endif
+#ifndef GBS_PANEL_LANES
+#define GBS_PANEL_LANES 32
+#endif
 
 // Cross pairs of two panels held in LDS (wI columns then wJ columns, panel
 // width w): w sub-rounds, column t of the first panel with (t + sr) mod w of
@@ -1022,14 +1023,14 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly, int lo, int
   __syncthreads();
   for (int i = threadIdx.x; i < m * n; i += blockDim.x) f2 += cabs2(sA[i]);
   f2 = block_sum(f2, s_red);
-  const double tol = jacobi_tol(m), tiny = 1e-30 * f2;
+  const double tol = jacobi_tol(m), tiny = jacobi_floor(m, f2);
   int sweep = 0;
   if (n > 1) {
     for (sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
       if (threadIdx.x == 0) s_rot = 0;
       column_norms(sA, m, n, sig);
       int rot = 0;
-      round_robin_pass(sA, sig, m, n, tol, tiny, rot);
+      round_robin_pass_l<GBS_SMALL_LANES>(sA, sig, m, n, tol, tiny, rot);
       if (rot) s_rot = 1;
       __syncthreads();
       const int any = s_rot;
@@ -1112,17 +1113,14 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
   copy_in(sA, A + (size_t)i0 * m, wI * m);
   copy_in(sA + (size_t)wI * m, A + (size_t)j0 * m, wJ * m);
   __syncthreads();
-  const double tol = jacobi_tol(m), tiny = 1e-30 * B.fro2;
+  const double tol = jacobi_tol(m), tiny = jacobi_floor(m, B.fro2);
   __shared__ double s_nrm[64];
   column_norms(sA, m, nc, s_nrm);
   int rot = 0;
   if (round == 0) {
-    round_robin_pass(sA, s_nrm, m, nc, tol, tiny, rot);
+    round_robin_pass_l<GBS_PANEL_LANES>(sA, s_nrm, m, nc, tol, tiny, rot);
   } else {
-    const int L = lanes_per_pair(min(wI, wJ), m, blockDim.x);
-    if (L == 16) cross_pass_l<16>(sA, s_nrm, m, w, wI, wJ, tol, tiny, rot);
-    else if (L == 32) cross_pass_l<32>(sA, s_nrm, m, w, wI, wJ, tol, tiny, rot);
-    else cross_pass_l<64>(sA, s_nrm, m, w, wI, wJ, tol, tiny, rot);
+    cross_pass_l<GBS_PANEL_LANES>(sA, s_nrm, m, w, wI, wJ, tol, tiny, rot);
   }
   if (rot) rf[sweep % 3] = 1;
   __syncthreads();
@@ -1208,11 +1206,26 @@ hipError_t launch_svd_big_prep(Layer ly, hipStream_t s) {
   return hipGetLastError();
 }
 
+#ifndef GBS_PANEL_HALF_LDS
+#define GBS_PANEL_HALF_LDS 0
+#endif
+
+int panel_lds_bytes(int max_chi) {
+  const int lb = svd_lds_bytes();
+  if (!GBS_PANEL_HALF_LDS) return lb;
+  const int half = lb / 2 - 1024;
+  // two columns of the longest operand must fit at panel width 1
+  return 2 * (int)sizeof(cd) * max_chi <= half ? half : lb;
+}
+
 hipError_t launch_svd_panel_step(Layer ly, int step, hipStream_t s) {
   if (ly.total_big == 0) return hipSuccess;
   const int lb = svd_lds_bytes();
-  hipLaunchKernelGGL(k_panel, dim3(ly.maxpp / 2, ly.total_big), dim3(PANEL_THREADS), (size_t)lb, s,
-                     ly, step);
+  // half the LDS per workgroup: two panel workgroups share a CU, one loading
+  // or storing its panels while the other rotates
+  const int thr = ly.panel_lds <= lb / 2 ? PANEL_THREADS / 2 : PANEL_THREADS;
+  hipLaunchKernelGGL(k_panel, dim3(ly.maxpp / 2, ly.total_big), dim3(thr), (size_t)ly.panel_lds,
+                     s, ly, step);
   return hipGetLastError();
 }
 

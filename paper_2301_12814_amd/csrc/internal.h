@@ -101,6 +101,7 @@ struct Layer {
   int *active;       // big blocks still rotating after the latest checked sweep
   int total_big;     // big blocks in the layer
   int maxpp;         // largest even panel count in the layer
+  int panel_lds;     // LDS bytes of one panel workgroup
   double *sv;        // singular values, sorted descending per block
   int *perm;         // rank -> operand column
   unsigned long long *uval;   // selection units: value bits
@@ -134,6 +135,7 @@ hipError_t launch_svd_small(Layer ly, hipStream_t s);
 hipError_t launch_svd_big_prep(Layer ly, hipStream_t s);
 hipError_t launch_svd_panel_step(Layer ly, int step, hipStream_t s);
 int svd_max_steps(Layer ly);
+int panel_lds_bytes(int max_chi);
 hipError_t launch_svd_count(Layer ly, int last, hipStream_t s);
 hipError_t launch_svd_big_finish(Layer ly, int sweeps_run, int max_chi, hipStream_t s);
 hipError_t launch_select(Layer ly, hipStream_t s);

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgbsmpo.so")
+# GBSMPO_LIB overrides the in-tree library (variant builds of the same sources)
+LIB_PATH = os.environ.get("GBSMPO_LIB") or os.path.join(_HERE, "libgbsmpo.so")
 
 MPO_OK, MPO_EINVAL, MPO_ENOMEM, MPO_EDEVICE, MPO_ENUMERIC, MPO_EBUSY = 0, -1, -2, -3, -4, -5
 MPO_FP64, MPO_MIXED = 0, 1
