@@ -142,20 +142,28 @@ def run_batch(args, prec):
         t_adm = time.perf_counter() - t0
         print(f"admitted {len(ids)} simulations in {t_adm:.2f} s", file=sys.stderr, flush=True)
         done_at = {}
+        failed = []
         step = 0
         while len(done_at) < len(ids):
             n_act = eng.step()
             step += 1
             now = time.perf_counter() - t0
             for sid in ids:
-                if sid not in done_at and eng.result(sid) is not None:
+                if sid in done_at:
+                    continue
+                try:
+                    if eng.result(sid) is not None:
+                        done_at[sid] = now
+                except gbsmpo.GbsMpoError as e:      # retired with a device error
                     done_at[sid] = now
+                    failed.append((sid, str(e)))
             if step % 8 == 0:
                 print(f"step {step}: {n_act} running, {len(done_at)} done, {now:.1f} s",
                       file=sys.stderr, flush=True)
         elapsed = time.perf_counter() - t0
         ms, n, work = eng.profile()
-        res = [eng.result(s) for s in ids]
+        bad = {f[0] for f in failed}
+        res = [eng.result(s) for s in ids if s not in bad]
     p50, p99 = _percentiles(list(done_at.values()))
     return {
         "metric": "batched simulations/s (256 instances of the batch law)",
@@ -170,67 +178,136 @@ def run_batch(args, prec):
         "completion_s": {"p50": p50, "p99": p99},
         "engine_steps": step,
         "phase_ms": ms,
+        "failed": len(failed),
         "max_S": max(r["S_max"] for r in res),
+    }
+
+
+def run_alone(args, prec):
+    """Baseline for serving: the first --requests requests of the same stream,
+    each run alone to completion on the single-simulation path, one after
+    another (no batching, no overlap)."""
+    from paper_2301_12814_amd import gbsmpo, inputs
+    reqs = inputs.serving_requests(args.requests, args.rate)
+    times, kinds = [], []
+    t_all = time.perf_counter()
+    for k, (_, w) in enumerate(reqs):
+        U = inputs.haar_unitary(w.M, w.seed)
+        t0 = time.perf_counter()
+        layers, _ = gbsmpo.clements(U)
+        with gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi, prec) as g:
+            for L in layers:
+                g.apply_layer(*L)
+            g.entropy()
+            g.marginals()
+        times.append(time.perf_counter() - t0)
+        kinds.append("large" if w.name.endswith("large") else "batch-law")
+        print(f"alone {k} {w.name}: {times[-1]:.2f} s", file=sys.stderr, flush=True)
+    total = time.perf_counter() - t_all
+    p50, p99 = _percentiles(times)
+    big = [t for t, k in zip(times, kinds) if k == "large"]
+    return {
+        "metric": "simulations/s, each request alone (serving baseline)",
+        "value": len(times) / total, "unit": "simulations/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": total * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == gbsmpo.MPO_FP64 else "mixed",
+        "data": "synthetic (same request stream as the serving run, arrival times ignored)",
+        "config": {"workload": f"first {len(times)} requests of the serving stream, alone"},
+        "run_s": {"p50": p50, "p99": p99, "mean": total / len(times),
+                  "large_mean": (sum(big) / len(big)) if big else None, "n_large": len(big)},
     }
 
 
 def run_serve(args, prec):
     """Continuous batching: Poisson arrivals, admission by projected device
-    bytes, every step applies the next layer of every running simulation."""
+    bytes, every engine step applies the next layer of every running
+    simulation.  Two lanes, each an engine on its own HIP stream driven by its
+    own host thread, so that the work of both overlaps on the device: requests
+    with chi >= 1024 go to the heavy lane, the rest to the light lane (a light
+    request never waits for a heavy request's layer)."""
+    import threading
+    import torch
     from paper_2301_12814_amd import gbsmpo, inputs
     reqs = inputs.serving_requests(args.requests, args.rate)
     Us = [inputs.haar_unitary(w.M, w.seed) for _, w in reqs]
-    lat, queue_wait = [], []
-    waiting = []                       # indices admitted to the queue, not yet on the device
-    running = {}                       # sid -> request index
-    nxt = 0
-    with gbsmpo.Engine(precision=prec) as eng:
-        t0 = time.perf_counter()
-        admitted_at = {}
-        while nxt < len(reqs) or waiting or running:
-            now = time.perf_counter() - t0
-            while nxt < len(reqs) and reqs[nxt][0] <= now:
-                waiting.append(nxt)
-                nxt += 1
-            while waiting:
-                k = waiting[0]
-                w = reqs[k][1]
-                try:
-                    sid = eng.add(w.M, w.r, w.eta, w.d, w.chi, Us[k])
-                except gbsmpo.GbsMpoError as e:
-                    if e.code == gbsmpo.MPO_ENOMEM and running:
-                        break                  # wait for memory to free up
-                    raise
-                waiting.pop(0)
-                running[sid] = k
-                admitted_at[k] = time.perf_counter() - t0
-            if not running:
-                if nxt < len(reqs):            # idle until the next arrival
-                    time.sleep(max(0.0, reqs[nxt][0] - (time.perf_counter() - t0)))
-                continue
-            eng.step()
-            now = time.perf_counter() - t0
-            for sid in list(running):
-                r = eng.result(sid)
-                if r is not None:
-                    k = running.pop(sid)
-                    lat.append(now - reqs[k][0])
-                    queue_wait.append(admitted_at[k] - reqs[k][0])
-                    eng.release(sid)
-                    if len(lat) % 10 == 0:
-                        print(f"{len(lat)} done at {now:.1f} s, {len(running)} running, "
-                              f"{len(waiting)} waiting", file=sys.stderr, flush=True)
-        elapsed = time.perf_counter() - t0
-    p50, p99 = _percentiles(lat)
+    free, _ = torch.cuda.mem_get_info()
+    heavy = [k for k, (_, w) in enumerate(reqs) if w.chi >= 1024]
+    light = [k for k, (_, w) in enumerate(reqs) if w.chi < 1024]
+    lat = {}                 # request -> latency
+    wait = {}                # request -> queueing delay before admission
+    failed = []
+    t0 = time.perf_counter()
+    lock = threading.Lock()
+
+    def lane(order, budget, name):
+        nxt, waiting, running = 0, [], {}
+        with gbsmpo.Engine(precision=prec, budget_bytes=budget) as eng:
+            while nxt < len(order) or waiting or running:
+                now = time.perf_counter() - t0
+                while nxt < len(order) and reqs[order[nxt]][0] <= now:
+                    waiting.append(order[nxt])
+                    nxt += 1
+                while waiting:
+                    k = waiting[0]
+                    w = reqs[k][1]
+                    try:
+                        sid = eng.add(w.M, w.r, w.eta, w.d, w.chi, Us[k])
+                    except gbsmpo.GbsMpoError as e:
+                        if e.code == gbsmpo.MPO_ENOMEM and running:
+                            break              # wait for memory to free up
+                        raise
+                    waiting.pop(0)
+                    running[sid] = k
+                    wait[k] = time.perf_counter() - t0 - reqs[k][0]
+                if not running:
+                    if nxt < len(order):       # idle until the next arrival
+                        time.sleep(max(0.0, reqs[order[nxt]][0] - (time.perf_counter() - t0)))
+                    continue
+                eng.step()
+                now = time.perf_counter() - t0
+                for sid in list(running):
+                    try:
+                        r = eng.result(sid)
+                    except gbsmpo.GbsMpoError:       # retired with a device error
+                        r = "failed"
+                        failed.append(running[sid])
+                    if r is not None:
+                        k = running.pop(sid)
+                        eng.release(sid)
+                        with lock:
+                            lat[k] = now - reqs[k][0]
+                            if len(lat) % 10 == 0:
+                                print(f"{len(lat)} done at {now:.1f} s ({name} lane: "
+                                      f"{len(running)} running, {len(waiting)} waiting)",
+                                      file=sys.stderr, flush=True)
+
+    th = [threading.Thread(target=lane, args=(light, int(0.45 * free), "light")),
+          threading.Thread(target=lane, args=(heavy, int(0.40 * free), "heavy"))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    elapsed = time.perf_counter() - t0
+    all_l = list(lat.values())
+    p50, p99 = _percentiles(all_l)
+    lt = [lat[k] for k in light if k in lat]
+    hv = [lat[k] for k in heavy if k in lat]
     return {
         "metric": "served simulations/s with p50/p99 latency (continuous batching)",
-        "value": len(lat) / elapsed, "unit": "simulations/s", "n_gpus": 1, "steps": 1,
+        "value": len(all_l) / elapsed, "unit": "simulations/s", "n_gpus": 1, "steps": 1,
         "warmup": 0, "ms_per_step": elapsed * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if prec == gbsmpo.MPO_FP64 else "mixed",
         "data": "synthetic (Poisson arrivals seed 5, batch law + 5% M=96 d=10 chi=1024)",
-        "config": {"workload": f"{len(reqs)} requests at {args.rate} req/s"},
-        "latency_s": {"p50": p50, "p99": p99, "max": max(lat)},
-        "queue_wait_s": {"p50": _percentiles(queue_wait)[0], "p99": _percentiles(queue_wait)[1]},
+        "config": {"workload": f"{len(reqs)} requests at {args.rate} req/s "
+                               f"({len(light)} batch-law, {len(heavy)} large)"},
+        "latency_s": {"p50": p50, "p99": p99, "max": max(all_l),
+                      "batch_law_p50": _percentiles(lt)[0] if lt else None,
+                      "batch_law_p99": _percentiles(lt)[1] if lt else None,
+                      "large_p50": _percentiles(hv)[0] if hv else None,
+                      "large_p99": _percentiles(hv)[1] if hv else None},
+        "queue_wait_s": {"p50": _percentiles(list(wait.values()))[0],
+                         "p99": _percentiles(list(wait.values()))[1]},
+        "failed": len(failed),
     }
 
 
@@ -263,8 +340,8 @@ def main():
         __graft_entry__.build()
 
     prec = gbsmpo.MPO_FP64 if args.precision == "fp64" else gbsmpo.MPO_MIXED
-    if args.workload in ("batch", "serve"):
-        out = run_batch(args, prec) if args.workload == "batch" else run_serve(args, prec)
+    if args.workload in ("batch", "serve", "alone"):
+        out = {"batch": run_batch, "serve": run_serve, "alone": run_alone}[args.workload](args, prec)
         print(json.dumps(out), flush=True)
         return
     w = inputs.workload(args.workload)

@@ -1168,17 +1168,17 @@ __global__ __launch_bounds__(256) void k_big_finish(Layer ly, int sweeps_run) {
 }
 
 int svd_lds_bytes() {
-  static int bytes = -1;
-  if (bytes < 0) {
+  // initialised once per process (thread-safe static initialisation)
+  static const int bytes = [] {
     int dev = 0, v = 0;
     hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
       v = 65536;
-    bytes = (v > 163840 ? 163840 : v) - 2048;   // room for static LDS
-    hipFuncSetAttribute((const void *)k_svd_small, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        bytes);
-    hipFuncSetAttribute((const void *)k_panel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  }
+    const int b = (v > 163840 ? 163840 : v) - 2048;   // room for static LDS
+    hipFuncSetAttribute((const void *)k_svd_small, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    hipFuncSetAttribute((const void *)k_panel, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    return b;
+  }();
   return bytes;
 }
 

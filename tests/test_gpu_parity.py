@@ -317,3 +317,29 @@ def test_gpu_large_qr_route_matches_unreduced(svd_route):
     for b in range(w.M + 1):
         assert_bond_equal(b1[b][0], b1[b][1], b2[b][0], b2[b][1], f"bond {b}")
     assert np.abs(S1 - S2).max() < 1e-10
+
+
+@pytest.mark.parametrize("idx", [156, 82])
+def test_gpu_noise_level_sectors_converge(idx):
+    """Regression: instances of the batch law whose first gate carries a
+    self-mirror sector with columns at the rounding floor (d=10, chi=64) run
+    to the end without a Jacobi non-convergence error; trace and marginals
+    stay finite and every bond keeps mirror-symmetric spectra."""
+    w = inputs.batch_workloads(idx + 1)[idx]
+    say("noise-level instance", idx, w.M, w.d, w.chi)
+    layers, _ = gbsmpo.clements(inputs.haar_unitary(w.M, w.seed))
+    with gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi) as g:
+        for L in layers:
+            g.apply_layer(*L)
+        S, smax = g.entropy()
+        P, tr = g.marginals()
+        assert np.isfinite(smax) and np.all(np.isfinite(S))
+        assert np.isfinite(tr) and np.all(np.isfinite(P))
+        for b in range(1, w.M):
+            lam, ch = g.bond(b)
+            key = {(int(a), int(c)): np.sort(lam[(ch[:, 0] == a) & (ch[:, 1] == c)])
+                   for a, c in set(map(tuple, ch.tolist()))}
+            for (a, c), v in key.items():
+                m = key.get((c, a))
+                assert m is not None and len(m) == len(v), (b, a, c)
+                assert np.allclose(v, m, rtol=1e-12, atol=1e-14 * lam.max()), (b, a, c)
