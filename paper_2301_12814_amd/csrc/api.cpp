@@ -119,7 +119,7 @@ struct Engine {
   DBuf<GateTot> d_tot;
   DBuf<GateBase> d_base;
   DBuf<cd> d_fock;
-  DBuf<int> d_mirL, d_mirR;
+  DBuf<int> d_mirL, d_mirR, d_ctab;
   GateParam *h_gates = nullptr;
   GateTot *h_tot = nullptr;
   GateBase *h_base = nullptr;
@@ -255,6 +255,7 @@ void engine_destroy(Engine &E) {
   E.d_fock.release();
   E.d_mirL.release();
   E.d_mirR.release();
+  E.d_ctab.release();
   E.d_blk.release();
   E.d_rows.release();
   E.d_cols.release();
@@ -555,6 +556,18 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     E.work[2] += (double)st_sv;
     E.work[3] += 1.0;
   }
+  // centre-bond run tables of every gate
+  long long ct = 0;
+  for (int g = 0; g < n; ++g) {
+    const GateTot &t = E.h_tot[g];
+    E.h_gates[g].ct0 = ct;
+    if (t.c1hi >= 0) ct += (long long)(t.c0hi - t.c0lo + 2) * (t.c1hi + 2);
+  }
+  HIPCHK(E.d_ctab.ensure(std::max(ct, 1LL)));
+  HIPCHK(hipMemcpyAsync(E.d_gates.p, E.h_gates, sizeof(GateParam) * n, hipMemcpyHostToDevice,
+                        E.stream));
+  L.ctab = E.d_ctab.p;
+  HIPCHK(launch_ctab(L, E.stream));
   E.last_blk.clear();
   E.last_blk_gate.clear();
   int c0 = 0;

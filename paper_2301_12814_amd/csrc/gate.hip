@@ -145,11 +145,11 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
   const double *lamL = st.lam + (size_t)j * chi;
   const double *lamR = st.lam + (size_t)(j + 2) * chi;
   __shared__ int s_sym;
-  __shared__ int s_min1L, s_max1L, s_min1R, s_max1R;
+  __shared__ int s_min1L, s_max1L, s_min1R, s_max1R, s_max1C;
   __shared__ long long s_scan[17];
   __shared__ int s_iscan[17];
   if (threadIdx.x == 0) {
-    s_min1L = 1 << 30; s_max1L = -1; s_min1R = 1 << 30; s_max1R = -1;
+    s_min1L = 1 << 30; s_max1L = -1; s_min1R = 1 << 30; s_max1R = -1; s_max1C = -1;
     s_sym = 1;
   }
   __syncthreads();
@@ -190,11 +190,25 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
     }
     atomicMin(&s_min1R, mn);
     atomicMax(&s_max1R, mx);
+    if (!FILL) {
+      const int DC = st.dim[j + 1];
+      const int *cC = st.chg + (size_t)(j + 1) * chi;
+      mx = -1;
+      for (int c = threadIdx.x; c < DC; c += blockDim.x) mx = max(mx, charge_np(cC[c]));
+      atomicMax(&s_max1C, mx);
+    }
   }
   __syncthreads();
   const int sym = FILL ? ly.tot[g].sym : s_sym;
   GateTot tot = {};
   tot.sym = sym;
+  {
+    const int DC = st.dim[j + 1];
+    const int *cC = st.chg + (size_t)(j + 1) * chi;
+    tot.c0lo = DC > 0 ? charge_n(cC[0]) : 0;
+    tot.c0hi = DC > 0 ? charge_n(cC[DC - 1]) : -1;
+    tot.c1hi = DC > 0 ? s_max1C : -1;
+  }
   if (DL == 0 || DR == 0) {
     if (!FILL && threadIdx.x == 0) ly.tot[g] = tot;
     return;
@@ -505,12 +519,18 @@ __global__ __launch_bounds__(CHUNK) void k_contract(Layer ly) {
   const cd *Ga = st.gam + (size_t)j * chi * chi + (size_t)a * chi;
   const cd *Gb = st.gam + (size_t)(j + 1) * chi * chi + b;
   const double *lC = st.lam + (size_t)(j + 1) * chi;
-  const int p0lo = max(cb0, ca0 - d + 1), p0hi = min(cb0 + d - 1, ca0);
-  const int p1lo = max(cb1, ca1 - d + 1), p1hi = min(cb1 + d - 1, ca1);
+  const GateTot gt = ly.tot[g];
+  const int W1 = gt.c1hi + 2;
+  const int *T = ly.ctab + gp.ct0;
+  const int p0lo = max(max(cb0, ca0 - d + 1), gt.c0lo), p0hi = min(min(cb0 + d - 1, ca0), gt.c0hi);
+  const int p1lo = min(max(cb1, ca1 - d + 1), W1 - 1), p1hi = min(min(cb1 + d - 1, ca1) + 1, W1 - 1);
+  (void)DC;
   cd acc = cmk(0.0, 0.0);
   for (int p0 = p0lo; p0 <= p0hi; ++p0) {
-    const int al0 = lower_bound(cC, DC, pack_charge(p0, p1lo));
-    const int al1 = lower_bound(cC, DC, pack_charge(p0, p1hi + 1));
+    // bond-C indices with charge (p0, p1), p1 in [p1lo, p1hi): one table run
+    const int *Tp = T + (size_t)(p0 - gt.c0lo) * W1;
+    const int al0 = Tp[p1lo];
+    const int al1 = Tp[p1hi];
     const cd wk = tab[((size_t)n0 * d + i0) * d + (ca0 - p0)];
     for (int al = al0; al < al1; ++al) {
       const int p1 = charge_np(cC[al]);
@@ -526,6 +546,30 @@ __global__ __launch_bounds__(CHUNK) void k_contract(Layer ly) {
                          : (size_t)ia * B.m + ib;      // Theta^T, m = s rows
   ly.A[gb.e + B.eoff + at] = acc;
   ly.A0[gb.e + B.eoff + at] = acc;
+}
+
+// Centre-bond run table of every gate: T[x][y] = first index of the sorted
+// centre bond with charge >= (c0lo + x, y).  The indices with charge (p0, p1)
+// for p1 in [a, b) are then [T[p0 - c0lo][a], T[p0 - c0lo][b]).
+__global__ __launch_bounds__(256) void k_ctab(Layer ly) {
+  const int g = blockIdx.x;
+  const GateParam gp = ly.gates[g];
+  const GateTot gt = ly.tot[g];
+  if (gt.c1hi < 0) return;
+  const State st = ly.states[gp.inst];
+  const int DC = st.dim[gp.site + 1];
+  const int *cC = st.chg + (size_t)(gp.site + 1) * st.chi;
+  const int W0 = gt.c0hi - gt.c0lo + 2, W1 = gt.c1hi + 2;
+  int *T = ly.ctab + gp.ct0;
+  for (int idx = threadIdx.x; idx < W0 * W1; idx += blockDim.x) {
+    const int x = idx / W1, y = idx % W1;
+    T[idx] = lower_bound(cC, DC, pack_charge(gt.c0lo + x, y));
+  }
+}
+
+hipError_t launch_ctab(Layer ly, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctab, dim3(ly.ngates), dim3(256), 0, s, ly);
+  return hipGetLastError();
 }
 
 hipError_t launch_contract(Layer ly, hipStream_t s) {

@@ -19,6 +19,7 @@ struct GateParam {
   long long mir0;  // first entry of the gate's mirror maps (chi of the instance)
   long long blk0;  // first block descriptor of the gate (set per chunk)
   long long lst0;  // first entry of the gate's list regions (set per chunk)
+  long long ct0;   // first entry of the gate's centre-bond run table
 };
 
 // One charge sector Theta(q) of one gate (App. D, Eq. theta).
@@ -53,6 +54,7 @@ struct GateTot {
   int nbig, maxpp;    // big blocks, largest even panel count among them
   long long elems;
   long long relems;   // R factors of the QR'd blocks (sum of n^2)
+  int c0lo, c0hi, c1hi;  // centre bond: range of n, largest n' (-1: empty bond)
   double svd_flops;   // sum over blocks of 16 m n^2 + 36 n^3 (complex SVD convention)
 };
 
@@ -89,6 +91,8 @@ struct Layer {
   GateBase *base;    // ngates
   int *rows, *cols;  // per-gate row / column index lists (at lst0)
   int *mirL, *mirR;  // per gate: mirror index on the left / right bond, -1 if none (at mir0)
+  int *ctab;         // per gate (at ct0): first centre-bond index with charge >= (c0lo + x, y),
+                     // [x][y] for x in [0, c0hi - c0lo + 2), y in [0, c1hi + 2)
   cd *A;             // sector operands (overwritten by U * Sigma)
   cd *A0;            // pristine copies of the operands (right-vector recovery)
   cd *R;             // X = R^H of QR'd blocks, n x n (rotated by the Jacobi)
@@ -128,6 +132,7 @@ hipError_t launch_init_gamma(State st, const double *rho, const double *A, hipSt
 hipError_t launch_fock(Layer ly, hipStream_t s);
 hipError_t launch_plan_count(Layer ly, hipStream_t s);
 hipError_t launch_plan_fill(Layer ly, hipStream_t s);
+hipError_t launch_ctab(Layer ly, hipStream_t s);
 hipError_t launch_contract(Layer ly, hipStream_t s);
 hipError_t launch_qr(Layer ly, int max_chi, hipStream_t s);
 hipError_t launch_leftvec(Layer ly, hipStream_t s);
