@@ -422,7 +422,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "bf16x3/f32-acc + f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32 Jacobi + f64",
         "data": "synthetic (seeded Haar interferometer, squeezed inputs)",
         "config": {"workload": f"{w.name}: M={w.M}, r={w.r[0]}, eta={w.eta}, d={w.d}, "
                                f"chi={w.chi}, Haar seed {w.seed}, {n_gates} beam splitters in "
@@ -431,6 +431,17 @@ def main():
         "phase_ms_per_step": {k: v / args.steps for k, v in phase_ms.items() if k != "unused"},
         "result": {"S_max": smax, "trace": tr},
     }
+    if prec == gbsmpo.MPO_MIXED:
+        # the FP64 GPU path on the same seed, untimed, as the reference
+        import numpy as np
+        with gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi, gbsmpo.MPO_FP64) as g64:
+            evolve(g64)
+            S64, smax64 = g64.entropy()
+            P64, tr64 = g64.marginals()
+        out["error_vs_fp64"] = {"ee_max_abs": float(np.abs(S - S64).max()),
+                                "S_max_abs": abs(smax - smax64),
+                                "marginal_max_abs": float(np.abs(P - P64).max()),
+                                "trace_abs": abs(tr - tr64)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

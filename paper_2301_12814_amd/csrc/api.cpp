@@ -527,6 +527,8 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
   L.tot = E.d_tot.p;
   L.base = E.d_base.p;
   L.panel_lds = panel_lds_bytes(max_chi);
+  L.mixed = E.precision == MPO_MIXED ? 1 : 0;
+  L.esz = L.mixed ? 8 : 16;
   {
     PhaseMark pm(E, 0);
     HIPCHK(launch_fock(L, E.stream));

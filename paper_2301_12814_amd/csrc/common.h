@@ -37,6 +37,33 @@ __host__ __device__ inline void cfma(cd &acc, cd a, cd b) {
   acc.im = fma(a.re, b.im, fma(a.im, b.re, acc.im));
 }
 
+// Single-precision complex (the mixed-precision Jacobi's LDS operand).
+struct cf {
+  float re, im;
+};
+
+__host__ __device__ inline cf cfmk(float r, float i) { return cf{r, i}; }
+__host__ __device__ inline cf cadd(cf a, cf b) { return cf{a.re + b.re, a.im + b.im}; }
+__host__ __device__ inline cf csub(cf a, cf b) { return cf{a.re - b.re, a.im - b.im}; }
+__host__ __device__ inline cf cmul(cf a, cf b) {
+  return cf{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__host__ __device__ inline cf cconj(cf a) { return cf{a.re, -a.im}; }
+__host__ __device__ inline cf cscale(cf a, float s) { return cf{a.re * s, a.im * s}; }
+__host__ __device__ inline float cabs2(cf a) { return a.re * a.re + a.im * a.im; }
+
+// Conversions between the two precisions (the global operands stay FP64).
+template <typename T> __host__ __device__ inline T to_c(cd a);
+template <> __host__ __device__ inline cd to_c<cd>(cd a) { return a; }
+template <> __host__ __device__ inline cf to_c<cf>(cd a) { return cf{(float)a.re, (float)a.im}; }
+__host__ __device__ inline cd to_cd(cd a) { return a; }
+__host__ __device__ inline cd to_cd(cf a) { return cd{(double)a.re, (double)a.im}; }
+
+// Real scalar type of a complex type.
+template <typename T> struct real_of;
+template <> struct real_of<cd> { using type = double; };
+template <> struct real_of<cf> { using type = float; };
+
 __host__ __device__ inline int pack_charge(int n, int np) { return (n << 16) | np; }
 __host__ __device__ inline int charge_n(int c) { return c >> 16; }
 __host__ __device__ inline int charge_np(int c) { return c & 0xffff; }

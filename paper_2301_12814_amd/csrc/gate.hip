@@ -94,14 +94,14 @@ constexpr int CHUNK = 256;
 
 // LDS bytes of the one-workgroup Jacobi (operand + column norms) and the
 // widest panel whose pair (2 w columns of m rows) fits in LDS.
-__host__ __device__ inline size_t svd_small_need_(int m, int n) {
-  return sizeof(cd) * (size_t)m * n + sizeof(double) * (size_t)n;
+__host__ __device__ inline size_t svd_small_need(int m, int n, int esz) {
+  return (size_t)esz * m * n + sizeof(double) * (size_t)n;
 }
-size_t svd_small_need(int m, int n) { return svd_small_need_(m, n); }
-#define svd_small_need svd_small_need_
-__host__ __device__ inline int panel_width(int m, int lds_bytes) {
+// Widest panel (32, 16, ..., 1) whose pair (2 w columns of m elements of esz
+// bytes) fits in lds_bytes.
+__host__ __device__ inline int panel_width(int m, int lds_bytes, int esz) {
   int w = 32;
-  while (w > 1 && 2 * (size_t)w * m * sizeof(cd) > (size_t)lds_bytes) w >>= 1;
+  while (w > 1 && 2 * (size_t)w * m * esz > (size_t)lds_bytes) w >>= 1;
   return w;
 }
 
@@ -111,15 +111,15 @@ __host__ __device__ inline int panel_width(int m, int lds_bytes) {
 // of A (the Jacobi needs about a third of the sweeps) and the work per sweep
 // drops by m / n.  The Jacobi runs in one workgroup from LDS when its operand
 // fits there, otherwise as multi-workgroup panel rounds.
-__host__ __device__ inline void svd_route(int m, int n, int lds_bytes, int qr_ok, int &qr,
-                                          int &big, int &mj) {
+__host__ __device__ inline void svd_route(int m, int n, int lds_bytes, int qr_ok, int esz,
+                                          int &qr, int &big, int &mj) {
   qr = 0;
   mj = m;
-  if (qr_ok && svd_small_need(m, n) > (size_t)lds_bytes) {
+  if (qr_ok && svd_small_need(m, n, esz) > (size_t)lds_bytes) {
     qr = 1;
     mj = n;
   }
-  big = svd_small_need(mj, n) > (size_t)lds_bytes ? 1 : 0;
+  big = svd_small_need(mj, n, esz) > (size_t)lds_bytes ? 1 : 0;
 }
 
 // Two passes over the charge box of every gate.  The count pass (FILL =
@@ -262,12 +262,12 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
           chb += (int)(((long long)r * s + CHUNK - 1) / CHUNK);
           fl += 16.0 * m * (double)n * n + 36.0 * (double)n * n * n;
           int qr, big, mj;
-          svd_route(m, n, lds_bytes, qr_ok, qr, big, mj);
+          svd_route(m, n, lds_bytes, qr_ok, ly.esz, qr, big, mj);
           if (qr) reb += (long long)n * n;
-          if (big && 2LL * mj * (long long)sizeof(cd) > panel_lds) atomicOr(st.err, ERR_WORKSPACE);
+          if (big && 2LL * mj * ly.esz > panel_lds) atomicOr(st.err, ERR_WORKSPACE);
           if (big) {
             ++bgb;
-            const int w = panel_width(mj, min(lds_bytes, panel_lds));
+            const int w = panel_width(mj, min(lds_bytes, panel_lds), ly.esz);
             const int np = (n + w - 1) / w;
             maxpp = max(maxpp, np + (np & 1));
           }
@@ -361,10 +361,10 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
         e = (long long)B.r * B.s;
         sv = B.n;
         ch = (int)((e + CHUNK - 1) / CHUNK);
-        svd_route(B.m, B.n, lds_bytes, qr_ok, qr, bg, mj);
+        svd_route(B.m, B.n, lds_bytes, qr_ok, ly.esz, qr, bg, mj);
         if (qr) re = (long long)B.n * B.n;
         if (bg) {
-          w = panel_width(mj, min(lds_bytes, panel_lds));
+          w = panel_width(mj, min(lds_bytes, panel_lds), ly.esz);
           npan = (B.n + w - 1) / w;
         }
       }
@@ -765,14 +765,19 @@ __device__ __forceinline__ double dpp_d(double v) {
   const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
   return __hiloint2double(h2, l2);
 }
+template <int CTRL>
+__device__ __forceinline__ float dpp_d(float v) {
+  const int x = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false));
+}
 
 // Sum over a group of L lanes: xor 1 and xor 2 inside each quad, the row
 // mirror (quad q with quad 3 - q), the half-row mirror (quad 0 with 1, 2
 // with 3), then xor 16 and xor 32 across rows.  Every step adds two values
 // in an order-independent way, so all lanes of the group end with bitwise
 // the same sum (the callers branch on it).
-template <int L>
-__device__ __forceinline__ double group_sum(double v) {
+template <int L, typename R>
+__device__ __forceinline__ R group_sum(R v) {
   v += dpp_d<0xB1>(v);
   v += dpp_d<0x4E>(v);
   v += dpp_d<0x140>(v);
@@ -787,50 +792,53 @@ __device__ __forceinline__ double group_sum(double v) {
 // LDS: a rotation with tangent t changes them exactly to al - t |g| and
 // be + t |g|; when either loses more than half it is recomputed from the
 // rotated column.
-template <int L>
-__device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, double *nx, double *ny, int m,
+// T is the complex type of the LDS operand (cd: FP64; cf: the FP32 Jacobi of
+// the mixed-precision path); dot products and rotations run in its precision,
+// the tracked norms and the rotation parameters in FP64.
+template <int L, typename T>
+__device__ __forceinline__ void jacobi_pair(T *xp, T *xq, double *nx, double *ny, int m,
                                             int gl, double tol, double tiny, int &rot) {
+  using R = typename real_of<T>::type;
   const double al = *nx, be = *ny;
   if (fmin(al, be) <= tiny) return;
-  double gr = 0.0, gi = 0.0;
+  R gr = 0, gi = 0;
   const bool cached = m <= L * CE;
-  cd rx[CE], ry[CE];
+  T rx[CE], ry[CE];
   if (cached) {
 #pragma unroll
     for (int k = 0; k < CE; ++k) {
       const int i = gl + L * k;
-      rx[k] = i < m ? xp[i] : cmk(0.0, 0.0);
-      ry[k] = i < m ? xq[i] : cmk(0.0, 0.0);
+      rx[k] = i < m ? xp[i] : T{0, 0};
+      ry[k] = i < m ? xq[i] : T{0, 0};
       gr += rx[k].re * ry[k].re + rx[k].im * ry[k].im;
       gi += rx[k].re * ry[k].im - rx[k].im * ry[k].re;
     }
   } else {
     for (int i = gl; i < m; i += L) {
-      const cd x = xp[i], y = xq[i];
+      const T x = xp[i], y = xq[i];
       gr += x.re * y.re + x.im * y.im;
       gi += x.re * y.im - x.im * y.re;
     }
   }
-  gr = group_sum<L>(gr);
-  gi = group_sum<L>(gi);
-  const double ga = sqrt(gr * gr + gi * gi);
+  const double grd = group_sum<L>(gr), gid = group_sum<L>(gi);
+  const double ga = sqrt(grd * grd + gid * gid);
   if (!(ga > tol * sqrt(al * be)) || ga < 1e-300) return;
   const double zeta = (be - al) / (2.0 * ga);
   const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double c = 1.0 / sqrt(1.0 + t * t);
-  const double s = c * t;
-  const cd e = cmk(gr / ga, -gi / ga);      // e^{-i psi}
+  const double cd_ = 1.0 / sqrt(1.0 + t * t);
+  const R c = (R)cd_, s = (R)(cd_ * t);
+  const T e = T{(R)(grd / ga), (R)(-gid / ga)};      // e^{-i psi}
   double al2 = al - t * ga, be2 = be + t * ga;
   const bool exact = !(al2 >= 0.5 * al) || !(be2 >= 0.5 * be);
-  double na = 0.0, nb = 0.0;
+  R na = 0, nb = 0;
   if (cached) {
 #pragma unroll
     for (int k = 0; k < CE; ++k) {
       const int i = gl + L * k;
       if (i < m) {
-        const cd y = cmul(e, ry[k]);
-        const cd x2 = csub(cscale(rx[k], c), cscale(y, s));
-        const cd y2 = cadd(cscale(rx[k], s), cscale(y, c));
+        const T y = cmul(e, ry[k]);
+        const T x2 = csub(cscale(rx[k], c), cscale(y, s));
+        const T y2 = cadd(cscale(rx[k], s), cscale(y, c));
         xp[i] = x2;
         xq[i] = y2;
         na += cabs2(x2);
@@ -839,10 +847,10 @@ __device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, double *nx, double *
     }
   } else {
     for (int i = gl; i < m; i += L) {
-      const cd x = xp[i];
-      const cd y = cmul(e, xq[i]);
-      const cd x2 = csub(cscale(x, c), cscale(y, s));
-      const cd y2 = cadd(cscale(x, s), cscale(y, c));
+      const T x = xp[i];
+      const T y = cmul(e, xq[i]);
+      const T x2 = csub(cscale(x, c), cscale(y, s));
+      const T y2 = cadd(cscale(x, s), cscale(y, c));
       xp[i] = x2;
       xq[i] = y2;
       na += cabs2(x2);
@@ -861,11 +869,13 @@ __device__ __forceinline__ void jacobi_pair(cd *xp, cd *xq, double *nx, double *
 }
 
 // Squared norms of the nc columns at A (column stride m) into nrm.
-__device__ __forceinline__ void column_norms(const cd *A, int m, int nc, double *nrm) {
+template <typename T>
+__device__ __forceinline__ void column_norms(const T *A, int m, int nc, double *nrm) {
+  using R = typename real_of<T>::type;
   const int gl = threadIdx.x & 15, slot = threadIdx.x >> 4;
   const int ns = blockDim.x >> 4;
   for (int c = slot; c < nc; c += ns) {
-    double acc = 0.0;
+    R acc = 0;
     for (int i = gl; i < m; i += 16) acc += cabs2(A[(size_t)c * m + i]);
     acc = group_sum<16>(acc);
     if (gl == 0) nrm[c] = acc;
@@ -873,7 +883,17 @@ __device__ __forceinline__ void column_norms(const cd *A, int m, int nc, double 
   __syncthreads();
 }
 
-__device__ __forceinline__ double jacobi_tol(int m) { return fmax(1e-15, 2.3e-16 * m); }
+// Unit roundoff of the Jacobi's working precision.
+template <typename T> __device__ __forceinline__ double unit_eps();
+template <> __device__ __forceinline__ double unit_eps<cd>() { return 1.11e-16; }
+template <> __device__ __forceinline__ double unit_eps<cf>() { return 5.96e-8; }
+
+// Relative orthogonality tolerance: max(9 eps, 2.07 eps m) (1e-15 and
+// 2.3e-16 m in FP64).
+template <typename T = cd>
+__device__ __forceinline__ double jacobi_tol(int m) {
+  return fmax(9.0 * unit_eps<T>(), 2.07 * unit_eps<T>() * m);
+}
 
 // Rounding floor of a column's squared norm: a column of an operand with
 // squared Frobenius norm fro2 whose own squared norm is below 16 m eps^2 fro2
@@ -881,8 +901,9 @@ __device__ __forceinline__ double jacobi_tol(int m) { return fmax(1e-15, 2.3e-16
 // cannot be resolved to the relative tolerance (rotating such pairs never
 // settles).  Pairs with either column below the floor are left alone; their
 // singular values lie far below the 1e-14 rank cut.
+template <typename T = cd>
 __device__ __forceinline__ double jacobi_floor(int m, double fro2) {
-  return 16.0 * m * (1.11e-16 * 1.11e-16) * fro2;
+  return 16.0 * m * (unit_eps<T>() * unit_eps<T>()) * fro2;
 }
 
 // The Jacobi operand of a computed block: R of a QR'd block, else the block.
@@ -893,8 +914,8 @@ __device__ __forceinline__ cd *jacobi_operand(const Layer &ly, const GateBase &g
 
 // One round-robin pass over all pairs of the nc columns at A (column stride m,
 // squared norms in nrm), L lanes per pair.
-template <int L>
-__device__ __forceinline__ void round_robin_pass_l(cd *A, double *nrm, int m, int nc, double tol,
+template <int L, typename T>
+__device__ __forceinline__ void round_robin_pass_l(T *A, double *nrm, int m, int nc, double tol,
                                                    double tiny, int &rot) {
   const int gl = threadIdx.x & (L - 1), slot = threadIdx.x / L;
   const int ns = blockDim.x / L;
@@ -928,8 +949,8 @@ __device__ __forceinline__ void round_robin_pass_l(cd *A, double *nrm, int m, in
 // Cross pairs of two panels held in LDS (wI columns then wJ columns, panel
 // width w): w sub-rounds, column t of the first panel with (t + sr) mod w of
 // the second; L lanes per pair.
-template <int L>
-__device__ __forceinline__ void cross_pass_l(cd *sA, double *nrm, int m, int w, int wI, int wJ,
+template <int L, typename T>
+__device__ __forceinline__ void cross_pass_l(T *sA, double *nrm, int m, int w, int wI, int wJ,
                                              double tol, double tiny, int &rot) {
   const int gl = threadIdx.x & (L - 1), slot = threadIdx.x / L;
   const int ns = blockDim.x / L;
@@ -956,7 +977,11 @@ __device__ __forceinline__ double block_sum(double v, double *s_red) {
 
 // Workgroup copies between global memory and LDS with eight loads in flight
 // per thread (a plain loop waits for each load before the next).
-__device__ __forceinline__ void copy_in(cd *dst, const cd *src, int count) {
+// (scaled by sc on the way in and by 1 / sc on the way out: the FP32 Jacobi
+// works on the operand normalised to unit Frobenius norm, so that sectors of
+// tiny weight do not underflow in single precision)
+template <typename T>
+__device__ __forceinline__ void copy_in(T *dst, const cd *src, int count, double sc = 1.0) {
   const int step = blockDim.x;
   for (int base = threadIdx.x; base < count; base += 8 * step) {
     cd r[8];
@@ -968,13 +993,23 @@ __device__ __forceinline__ void copy_in(cd *dst, const cd *src, int count) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int idx = base + u * step;
-      if (idx < count) dst[idx] = r[u];
+      if (idx < count) dst[idx] = to_c<T>(sc == 1.0 ? r[u] : cscale(r[u], sc));
     }
   }
 }
 
-__device__ __forceinline__ void copy_out(cd *dst, const cd *src, int count) {
-  for (int idx = threadIdx.x; idx < count; idx += blockDim.x) dst[idx] = src[idx];
+template <typename T>
+__device__ __forceinline__ void copy_out(cd *dst, const T *src, int count, double isc = 1.0) {
+  for (int idx = threadIdx.x; idx < count; idx += blockDim.x)
+    dst[idx] = isc == 1.0 ? to_cd(src[idx]) : cscale(to_cd(src[idx]), isc);
+}
+
+// Scale applied to an operand of squared Frobenius norm fro2 before its
+// Jacobi: 1 in FP64, 1 / |A|_F in FP32.
+template <typename T> __device__ __forceinline__ double jacobi_scale(double fro2);
+template <> __device__ __forceinline__ double jacobi_scale<cd>(double) { return 1.0; }
+template <> __device__ __forceinline__ double jacobi_scale<cf>(double fro2) {
+  return fro2 > 0.0 ? 1.0 / sqrt(fro2) : 1.0;
 }
 
 // Self-mirror block (q = (n, n)) of a Hermitian state: the block obeys
@@ -982,8 +1017,9 @@ __device__ __forceinline__ void copy_out(cd *dst, const cd *src, int count) {
 // non-degenerate singular vector is J-real up to a phase: u[y~] = e^{i phi}
 // conj(u[y]) on the operand's rows.  The bilinear sum s = sum_y u[y] u[y~] =
 // e^{i phi} |u|^2 gives the phase and the column is multiplied by e^{-i phi/2}.
+template <typename T>
 __device__ __forceinline__ void self_mirror_phase(const Layer &ly, const GateParam &gp,
-                                                  const BlkDesc &B, cd *A) {
+                                                  const BlkDesc &B, T *A) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const int m = B.m, n = B.n;
@@ -994,7 +1030,7 @@ __device__ __forceinline__ void self_mirror_phase(const Layer &ly, const GatePar
     double sr = 0.0, si = 0.0, nr = 0.0;
     for (int y = lane; y < m; y += 64) {
       const int ym = lower_bound(lst, m, my[lst[y]]);
-      const cd x = A[(size_t)c * m + y], z = A[(size_t)c * m + ym];
+      const cd x = to_cd(A[(size_t)c * m + y]), z = to_cd(A[(size_t)c * m + ym]);
       const cd p = cmul(x, z);
       sr += p.re;
       si += p.im;
@@ -1007,19 +1043,21 @@ __device__ __forceinline__ void self_mirror_phase(const Layer &ly, const GatePar
     if (sa > 0.5 * nr && sa > 0.0) {
       const double ang = -0.5 * atan2(si, sr);
       const cd f = cmk(cos(ang), sin(ang));
-      for (int i = lane; i < m; i += 64) A[(size_t)c * m + i] = cmul(A[(size_t)c * m + i], f);
+      for (int i = lane; i < m; i += 64)
+        A[(size_t)c * m + i] = to_c<T>(cmul(to_cd(A[(size_t)c * m + i]), f));
     }
   }
   __syncthreads();
 }
 
 // Singular values = column norms, sorted descending (ties by column).
-__device__ __forceinline__ void sort_values(int *err, const cd *A, int m, int n, double *sig,
-                                            double *sv, int *perm) {
+template <typename T>
+__device__ __forceinline__ void sort_values(int *err, const T *A, int m, int n, double *sig,
+                                            double *sv, int *perm, double vscale = 1.0) {
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     double acc = 0.0;
-    for (int i = 0; i < m; ++i) acc += cabs2(A[(size_t)c * m + i]);
-    sig[c] = sqrt(acc);
+    for (int i = 0; i < m; ++i) acc += cabs2(to_cd(A[(size_t)c * m + i]));
+    sig[c] = sqrt(acc) * vscale;
   }
   __syncthreads();
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
@@ -1042,6 +1080,7 @@ __device__ inline void big_block_of(const Layer &ly, int flat_big, int &g, int &
 
 // One workgroup per block whose LDS need lies in (lo, hi] (the launches are
 // split by size so that small blocks do not reserve a whole CU's LDS).
+template <typename T>
 __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly, int lo, int hi) {
   const int flat = blockIdx.x;
   const int g = find_gate_blk(ly.base, ly.ngates, flat);
@@ -1052,22 +1091,23 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly, int lo, int
   const BlkDesc B = *Bp;
   if (!B.comp || B.big) return;
   {
-    const long long need = (long long)svd_small_need(B.mj, B.n);
+    const long long need = (long long)svd_small_need(B.mj, B.n, (int)sizeof(T));
     if (need <= lo || need > hi) return;
   }
   const int m = B.mj, n = B.n;
   extern __shared__ double s_dyn[];
-  cd *sA = reinterpret_cast<cd *>(s_dyn);
-  double *sig = reinterpret_cast<double *>(sA + (size_t)m * n);
+  double *sig = s_dyn;                                   // n column norms^2
+  T *sA = reinterpret_cast<T *>(s_dyn + n);              // m x n operand
   __shared__ int s_rot;
   __shared__ double s_red[16];
   cd *A = jacobi_operand(ly, gb, B);
   double f2 = 0.0;
-  copy_in(sA, A, m * n);
-  __syncthreads();
-  for (int i = threadIdx.x; i < m * n; i += blockDim.x) f2 += cabs2(sA[i]);
+  for (int i = threadIdx.x; i < m * n; i += blockDim.x) f2 += cabs2(A[i]);
   f2 = block_sum(f2, s_red);
-  const double tol = jacobi_tol(m), tiny = jacobi_floor(m, f2);
+  const double sc = jacobi_scale<T>(f2);
+  copy_in(sA, A, m * n, sc);
+  __syncthreads();
+  const double tol = jacobi_tol<T>(m), tiny = jacobi_floor<T>(m, f2 * sc * sc);
   int sweep = 0;
   if (n > 1) {
     for (sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
@@ -1084,8 +1124,9 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly, int lo, int
     if (sweep == MAX_SWEEPS && threadIdx.x == 0) atomicOr(st.err, ERR_SVD_NOT_CONVERGED);
   }
   if (!B.qr && charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym) self_mirror_phase(ly, gp, B, sA);
-  sort_values(st.err, sA, m, n, sig, ly.sv + gp.lst0 + B.svoff, ly.perm + gp.lst0 + B.svoff);
-  copy_out(A, sA, m * n);
+  sort_values(st.err, sA, m, n, sig, ly.sv + gp.lst0 + B.svoff, ly.perm + gp.lst0 + B.svoff,
+              1.0 / sc);
+  copy_out(A, sA, m * n, 1.0 / sc);
   if (threadIdx.x == 0) {
     Bp->sweeps = sweep;
     Bp->fro2 = f2;
@@ -1118,6 +1159,7 @@ constexpr int PANEL_THREADS = 1024;
 // sweeps, Pp - 1 rounds each (Pp = panel count rounded up to even), so block
 // b is at sweep t / (Pp_b - 1), round t mod (Pp_b - 1): blocks with few
 // panels do not wait for the rounds of the largest ones.
+template <typename T>
 __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
   const int kbig = blockIdx.y;
   int g, bi;
@@ -1151,13 +1193,14 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
   const int j0 = hasJ ? J * w : 0, wJ = hasJ ? min(w, n - J * w) : 0;
   const int nc = wI + wJ;
   extern __shared__ double s_dyn[];
-  cd *sA = reinterpret_cast<cd *>(s_dyn);
+  T *sA = reinterpret_cast<T *>(s_dyn);
   cd *A = jacobi_operand(ly, ly.base[g], B);
   // the two panels are contiguous column ranges of the operand
-  copy_in(sA, A + (size_t)i0 * m, wI * m);
-  copy_in(sA + (size_t)wI * m, A + (size_t)j0 * m, wJ * m);
+  const double sc = jacobi_scale<T>(B.fro2);
+  copy_in(sA, A + (size_t)i0 * m, wI * m, sc);
+  copy_in(sA + (size_t)wI * m, A + (size_t)j0 * m, wJ * m, sc);
   __syncthreads();
-  const double tol = jacobi_tol(m), tiny = jacobi_floor(m, B.fro2);
+  const double tol = jacobi_tol<T>(m), tiny = jacobi_floor<T>(m, B.fro2 * sc * sc);
   __shared__ double s_nrm[64];
   column_norms(sA, m, nc, s_nrm);
   int rot = 0;
@@ -1168,8 +1211,8 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
   }
   if (rot) rf[sweep % 3] = 1;
   __syncthreads();
-  copy_out(A + (size_t)i0 * m, sA, wI * m);
-  copy_out(A + (size_t)j0 * m, sA + (size_t)wI * m, wJ * m);
+  copy_out(A + (size_t)i0 * m, sA, wI * m, 1.0 / sc);
+  copy_out(A + (size_t)j0 * m, sA + (size_t)wI * m, wJ * m, 1.0 / sc);
 }
 
 // Big blocks not yet converged; with `last`, the simulations owning them get
@@ -1219,8 +1262,10 @@ int svd_lds_bytes() {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
       v = 65536;
     const int b = (v > 163840 ? 163840 : v) - 2048;   // room for static LDS
-    hipFuncSetAttribute((const void *)k_svd_small, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    hipFuncSetAttribute((const void *)k_panel, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    hipFuncSetAttribute((const void *)k_svd_small<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    hipFuncSetAttribute((const void *)k_svd_small<cf>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    hipFuncSetAttribute((const void *)k_panel<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    hipFuncSetAttribute((const void *)k_panel<cf>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     return b;
   }();
   return bytes;
@@ -1236,7 +1281,12 @@ hipError_t launch_svd_small(Layer ly, hipStream_t s) {
   for (int k = 0; k < 4; ++k) {
     const int hi = cap[k] < lb ? cap[k] : lb;
     if (hi <= lo) continue;
-    hipLaunchKernelGGL(k_svd_small, dim3(ly.total_blocks), dim3(thr[k]), (size_t)hi, s, ly, lo, hi);
+    if (ly.mixed)
+      hipLaunchKernelGGL(k_svd_small<cf>, dim3(ly.total_blocks), dim3(thr[k]), (size_t)hi, s, ly,
+                         lo, hi);
+    else
+      hipLaunchKernelGGL(k_svd_small<cd>, dim3(ly.total_blocks), dim3(thr[k]), (size_t)hi, s, ly,
+                         lo, hi);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     lo = hi;
@@ -1268,8 +1318,12 @@ hipError_t launch_svd_panel_step(Layer ly, int step, hipStream_t s) {
   // half the LDS per workgroup: two panel workgroups share a CU, one loading
   // or storing its panels while the other rotates
   const int thr = ly.panel_lds <= lb / 2 ? PANEL_THREADS / 2 : PANEL_THREADS;
-  hipLaunchKernelGGL(k_panel, dim3(ly.maxpp / 2, ly.total_big), dim3(thr), (size_t)ly.panel_lds,
-                     s, ly, step);
+  if (ly.mixed)
+    hipLaunchKernelGGL(k_panel<cf>, dim3(ly.maxpp / 2, ly.total_big), dim3(thr),
+                       (size_t)ly.panel_lds, s, ly, step);
+  else
+    hipLaunchKernelGGL(k_panel<cd>, dim3(ly.maxpp / 2, ly.total_big), dim3(thr),
+                       (size_t)ly.panel_lds, s, ly, step);
   return hipGetLastError();
 }
 
@@ -1443,7 +1497,12 @@ __global__ __launch_bounds__(256) void k_leftvec(Layer ly) {
     if (i < B.kq) {
       // right vector of A P is Y[:, perm[i]] / sigma; of A: v[piv[x]] = that[x]
       const cd *y = Y + (size_t)perm[i] * n;
-      const double s1 = 1.0 / sv[i];
+      double s1 = 1.0 / sv[i];
+      if (ly.mixed) {          // the FP32 Jacobi's norm is not exact: normalise in FP64
+        double nn = 0.0;
+        for (int x = lane; x < n; x += 64) nn += cabs2(y[x]);
+        s1 = 1.0 / sqrt(wave_sum(nn));
+      }
       cd *v = V + (size_t)i * n;
       for (int x = lane; x < n; x += 64) v[piv[x]] = cconj(cscale(y[x], s1));   // conj(v)
     }
@@ -1478,7 +1537,8 @@ __global__ __launch_bounds__(256) void k_leftvec(Layer ly) {
     if (i < B.kq) {
       const cd *v = V + (size_t)i * n;
       cd *u = U + (size_t)i * m;
-      const double s1 = 1.0 / sv[i];
+      const double s1 = ly.mixed ? 1.0 : 1.0 / sv[i];
+      double nu = 0.0;
       for (int yy = lane; yy < m; yy += 64) {
         double re = 0.0, im = 0.0;
         for (int x = 0; x < n; ++x) {
@@ -1487,6 +1547,14 @@ __global__ __launch_bounds__(256) void k_leftvec(Layer ly) {
           im += p.im;
         }
         u[yy] = cmk(re * s1, im * s1);
+        nu += re * re + im * im;
+      }
+      if (ly.mixed) {
+        // sigma_i refined in FP64 as |A0 v_i|, u_i normalised (each lane owns its rows)
+        const double lam = sqrt(wave_sum(nu));
+        const double r = lam > 0.0 ? 1.0 / lam : 0.0;
+        for (int yy = lane; yy < m; yy += 64) u[yy] = cscale(u[yy], r);
+        if (lane == 0) ly.sv[gp.lst0 + B.svoff + i] = lam;
       }
     }
   }
@@ -1566,6 +1634,7 @@ __global__ __launch_bounds__(256) void k_scatter(Layer ly) {
   cd *G2 = st.gam + (size_t)(j + 1) * chi * chi;
   extern __shared__ double s_dyn[];
   cd *sv_x = reinterpret_cast<cd *>(s_dyn);          // v[x], n entries
+  __shared__ double s_red[16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int i = threadIdx.x; i < B.kq; i += blockDim.x) {
     st.lam[(size_t)(j + 1) * chi + B.boff + i] = sv[i];
@@ -1597,6 +1666,21 @@ __global__ __launch_bounds__(256) void k_scatter(Layer ly) {
       if (lane == 0) sv_x[x] = cmk(re * s2, im * s2);
     }
     __syncthreads();
+    if (ly.mixed && !B.qr) {
+      // the FP32 Jacobi's u is accurate to FP32 only: sigma_i refined in FP64
+      // as |A0^H u_i|, v_i normalised
+      double nn = 0.0;
+      for (int x = threadIdx.x; x < n; x += blockDim.x) nn += cabs2(sv_x[x]);
+      nn = block_sum(nn, s_red);
+      const double r = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+      for (int x = threadIdx.x; x < n; x += blockDim.x) sv_x[x] = cscale(sv_x[x], r);
+      if (threadIdx.x == 0) {
+        const double lam = sv[i] * sqrt(nn);
+        st.lam[(size_t)(j + 1) * chi + B.boff + i] = lam;
+        if (mirw) st.lam[(size_t)(j + 1) * chi + mboff + i] = lam;
+      }
+      __syncthreads();
+    }
     // operand-row side
     for (int y = threadIdx.x; y < m; y += blockDim.x) {
       cd u = cscale(Ac[y], s1);

@@ -106,6 +106,8 @@ struct Layer {
   int total_big;     // big blocks in the layer
   int maxpp;         // largest even panel count in the layer
   int panel_lds;     // LDS bytes of one panel workgroup
+  int mixed;         // 1: FP32 Jacobi (mixed-precision path), FP64 elsewhere
+  int esz;           // bytes per Jacobi operand element in LDS (16, or 8 when mixed)
   double *sv;        // singular values, sorted descending per block
   int *perm;         // rank -> operand column
   unsigned long long *uval;   // selection units: value bits
@@ -148,7 +150,6 @@ hipError_t launch_scatter(Layer ly, int max_chi, hipStream_t s);
 hipError_t launch_entropy_layer(Layer ly, hipStream_t s);
 int svd_lds_bytes();
 void set_svd_route(int lds_limit_bytes, int qr_enable);
-size_t svd_small_need(int m, int n);
 
 // readouts
 hipError_t launch_entropy_all(State st, hipStream_t s);

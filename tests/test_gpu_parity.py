@@ -343,3 +343,35 @@ def test_gpu_noise_level_sectors_converge(idx):
                 m = key.get((c, a))
                 assert m is not None and len(m) == len(v), (b, a, c)
                 assert np.allclose(v, m, rtol=1e-12, atol=1e-14 * lam.max()), (b, a, c)
+
+
+@pytest.mark.parametrize("lds", [0, 3000])
+def test_gpu_mixed_precision_small_matches_oracle(svd_route, lds):
+    """Mixed-precision path (FP32 Jacobi on the operand normalised to unit
+    norm, FP64 everywhere else, kept values and vectors refined in FP64) on
+    the whole small workload against the FP64 oracle: every bond's EE within
+    1e-6 absolute; marginals and trace within 2e-7 (the FP32 Jacobi's vectors
+    carry ~1e-7 relative errors, so the 1e-8 marginal target is not reached),
+    with the default route and with the QR / panel routes forced by a lowered
+    LDS budget."""
+    svd_route(lds, True)
+    w = inputs.workload("small")
+    U = inputs.haar_unitary(w.M, w.seed)
+    layers, phase = gbsmpo.clements(U)
+    og, oph = oclem.decompose(U)
+    olayers = oclem.layers(w.M, og)
+    o = omp.DenseMPO.product(rhos_of(w), w.chi)
+    worst = 0.0
+    with gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi, gbsmpo.MPO_MIXED) as g:
+        for li, (S, T, P) in enumerate(layers):
+            g.apply_layer(S, T, P)
+            for (k, th, ph) in olayers[li]:
+                o.apply_gate(k, th, ph, w.chi)
+            Sg, _ = g.entropy()
+            worst = max(worst, float(np.abs(Sg - o.entropies()).max()))
+        P, tr = g.marginals()
+    oP, otr, _ = o.marginals()
+    say("mixed small: worst EE error", worst, "marginal error", float(np.abs(P - oP).max()))
+    assert worst < 1e-6
+    assert np.abs(P - oP).max() < 2e-7
+    assert abs(tr - otr) < 2e-7
