@@ -130,10 +130,10 @@ struct Engine {
   DBuf<double> d_sv;
   DBuf<unsigned long long> d_uval, d_ukey;
   DBuf<cd> d_A, d_A0, d_R, d_U, d_V, d_tau;
-  DBuf<int> d_rotf;
+  DBuf<int> d_rotf, d_tasks;
   DBuf<int> d_active;
   DBuf<int> d_eng_err;
-  int *h_small = nullptr;          // pinned: [0] active count, [1] engine error word
+  int *h_small = nullptr;          // pinned: [1] engine error word, [2..3] rotating blocks / tasks
   long long pool_budget = 0;       // sector operand elements per chunk
   // profiling
   static constexpr int NPH = 8;
@@ -236,7 +236,7 @@ int engine_init(Engine &E, void *hip_stream, int precision, long long budget) {
   // sector operand pools per chunk (A and A0): at most a quarter of the budget each
   E.pool_budget = std::max<long long>(1LL << 22, E.budget / 4 / (long long)sizeof(cd));
   HIPCHK(hipHostMalloc((void **)&E.h_small, sizeof(int) * 4));
-  HIPCHK(E.d_active.ensure(1));
+  HIPCHK(E.d_active.ensure(2));
   HIPCHK(E.d_eng_err.ensure(1));
   HIPCHK(hipMemsetAsync(E.d_eng_err.p, 0, sizeof(int), E.stream));
   HIPCHK(hipStreamSynchronize(E.stream));
@@ -273,6 +273,7 @@ void engine_destroy(Engine &E) {
   E.d_V.release();
   E.d_tau.release();
   E.d_rotf.release();
+  E.d_tasks.release();
   E.d_active.release();
   E.d_eng_err.release();
   if (E.h_errs) hipHostFree(E.h_errs);
@@ -615,6 +616,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     HIPCHK(E.d_tau.ensure(lst0));
     HIPCHK(E.d_piv.ensure(lst0));
     HIPCHK(E.d_rotf.ensure((size_t)4 * std::max(bigb, 1)));
+    HIPCHK(E.d_tasks.ensure((size_t)2 * std::max(bigb, 1) + 1));
     if (bigb > 65535 || maxpp / 2 > 65535)
       return fail(MPO_EINVAL, "too many large sectors in one layer chunk");
     HIPCHK(hipMemcpyAsync(E.d_gates.p + c0, E.h_gates + c0, sizeof(GateParam) * ng,
@@ -644,6 +646,10 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     C.piv = E.d_piv.p;
     C.rotf = E.d_rotf.p;
     C.active = E.d_active.p;
+    C.task_blk = E.d_tasks.p;
+    C.task_pre = E.d_tasks.p + std::max(bigb, 1);
+    C.nact = 0;
+    C.ntask = 0;
     C.total_chunks = ch;
     C.total_blocks = blkb;
     C.total_big = bigb;
@@ -663,19 +669,28 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
       HIPCHK(launch_svd_small(C, E.stream));
       if (bigb > 0) {
         // panel rounds of the big blocks (each block at its own sweep); the
-        // number still rotating is read back every 16 launches
+        // still-rotating blocks are compacted into the launch's task list and
+        // counted every 16 launches
         HIPCHK(launch_svd_big_prep(C, E.stream));
         const int tmax = svd_max_steps(C);
-        for (int t = 0; t < tmax; ++t) {
+        auto check = [&](int last) -> int {
+          HIPCHK(launch_svd_count(C, last, E.stream));
+          HIPCHK(hipMemcpyAsync(E.h_small + 2, E.d_active.p, 2 * sizeof(int),
+                                hipMemcpyDeviceToHost, E.stream));
+          HIPCHK(hipStreamSynchronize(E.stream));
+          C.nact = E.h_small[2];
+          C.ntask = E.h_small[3];
+          return MPO_OK;
+        };
+        int crc = check(0);
+        if (crc != MPO_OK) return crc;
+        for (int t = 0; t < tmax && C.nact > 0; ++t) {
           HIPCHK(launch_svd_panel_step(C, t, E.stream));
           sweeps_run = t + 1;
           const bool last = t == tmax - 1;
           if ((t & 15) == 15 || last) {
-            HIPCHK(launch_svd_count(C, last ? 1 : 0, E.stream));
-            HIPCHK(hipMemcpyAsync(E.h_small, E.d_active.p, sizeof(int), hipMemcpyDeviceToHost,
-                                  E.stream));
-            HIPCHK(hipStreamSynchronize(E.stream));
-            if (E.h_small[0] == 0) break;
+            crc = check(last ? 1 : 0);
+            if (crc != MPO_OK) return crc;
           }
         }
         HIPCHK(launch_svd_big_finish(C, sweeps_run, max_chi, E.stream));

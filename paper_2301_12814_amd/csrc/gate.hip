@@ -1161,12 +1161,20 @@ constexpr int PANEL_THREADS = 1024;
 // panels do not wait for the rounds of the largest ones.
 template <typename T>
 __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
-  const int kbig = blockIdx.y;
+  // task -> (still-rotating big block, panel pair) through the compacted list
+  const int task = blockIdx.x;
+  int lo = 0, hi = ly.nact;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ly.task_pre[mid] <= task) lo = mid; else hi = mid;
+  }
+  const int kbig = ly.task_blk[lo];
+  const int kpair = task - ly.task_pre[lo];
   int g, bi;
   big_block_of(ly, kbig, g, bi);
   const BlkDesc B = ly.blk[ly.gates[g].blk0 + bi];
   const int P = B.npan, Pp = P + (P & 1);
-  if ((int)blockIdx.x >= Pp / 2) return;
+  if (kpair >= Pp / 2) return;
   const int sweep = step / (Pp - 1), round = step % (Pp - 1);
   if (sweep >= MAX_SWEEPS) return;
   int *rf = ly.rotf + 4 * (size_t)kbig;
@@ -1175,8 +1183,8 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
     if (threadIdx.x == 0) rf[3] = sweep;
     return;
   }
-  if (round == 0 && blockIdx.x == 0 && threadIdx.x == 0) rf[(sweep + 1) % 3] = 0;
-  const int k = blockIdx.x;
+  if (round == 0 && kpair == 0 && threadIdx.x == 0) rf[(sweep + 1) % 3] = 0;
+  const int k = kpair;
   int I, J;
   if (k == 0) {
     I = round;
@@ -1215,26 +1223,40 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
   copy_out(A + (size_t)j0 * m, sA + (size_t)wI * m, wJ * m, 1.0 / sc);
 }
 
-// Big blocks not yet converged; with `last`, the simulations owning them get
-// their error latched (the sweep limit was reached).
-__global__ void k_big_count(Layer ly, int last) {
-  __shared__ int s_n;
-  if (threadIdx.x == 0) s_n = 0;
-  __syncthreads();
-  int c = 0;
-  for (int k = threadIdx.x; k < ly.total_big; k += blockDim.x) {
-    const int *rf = ly.rotf + 4 * (size_t)k;
-    if (!rf[3]) {
-      ++c;
-      if (last) {
-        const int g = find_gate_big(ly.base, ly.ngates, k);
-        atomicOr(ly.states[ly.gates[g].inst].err, ERR_SVD_NOT_CONVERGED);
-      }
+// Big blocks not yet converged, compacted into the task list of the next
+// panel launches: task_blk[i] = flat index of the i-th still-rotating block,
+// task_pre[i] = its first task (Pp / 2 panel pairs each), task_pre[n] = all
+// tasks; active[0] = blocks, active[1] = tasks.  With `last`, the simulations
+// owning a block that still rotates get their error latched (sweep limit).
+__global__ __launch_bounds__(1024) void k_big_count(Layer ly, int last) {
+  __shared__ int s_iscan[17];
+  int nb = 0, nt = 0;
+  for (int b0 = 0; b0 < ly.total_big; b0 += blockDim.x) {
+    const int k = b0 + threadIdx.x;
+    int act = 0, tasks = 0;
+    if (k < ly.total_big && !ly.rotf[4 * (size_t)k + 3]) {
+      int g, bi;
+      big_block_of(ly, k, g, bi);
+      const BlkDesc &B = ly.blk[ly.gates[g].blk0 + bi];
+      act = 1;
+      tasks = (B.npan + (B.npan & 1)) / 2;
+      if (last) atomicOr(ly.states[ly.gates[g].inst].err, ERR_SVD_NOT_CONVERGED);
     }
+    int tb, tt;
+    const int pb = nb + block_exclusive_scan<int>(act, s_iscan, tb);
+    const int pt = nt + block_exclusive_scan<int>(tasks, s_iscan, tt);
+    if (act) {
+      ly.task_blk[pb] = k;
+      ly.task_pre[pb] = pt;
+    }
+    nb += tb;
+    nt += tt;
   }
-  atomicAdd(&s_n, c);
-  __syncthreads();
-  if (threadIdx.x == 0) *ly.active = s_n;
+  if (threadIdx.x == 0) {
+    ly.task_pre[nb] = nt;
+    ly.active[0] = nb;
+    ly.active[1] = nt;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_big_finish(Layer ly, int sweeps_run) {
@@ -1318,19 +1340,18 @@ hipError_t launch_svd_panel_step(Layer ly, int step, hipStream_t s) {
   // half the LDS per workgroup: two panel workgroups share a CU, one loading
   // or storing its panels while the other rotates
   const int thr = ly.panel_lds <= lb / 2 ? PANEL_THREADS / 2 : PANEL_THREADS;
+  if (ly.ntask <= 0) return hipSuccess;
   if (ly.mixed)
-    hipLaunchKernelGGL(k_panel<cf>, dim3(ly.maxpp / 2, ly.total_big), dim3(thr),
-                       (size_t)ly.panel_lds, s, ly, step);
+    hipLaunchKernelGGL(k_panel<cf>, dim3(ly.ntask), dim3(thr), (size_t)ly.panel_lds, s, ly, step);
   else
-    hipLaunchKernelGGL(k_panel<cd>, dim3(ly.maxpp / 2, ly.total_big), dim3(thr),
-                       (size_t)ly.panel_lds, s, ly, step);
+    hipLaunchKernelGGL(k_panel<cd>, dim3(ly.ntask), dim3(thr), (size_t)ly.panel_lds, s, ly, step);
   return hipGetLastError();
 }
 
 int svd_max_steps(Layer ly) { return MAX_SWEEPS * (ly.maxpp > 1 ? ly.maxpp - 1 : 1) + 1; }
 
 hipError_t launch_svd_count(Layer ly, int last, hipStream_t s) {
-  hipLaunchKernelGGL(k_big_count, dim3(1), dim3(256), 0, s, ly, last);
+  hipLaunchKernelGGL(k_big_count, dim3(1), dim3(1024), 0, s, ly, last);
   return hipGetLastError();
 }
 

@@ -102,7 +102,10 @@ struct Layer {
   cd *V;             // conjugated kept right singular vectors of QR'd blocks (at the R offset)
   int *bigl;         // per gate: local indices of its big blocks (at lst0)
   int *rotf;         // per big block: rotation flags of the two latest sweeps
-  int *active;       // big blocks still rotating after the latest checked sweep
+  int *active;       // [0] big blocks still rotating at the latest check, [1] their tasks
+  int *task_blk;     // flat indices of the still-rotating big blocks
+  int *task_pre;     // first panel task of each (task_pre[nact] = all tasks)
+  int nact, ntask;   // host copies of active[0], active[1] for the panel launches
   int total_big;     // big blocks in the layer
   int maxpp;         // largest even panel count in the layer
   int panel_lds;     // LDS bytes of one panel workgroup
