@@ -703,7 +703,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     }
     {
       PhaseMark pm(E, 5);
-      HIPCHK(launch_leftvec(C, E.stream));
+      HIPCHK(launch_leftvec(C, max_chi, E.stream));
       HIPCHK(launch_scatter(C, max_chi, E.stream));
     }
     {

@@ -1276,6 +1276,9 @@ __global__ __launch_bounds__(256) void k_big_finish(Layer ly, int sweeps_run) {
   }
 }
 
+__global__ void k_leftvec(Layer ly, int nchunk);
+__global__ void k_scatter(Layer ly);
+
 int svd_lds_bytes() {
   // initialised once per process (thread-safe static initialisation)
   static const int bytes = [] {
@@ -1288,6 +1291,10 @@ int svd_lds_bytes() {
     hipFuncSetAttribute((const void *)k_svd_small<cf>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_panel<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_panel<cf>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    hipFuncSetAttribute((const void *)k_qr, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    hipFuncSetAttribute((const void *)k_leftvec, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    hipFuncSetAttribute((const void *)k_scatter, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    hipFuncSetAttribute((const void *)k_big_finish, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     return b;
   }();
   return bytes;
@@ -1492,7 +1499,9 @@ hipError_t launch_select(Layer ly, hipStream_t s) {
 // per vector; u_i goes to the U pool (at the operand offset), conj(v_i) to
 // the V pool (at the R offset), each lane owning fixed rows.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_leftvec(Layer ly) {
+constexpr int LV_CHUNK = 8;    // kept vectors per pass over the pristine sector
+
+__global__ __launch_bounds__(256) void k_leftvec(Layer ly, int nchunk) {
   const int flat = blockIdx.x;
   const int g = find_gate_blk(ly.base, ly.ngates, flat);
   const GateBase gb = ly.base[g];
@@ -1502,7 +1511,7 @@ __global__ __launch_bounds__(256) void k_leftvec(Layer ly) {
   const int m = B.m, n = B.n;
   const cd *A0 = ly.A0 + gb.e + B.eoff;
   const cd *Y = ly.R + gb.r + B.joff;
-  const double *sv = ly.sv + gp.lst0 + B.svoff;
+  double *sv = ly.sv + gp.lst0 + B.svoff;
   const int *perm = ly.perm + gp.lst0 + B.svoff;
   cd *U = ly.U + gb.e + B.eoff;
   cd *V = ly.V + gb.r + B.joff;
@@ -1512,6 +1521,10 @@ __global__ __launch_bounds__(256) void k_leftvec(Layer ly) {
   const int *mx = (!B.t ? ly.mirR : ly.mirL) + gp.mir0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int *piv = ly.piv + gp.lst0 + B.svoff;
+  extern __shared__ double s_dyn[];
+  cd *sV = reinterpret_cast<cd *>(s_dyn);    // LV_CHUNK right vectors, [c][x]
+  __shared__ double s_red[16];
+  // 1. right vectors (conjugated, original column order), one wavefront each
   for (int i0 = 0; i0 < B.kq; i0 += nw) {
     const int i = i0 + wave;
     cd f = cmk(1.0, 0.0);
@@ -1549,41 +1562,68 @@ __global__ __launch_bounds__(256) void k_leftvec(Layer ly) {
       }
     }
     __syncthreads();
-    if (i < B.kq) {
+    if (selfm && i < B.kq) {
       cd *v = V + (size_t)i * n;
-      if (selfm)
-        for (int x = lane; x < n; x += 64) v[x] = cmul(v[x], f);
+      for (int x = lane; x < n; x += 64) v[x] = cmul(v[x], f);
     }
     __syncthreads();
-    if (i < B.kq) {
-      const cd *v = V + (size_t)i * n;
-      cd *u = U + (size_t)i * m;
-      const double s1 = ly.mixed ? 1.0 : 1.0 / sv[i];
-      double nu = 0.0;
-      for (int yy = lane; yy < m; yy += 64) {
-        double re = 0.0, im = 0.0;
-        for (int x = 0; x < n; ++x) {
-          const cd p = cmulc(v[x], A0[(size_t)x * m + yy]);   // A0[y, x] v[x]
-          re += p.re;
-          im += p.im;
-        }
-        u[yy] = cmk(re * s1, im * s1);
-        nu += re * re + im * im;
+  }
+  // 2. U = A0 V, LV_CHUNK vectors per pass over A0 (v from LDS, A0 read once per pass)
+  for (int c0 = 0; c0 < B.kq; c0 += nchunk) {
+    const int nc = min(nchunk, B.kq - c0);
+    for (int idx = threadIdx.x; idx < nc * n; idx += blockDim.x) {
+      const int c = idx / n, x = idx % n;
+      sV[(size_t)c * n + x] = cconj(V[(size_t)(c0 + c) * n + x]);    // v
+    }
+    __syncthreads();
+    double nu[LV_CHUNK];
+#pragma unroll
+    for (int c = 0; c < LV_CHUNK; ++c) nu[c] = 0.0;
+    for (int y = threadIdx.x; y < m; y += blockDim.x) {
+      cd acc[LV_CHUNK];
+#pragma unroll
+      for (int c = 0; c < LV_CHUNK; ++c) acc[c] = cmk(0.0, 0.0);
+      for (int x = 0; x < n; ++x) {
+        const cd a = A0[(size_t)x * m + y];
+#pragma unroll
+        for (int c = 0; c < LV_CHUNK; ++c)
+          if (c < nc) cfma(acc[c], a, sV[(size_t)c * n + x]);
       }
-      if (ly.mixed) {
-        // sigma_i refined in FP64 as |A0 v_i|, u_i normalised (each lane owns its rows)
-        const double lam = sqrt(wave_sum(nu));
+#pragma unroll
+      for (int c = 0; c < LV_CHUNK; ++c)
+        if (c < nc) {
+          const double s1 = ly.mixed ? 1.0 : 1.0 / sv[c0 + c];
+          U[(size_t)(c0 + c) * m + y] = cscale(acc[c], s1);
+          nu[c] += cabs2(acc[c]);
+        }
+    }
+    if (ly.mixed) {
+      // sigma_i refined in FP64 as |A0 v_i|, u_i normalised
+      __shared__ double s_lam[LV_CHUNK];
+      for (int c = 0; c < nc; ++c) {
+        const double t = block_sum(nu[c], s_red);
+        if (threadIdx.x == 0) s_lam[c] = sqrt(t);
+      }
+      __syncthreads();
+      for (int c = 0; c < nc; ++c) {
+        const double lam = s_lam[c];
         const double r = lam > 0.0 ? 1.0 / lam : 0.0;
-        for (int yy = lane; yy < m; yy += 64) u[yy] = cscale(u[yy], r);
-        if (lane == 0) ly.sv[gp.lst0 + B.svoff + i] = lam;
+        for (int y = threadIdx.x; y < m; y += blockDim.x)
+          U[(size_t)(c0 + c) * m + y] = cscale(U[(size_t)(c0 + c) * m + y], r);
+        if (threadIdx.x == 0) sv[c0 + c] = lam;
       }
     }
+    __syncthreads();
   }
 }
 
-hipError_t launch_leftvec(Layer ly, hipStream_t s) {
+hipError_t launch_leftvec(Layer ly, int max_chi, hipStream_t s) {
   if (ly.total_blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_leftvec, dim3(ly.total_blocks), dim3(256), 0, s, ly);
+  // as many vectors per pass as the LDS holds (n <= max_chi entries each)
+  int nchunk = svd_lds_bytes() / (int)(sizeof(cd) * (size_t)max_chi);
+  nchunk = nchunk < 1 ? 1 : (nchunk > LV_CHUNK ? LV_CHUNK : nchunk);
+  hipLaunchKernelGGL(k_leftvec, dim3(ly.total_blocks), dim3(256),
+                     sizeof(cd) * (size_t)nchunk * max_chi, s, ly, nchunk);
   return hipGetLastError();
 }
 

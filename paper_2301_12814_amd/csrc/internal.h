@@ -140,7 +140,7 @@ hipError_t launch_plan_fill(Layer ly, hipStream_t s);
 hipError_t launch_ctab(Layer ly, hipStream_t s);
 hipError_t launch_contract(Layer ly, hipStream_t s);
 hipError_t launch_qr(Layer ly, int max_chi, hipStream_t s);
-hipError_t launch_leftvec(Layer ly, hipStream_t s);
+hipError_t launch_leftvec(Layer ly, int max_chi, hipStream_t s);
 hipError_t launch_svd_small(Layer ly, hipStream_t s);
 hipError_t launch_svd_big_prep(Layer ly, hipStream_t s);
 hipError_t launch_svd_panel_step(Layer ly, int step, hipStream_t s);
