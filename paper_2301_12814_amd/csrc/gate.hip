@@ -578,6 +578,35 @@ hipError_t launch_contract(Layer ly, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(h2, l2);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_d(float v) {
+  const int x = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false));
+}
+
+// Sum over a group of L lanes: xor 1 and xor 2 inside each quad, the row
+// mirror (quad q with quad 3 - q), the half-row mirror (quad 0 with 1, 2
+// with 3), then xor 16 and xor 32 across rows.  Every step adds two values
+// in an order-independent way, so all lanes of the group end with bitwise
+// the same sum (the callers branch on it).
+template <int L, typename R>
+__device__ __forceinline__ R group_sum(R v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x140>(v);
+  v += dpp_d<0x141>(v);
+  if (L >= 32) v += __shfl_xor(v, 16, 64);
+  if (L >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
 // ----------------------------------------------------------------------------
 // Householder QR with column pivoting of the large blocks: A P = Q R with
 // Q = H_0 H_1 ... H_{n-1}, H_k = I - tau_k v_k v_k^H, v_k[0] = 1.  Step k
@@ -591,7 +620,8 @@ hipError_t launch_contract(Layer ly, hipStream_t s) {
 // and the pivot order to piv (piv[k] = original column at position k).
 // The column pivoting grades R, so that the Jacobi on X needs few sweeps.
 // ----------------------------------------------------------------------------
-constexpr int QR_THREADS = 512;
+constexpr int QR_THREADS = 1024;
+constexpr int QC = 16;   // column elements per lane kept in registers (m - k <= 1024)
 
 __device__ __forceinline__ double block_sum(double v, double *s_red);
 
@@ -694,27 +724,63 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly) {
     }
     __syncthreads();
     const cd ct = skip ? cmk(0.0, 0.0) : cconj(s_tau);
-    for (int j = k + 1 + wave; j < n; j += nw) {
-      cd *a = A + (size_t)j * m + k;
-      double wr = 0.0, wi = 0.0;
-      if (!skip) {
-        for (int y = lane; y < len; y += 64) {
-          const cd q = cmulc(v[y], a[y]);
-          wr += q.re;
-          wi += q.im;
+    if (len <= 64 * QC) {
+      // column segment held in registers between the dot product and the update
+      for (int j = k + 1 + wave; j < n; j += nw) {
+        cd *a = A + (size_t)j * m + k;
+        cd ra[QC];
+        double wr = 0.0, wi = 0.0;
+#pragma unroll
+        for (int u = 0; u < QC; ++u) {
+          const int y = lane + 64 * u;
+          ra[u] = y < len ? a[y] : cmk(0.0, 0.0);
+          if (y < len && !skip) {
+            const cd q = cmulc(v[y], ra[u]);
+            wr += q.re;
+            wi += q.im;
+          }
         }
-        wr = wave_sum(wr);
-        wi = wave_sum(wi);
+        if (!skip) {
+          wr = group_sum<64>(wr);
+          wi = group_sum<64>(wi);
+        }
+        const cd f = cmul(ct, cmk(wr, wi));    // conj(tau) v^H a
+        double nb = 0.0;
+#pragma unroll
+        for (int u = 0; u < QC; ++u) {
+          const int y = lane + 64 * u;
+          if (y < len) {
+            const cd an = skip ? ra[u] : csub(ra[u], cmul(f, v[y]));
+            if (!skip) a[y] = an;
+            if (y >= 1) nb += cabs2(an);
+          }
+        }
+        nb = group_sum<64>(nb);
+        if (lane == 0) cn[j] = nb;
       }
-      const cd f = cmul(ct, cmk(wr, wi));    // conj(tau) v^H a
-      double nb = 0.0;
-      for (int y = lane; y < len; y += 64) {
-        const cd an = skip ? a[y] : csub(a[y], cmul(f, v[y]));
-        if (!skip) a[y] = an;
-        if (y >= 1) nb += cabs2(an);
+    } else {
+      for (int j = k + 1 + wave; j < n; j += nw) {
+        cd *a = A + (size_t)j * m + k;
+        double wr = 0.0, wi = 0.0;
+        if (!skip) {
+          for (int y = lane; y < len; y += 64) {
+            const cd q = cmulc(v[y], a[y]);
+            wr += q.re;
+            wi += q.im;
+          }
+          wr = group_sum<64>(wr);
+          wi = group_sum<64>(wi);
+        }
+        const cd f = cmul(ct, cmk(wr, wi));    // conj(tau) v^H a
+        double nb = 0.0;
+        for (int y = lane; y < len; y += 64) {
+          const cd an = skip ? a[y] : csub(a[y], cmul(f, v[y]));
+          if (!skip) a[y] = an;
+          if (y >= 1) nb += cabs2(an);
+        }
+        nb = group_sum<64>(nb);
+        if (lane == 0) cn[j] = nb;
       }
-      nb = wave_sum(nb);
-      if (lane == 0) cn[j] = nb;
     }
     __syncthreads();
   }
@@ -757,35 +823,6 @@ constexpr int RPL = 8;          // column rows cached per lane (m <= 512)
 // group busy).  Dot products reduce with DPP steps inside a row, plus one or
 // two cross-row butterflies for L = 32, 64.
 constexpr int CE = 8;    // elements per lane kept in registers (m <= L * CE)
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
-  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
-  return __hiloint2double(h2, l2);
-}
-template <int CTRL>
-__device__ __forceinline__ float dpp_d(float v) {
-  const int x = __float_as_int(v);
-  return __int_as_float(__builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false));
-}
-
-// Sum over a group of L lanes: xor 1 and xor 2 inside each quad, the row
-// mirror (quad q with quad 3 - q), the half-row mirror (quad 0 with 1, 2
-// with 3), then xor 16 and xor 32 across rows.  Every step adds two values
-// in an order-independent way, so all lanes of the group end with bitwise
-// the same sum (the callers branch on it).
-template <int L, typename R>
-__device__ __forceinline__ R group_sum(R v) {
-  v += dpp_d<0xB1>(v);
-  v += dpp_d<0x4E>(v);
-  v += dpp_d<0x140>(v);
-  v += dpp_d<0x141>(v);
-  if (L >= 32) v += __shfl_xor(v, 16, 64);
-  if (L >= 64) v += __shfl_xor(v, 32, 64);
-  return v;
-}
 
 // One rotation of the column pair (x, y) by one group of L lanes (gl = lane
 // in the group).  The squared norms al = |x|^2, be = |y|^2 are tracked in
