@@ -858,13 +858,14 @@ __device__ __forceinline__ void jacobi_pair(T *xp, T *xq, double *nx, double *ny
     }
   }
   const double grd = group_sum<L>(gr), gid = group_sum<L>(gi);
-  const double ga = sqrt(grd * grd + gid * gid);
-  if (!(ga > tol * sqrt(al * be)) || ga < 1e-300) return;
-  const double zeta = (be - al) / (2.0 * ga);
+  const double ga2 = grd * grd + gid * gid;
+  if (!(ga2 > tol * tol * (al * be)) || !(ga2 > 1e-300)) return;
+  const double ga = sqrt(ga2), rga = 1.0 / ga;
+  const double zeta = (be - al) * (0.5 * rga);
   const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   const double cd_ = 1.0 / sqrt(1.0 + t * t);
   const R c = (R)cd_, s = (R)(cd_ * t);
-  const T e = T{(R)(grd / ga), (R)(-gid / ga)};      // e^{-i psi}
+  const T e = T{(R)(grd * rga), (R)(-gid * rga)};    // e^{-i psi}
   double al2 = al - t * ga, be2 = be + t * ga;
   const bool exact = !(al2 >= 0.5 * al) || !(be2 >= 0.5 * be);
   R na = 0, nb = 0;
