@@ -822,7 +822,10 @@ constexpr int RPL = 8;          // column rows cached per lane (m <= 512)
 // pairs per wavefront; 32 or 64 when a round has too few pairs to keep every
 // group busy).  Dot products reduce with DPP steps inside a row, plus one or
 // two cross-row butterflies for L = 32, 64.
-constexpr int CE = 8;    // elements per lane kept in registers (m <= L * CE)
+#ifndef GBS_CE
+#define GBS_CE 8
+#endif
+constexpr int CE = GBS_CE;   // elements per lane kept in registers (m <= L * CE)
 
 // One rotation of the column pair (x, y) by one group of L lanes (gl = lane
 // in the group).  The squared norms al = |x|^2, be = |y|^2 are tracked in
@@ -1191,7 +1194,10 @@ __global__ __launch_bounds__(256) void k_big_prep(Layer ly) {
   }
 }
 
-constexpr int PANEL_THREADS = 1024;
+#ifndef GBS_PANEL_THREADS
+#define GBS_PANEL_THREADS 1024
+#endif
+constexpr int PANEL_THREADS = GBS_PANEL_THREADS;
 
 // Launch t of the panel rounds: every big block runs its own sequence of
 // sweeps, Pp - 1 rounds each (Pp = panel count rounded up to even), so block
@@ -1384,7 +1390,8 @@ hipError_t launch_svd_panel_step(Layer ly, int step, hipStream_t s) {
   const int lb = svd_lds_bytes();
   // half the LDS per workgroup: two panel workgroups share a CU, one loading
   // or storing its panels while the other rotates
-  const int thr = ly.panel_lds <= lb / 2 ? PANEL_THREADS / 2 : PANEL_THREADS;
+  const int thr = (ly.panel_lds <= lb / 2 && PANEL_THREADS > 256) ? PANEL_THREADS / 2
+                                                                  : PANEL_THREADS;
   if (ly.ntask <= 0) return hipSuccess;
   if (ly.mixed)
     hipLaunchKernelGGL(k_panel<cf>, dim3(ly.ntask), dim3(thr), (size_t)ly.panel_lds, s, ly, step);
