@@ -362,15 +362,18 @@ def main():
             g.sync()
             print(f"warmup {i}: {time.time() - t0:.3f} s", file=sys.stderr, flush=True)
 
+    import torch
     handles = [gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi, prec) for _ in range(args.steps)]
     for g in handles:
         g.set_profiling(True)
         g.sync()
+    torch.cuda.synchronize()          # every stream of the device, the library's included
     t0 = time.perf_counter()
     for i, g in enumerate(handles):
         evolve(g)
         g.sync()
         print(f"step {i}: {time.perf_counter() - t0:.3f} s cumulative", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
 

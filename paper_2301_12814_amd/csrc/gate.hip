@@ -1261,8 +1261,15 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
   } else {
     cross_pass_l<GBS_PANEL_LANES>(sA, s_nrm, m, w, wI, wJ, tol, tiny, rot);
   }
-  if (rot) rf[sweep % 3] = 1;
+  __shared__ int s_any;
+  if (threadIdx.x == 0) s_any = 0;
   __syncthreads();
+  if (rot) {
+    rf[sweep % 3] = 1;
+    s_any = 1;
+  }
+  __syncthreads();
+  if (!s_any) return;          // nothing rotated: the panels in memory are unchanged
   copy_out(A + (size_t)i0 * m, sA, wI * m, 1.0 / sc);
   copy_out(A + (size_t)j0 * m, sA + (size_t)wI * m, wJ * m, 1.0 / sc);
 }
