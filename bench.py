@@ -6,6 +6,11 @@ eta=0.3, d=8, chi=1024, seeded Haar-random 64x64 interferometer = 2016 beam
 splitters in 64 layers) from its initial state, which is built on the device
 before the timed region.  value = 2016 * steps / wall time of the steps.
 
+The timed region is bracketed by the library's own stream synchronisation
+(every handle is synchronised before the clock starts and after each step).
+PyTorch is not loaded on these paths: its wheel bundles a second HIP runtime,
+and the library runs on the system one.
+
 Also reported: the dominant kernel's roofline (HIP events on the library's
 stream, averaged over the timed launches; algorithmic work from the sector
 plan) and the FP64 dense oracle timed on this host (cpu_baseline).
@@ -226,11 +231,10 @@ def run_serve(args, prec):
     with chi >= 1024 go to the heavy lane, the rest to the light lane (a light
     request never waits for a heavy request's layer)."""
     import threading
-    import torch
     from paper_2301_12814_amd import gbsmpo, inputs
     reqs = inputs.serving_requests(args.requests, args.rate)
     Us = [inputs.haar_unitary(w.M, w.seed) for _, w in reqs]
-    free, _ = torch.cuda.mem_get_info()
+    free, _ = gbsmpo.device_memory()
     heavy = [k for k, (_, w) in enumerate(reqs) if w.chi >= 1024]
     light = [k for k, (_, w) in enumerate(reqs) if w.chi < 1024]
     lat = {}                 # request -> latency
@@ -362,18 +366,15 @@ def main():
             g.sync()
             print(f"warmup {i}: {time.time() - t0:.3f} s", file=sys.stderr, flush=True)
 
-    import torch
     handles = [gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi, prec) for _ in range(args.steps)]
     for g in handles:
         g.set_profiling(True)
         g.sync()
-    torch.cuda.synchronize()          # every stream of the device, the library's included
     t0 = time.perf_counter()
     for i, g in enumerate(handles):
         evolve(g)
         g.sync()
         print(f"step {i}: {time.perf_counter() - t0:.3f} s cumulative", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
 

@@ -68,8 +68,12 @@ enum { MPO_FP64 = 0, MPO_MIXED = 1 };
  *   eta      uniform transmission, 0 < eta <= 1
  *   d        per-mode Fock cutoff, 2 <= d <= 16
  *   chi      bond dimension, 1 <= chi <= 4096
- *   precision MPO_FP64 or MPO_MIXED (split-bf16 sector contractions)
- *   hip_stream  hipStream_t to run on, or NULL for a stream owned by the handle
+ *   precision MPO_FP64, or MPO_MIXED: the block SVDs' Jacobi rotations run in
+ *            FP32 on operands normalised to unit norm, everything else in FP64,
+ *            kept singular values and vectors refined in FP64 (faster, less
+ *            accurate: about 1e-7 relative on the kept vectors per gate)
+ *   hip_stream  hipStream_t to run on (created with the HIP runtime this library links),
+ *               or NULL for a stream owned by the handle
  *   out      receives the new handle
  * Each mode's state is built in a large internal Fock space, lossy, then
  * cropped to [0, d)^2 (no renormalisation).  The exact product Vidal form is
@@ -176,6 +180,10 @@ int mpo_layer_blocks(gbs_mpo *h, int max_blocks, int *out);
  * is first reduced by a Householder QR when qr_enable != 0.  0 restores the
  * device budget.  Affects layers planned after the call; not thread-safe. */
 int gbs_set_svd_route(int lds_limit_bytes, int qr_enable);
+
+/* Free and total bytes of the current device's memory (hipMemGetInfo), for
+ * callers that size admission budgets.  MPO_EDEVICE on a runtime error. */
+int gbs_device_memory(long long *free_bytes, long long *total_bytes);
 
 /* Releases every device allocation of the handle (NULL is a no-op). */
 void mpo_free(gbs_mpo *h);

@@ -792,6 +792,15 @@ bool valid_layer(int M, int n_gates, const int *left_site, const double *theta,
 // ============================================================================
 extern "C" const char *mpo_last_error(void) { return g_err.c_str(); }
 
+extern "C" int gbs_device_memory(long long *free_bytes, long long *total_bytes) {
+  if (!free_bytes || !total_bytes) return fail(MPO_EINVAL, "NULL argument");
+  size_t fb = 0, tb = 0;
+  HIPCHK(hipMemGetInfo(&fb, &tb));
+  *free_bytes = (long long)fb;
+  *total_bytes = (long long)tb;
+  return MPO_OK;
+}
+
 extern "C" int gbs_set_svd_route(int lds_limit_bytes, int qr_enable) {
   if (lds_limit_bytes < 0) return fail(MPO_EINVAL, "LDS limit must be >= 0");
   set_svd_route(lds_limit_bytes, qr_enable);

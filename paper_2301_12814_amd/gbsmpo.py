@@ -55,6 +55,8 @@ def lib() -> ctypes.CDLL:
         L.mpo_set_profiling.argtypes = [c_void_p, c_int]
         L.mpo_get_profile.argtypes = [c_void_p, pd, pll, pd]
         L.mpo_layer_blocks.argtypes = [c_void_p, c_int, pi]
+        L.gbs_device_memory.argtypes = [pll, pll]
+        L.gbs_device_memory.restype = c_int
         L.gbs_set_svd_route.argtypes = [c_int, c_int]
         L.gbs_set_svd_route.restype = c_int
         pe = ctypes.POINTER(c_void_p)
@@ -96,11 +98,14 @@ def _ip(a):
 
 
 def _stream_handle(stream):
+    """A raw hipStream_t (int) of the system HIP runtime the library links, or
+    None for the library's own stream.  (PyTorch wheels bundle a second HIP
+    runtime whose streams are not valid here.)"""
     if stream is None:
         return None
     if isinstance(stream, int):
         return ctypes.c_void_p(stream)
-    return ctypes.c_void_p(int(stream.cuda_stream))      # torch.cuda.Stream
+    raise TypeError("stream must be None or an int hipStream_t of the library's HIP runtime")
 
 
 def clements(U: np.ndarray):
@@ -220,6 +225,13 @@ class MPO:
                                      _dp(work)))
         return (dict(zip(self.PHASES, ms.tolist())), dict(zip(self.PHASES, n.tolist())),
                 dict(svd_flops=work[0], elements=work[1], candidates=work[2], layers=work[3]))
+
+
+def device_memory():
+    """(free, total) device bytes of the current device."""
+    f, t = ctypes.c_longlong(), ctypes.c_longlong()
+    _check(lib().gbs_device_memory(ctypes.byref(f), ctypes.byref(t)))
+    return f.value, t.value
 
 
 def set_svd_route(lds_limit_bytes=0, qr_enable=True):
