@@ -82,7 +82,7 @@ def cpu_baseline(budget_s: float = 25.0):
 
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "svd_stage_large_fp64_pmc.txt")
-STAGE_SOURCES = ("paper_2301_12814_amd/csrc/gate.hip", "paper_2301_12814_amd/csrc/api.cpp")
+STAGE_SOURCES = ("paper_2301_12814_amd/csrc/gate.hip",)   # the stage's kernels
 
 
 def _sources_digest():
