@@ -119,7 +119,7 @@ struct Engine {
   DBuf<GateTot> d_tot;
   DBuf<GateBase> d_base;
   DBuf<cd> d_fock;
-  DBuf<int> d_mirL, d_mirR, d_ctab;
+  DBuf<int> d_mirL, d_mirR, d_ctab, d_runs;
   GateParam *h_gates = nullptr;
   GateTot *h_tot = nullptr;
   GateBase *h_base = nullptr;
@@ -256,6 +256,7 @@ void engine_destroy(Engine &E) {
   E.d_mirL.release();
   E.d_mirR.release();
   E.d_ctab.release();
+  E.d_runs.release();
   E.d_blk.release();
   E.d_rows.release();
   E.d_cols.release();
@@ -497,7 +498,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
   rc = ensure_host(E, n);
   if (rc != MPO_OK) return rc;
   long long fk = 0, mr = 0;
-  int max_chi = 1;
+  int max_chi = 1, max_d = 2;
   for (int g = 0; g < n; ++g) {
     GateParam gp = gates[g];
     const State &st = E.inst[gp.inst].st;
@@ -508,6 +509,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     fk += (long long)(2 * st.d - 1) * st.d * st.d;
     mr += st.chi;
     max_chi = std::max(max_chi, st.chi);
+    max_d = std::max(max_d, st.d);
     E.h_gates[g] = gp;
   }
   HIPCHK(E.d_gates.ensure(n));
@@ -600,6 +602,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
       maxpp = std::max(maxpp, t.maxpp);
     }
     HIPCHK(E.d_blk.ensure(blk0));
+    HIPCHK(E.d_runs.ensure((size_t)blk0 * 64));
     HIPCHK(E.d_rows.ensure(lst0));
     HIPCHK(E.d_cols.ensure(lst0));
     HIPCHK(E.d_bigl.ensure(lst0));
@@ -629,6 +632,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     C.tot = E.d_tot.p + c0;
     C.base = E.d_base.p;
     C.blk = E.d_blk.p;
+    C.runs = E.d_runs.p;
     C.rows = E.d_rows.p;
     C.cols = E.d_cols.p;
     C.bigl = E.d_bigl.p;
@@ -660,7 +664,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     }
     {
       PhaseMark pm(E, 2);
-      HIPCHK(launch_contract(C, E.stream));
+      HIPCHK(launch_contract(C, max_chi, max_d, E.stream));
     }
     int sweeps_run = 0;
     {

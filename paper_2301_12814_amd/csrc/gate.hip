@@ -91,6 +91,7 @@ __device__ inline int count_window(const int *c, int D, int n, int lo, int hi) {
 }
 
 constexpr int CHUNK = 256;
+constexpr int RUNS_PER_BLOCK = 64;   // 4 tables of up to 16 (d <= 16) per block
 
 // LDS bytes of the one-workgroup Jacobi (operand + column norms) and the
 // widest panel whose pair (2 w columns of m rows) fits in LDS.
@@ -400,22 +401,30 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
     eb += te; reb += tre; svb += tsv; rb += tr; cb += tc; chb += tch; bgb += tbg;
   }
   __syncthreads();
-  // pass 3: row / column index lists (ascending)
+  // pass 3: row / column index lists (ascending) and, per block, the run
+  // tables of the contraction: for k in [0, d), the rows with n = q0 + k start
+  // at list position runs[k] and bond index runs[16 + k]; the columns with
+  // n = q0 - k at list position runs[32 + k] and bond index runs[48 + k]
   int *rows = ly.rows + gp.lst0;
   int *cols = ly.cols + gp.lst0;
   for (int bi = threadIdx.x; bi < nblk; bi += blockDim.x) {
     const BlkDesc B = blk[bi];
     const int q0 = charge_n(B.q), q1 = charge_np(B.q);
+    int *run = ly.runs + (size_t)(gp.blk0 + bi) * RUNS_PER_BLOCK;
     int k = 0;
     for (int n = q0; n <= q0 + d - 1; ++n) {
       const int a0 = lower_bound(cL, DL, pack_charge(n, q1));
       const int a1 = lower_bound(cL, DL, pack_charge(n, q1 + d));
+      run[n - q0] = k;
+      run[16 + n - q0] = a0;
       for (int a = a0; a < a1; ++a) rows[B.roff + k++] = a;
     }
     k = 0;
     for (int n = max(q0 - d + 1, 0); n <= q0; ++n) {
       const int b0 = lower_bound(cR, DR, pack_charge(n, max(q1 - d + 1, 0)));
       const int b1 = lower_bound(cR, DR, pack_charge(n, q1 + 1));
+      run[32 + q0 - n] = k;
+      run[48 + q0 - n] = b0;
       for (int b = b0; b < b1; ++b) cols[B.coff + k++] = b;
     }
   }
@@ -477,75 +486,157 @@ __device__ inline int find_gate_big(const GateBase *base, int ng, int flat) {
 }
 
 // ----------------------------------------------------------------------------
-// Theta(q) blocks: one 256-element chunk of one block per workgroup, one
-// element per thread (b fastest).  The sum over alpha runs over the bond-C
-// charges p with c_a - p and p - c_b both in [0,d)^2: p0 in
-// [max(c_b0, c_a0-d+1), min(c_b0+d-1, c_a0)], same for p1, i.e. one
-// contiguous run of the sorted bond per p0.
+// Theta(q) blocks in two stages.  For a pair (a, b) of outer indices the
+// centre charges p that connect them form the box P(a, b) = [max(c_b,
+// c_a - d + 1), min(c_b + d - 1, c_a)] (componentwise), and the new centre
+// charges q of the blocks holding (a, b) form the same box.  The weight
+// factorises into a ket and a bra part, W = K_q0[p0] conj(B_q1[p1]) with
+// K = U[n0][c_a0 - q0][c_a0 - p0], B = U[n1][c_a1 - q1][c_a1 - p1],
+// (n0, n1) = c_a - c_b.  So per (a, b, q0):
+//   G_p   = sum_{alpha of charge p} Gamma_j[a, alpha] lam_C[alpha] Gamma_{j+1}[alpha, b]
+//   H[q1] = sum_{p1} conj(B_q1[p1]) G_(p0, p1)            (for each p0)
+//   Theta(q0, q1)[a, b] = lam_L[a] lam_R[b] sum_{p0} K_q0[p0] H[q1]
+// each G_p is formed once instead of once per q1, and the Fock weights are
+// applied to charge sums instead of to every alpha term.  One workgroup per
+// (gate, row a); its threads run over the (b, q0) pairs of the row.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(CHUNK) void k_contract(Layer ly) {
-  const long long chunk = blockIdx.x;
-  const int g = find_gate_chunk(ly.base, ly.ngates, chunk);
+template <int DMAX>
+__global__ __launch_bounds__(256) void k_contract(Layer ly, int max_chi) {
+  const int g = blockIdx.x / max_chi;
+  const int a = blockIdx.x % max_chi;
   const GateParam gp = ly.gates[g];
   const State st = ly.states[gp.inst];
   const int d = st.d, chi = st.chi;
   const int j = gp.site;
-  const GateBase gb = ly.base[g];
-  const int nblk = ly.tot[g].nblk;
-  const BlkDesc *blk = ly.blk + gp.blk0;
-  // block containing this chunk (chunk offsets stored in uoff)
-  const int lc = (int)(chunk - gb.echunk);
-  int lo = 0, hi = nblk;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (blk[mid].uoff <= lc) lo = mid; else hi = mid;
-  }
-  const BlkDesc B = blk[lo];
-  const long long e = (long long)(lc - B.uoff) * CHUNK + threadIdx.x;
-  if (e >= (long long)B.r * B.s) return;
-  const int ia = (int)(e / B.s), ib = (int)(e % B.s);
-  const int a = ly.rows[gp.lst0 + B.roff + ia];
-  const int b = ly.cols[gp.lst0 + B.coff + ib];
+  const int DL = st.dim[j], DR = st.dim[j + 2];
+  if (a >= DL || DR == 0) return;
+  const GateTot gt = ly.tot[g];
+  if (gt.nblk == 0) return;
   const int *cL = st.chg + (size_t)j * chi;
-  const int *cC = st.chg + (size_t)(j + 1) * chi;
   const int *cR = st.chg + (size_t)(j + 2) * chi;
-  const int DC = st.dim[j + 1];
-  const int ca = cL[a], cb = cR[b];
-  const int ca0 = charge_n(ca), ca1 = charge_np(ca), cb0 = charge_n(cb), cb1 = charge_np(cb);
-  const int q0 = charge_n(B.q), q1 = charge_np(B.q);
-  const int n0 = ca0 - cb0, n1 = ca1 - cb1;
-  const int i0 = ca0 - q0, i1 = ca1 - q1;
+  const int ca = cL[a];
+  const int ca0 = charge_n(ca), ca1 = charge_np(ca);
+  // runs of b: for each n0 in [ca0 - 2d + 2, ca0], the indices with n1 in
+  // [ca1 - 2d + 2, ca1]; a run of n0 contributes len * |Q0| (b, q0) items
+  __shared__ int s_b0[32], s_len[32], s_nq[32], s_item[33];
+  const int nrun = 2 * d - 1;
+  if (threadIdx.x < nrun) {
+    const int n0 = ca0 - 2 * d + 2 + (int)threadIdx.x;
+    int b0 = 0, len = 0, nq = 0;
+    if (n0 >= 0) {
+      b0 = lower_bound(cR, DR, pack_charge(n0, max(ca1 - 2 * d + 2, 0)));
+      len = lower_bound(cR, DR, pack_charge(n0, ca1 + 1)) - b0;
+      // q0 in [max(n0, ca0 - d + 1), min(n0 + d - 1, ca0)]
+      nq = min(n0 + d - 1, ca0) - max(n0, ca0 - d + 1) + 1;
+    }
+    s_b0[threadIdx.x] = b0;
+    s_len[threadIdx.x] = len;
+    s_nq[threadIdx.x] = nq;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int r = 0; r < nrun; ++r) {
+      s_item[r] = acc;
+      acc += s_len[r] * s_nq[r];
+    }
+    s_item[nrun] = acc;
+  }
+  __syncthreads();
+  const int nitem = s_item[nrun];
   const cd *tab = ly.fock + gp.fock0;
   const cd *Ga = st.gam + (size_t)j * chi * chi + (size_t)a * chi;
-  const cd *Gb = st.gam + (size_t)(j + 1) * chi * chi + b;
   const double *lC = st.lam + (size_t)(j + 1) * chi;
-  const GateTot gt = ly.tot[g];
+  const double la = st.lam[(size_t)j * chi + a];
   const int W1 = gt.c1hi + 2;
   const int *T = ly.ctab + gp.ct0;
-  const int p0lo = max(max(cb0, ca0 - d + 1), gt.c0lo), p0hi = min(min(cb0 + d - 1, ca0), gt.c0hi);
-  const int p1lo = min(max(cb1, ca1 - d + 1), W1 - 1), p1hi = min(min(cb1 + d - 1, ca1) + 1, W1 - 1);
-  (void)DC;
-  cd acc = cmk(0.0, 0.0);
-  for (int p0 = p0lo; p0 <= p0hi; ++p0) {
-    // bond-C indices with charge (p0, p1), p1 in [p1lo, p1hi): one table run
-    const int *Tp = T + (size_t)(p0 - gt.c0lo) * W1;
-    const int al0 = Tp[p1lo];
-    const int al1 = Tp[p1hi];
-    const cd wk = tab[((size_t)n0 * d + i0) * d + (ca0 - p0)];
-    for (int al = al0; al < al1; ++al) {
-      const int p1 = charge_np(cC[al]);
-      const cd wb = tab[((size_t)n1 * d + i1) * d + (ca1 - p1)];
-      const cd w = cmulc(wb, wk);                        // U_ket * conj(U_bra)
-      const cd x = cscale(cmul(Ga[al], Gb[(size_t)al * chi]), lC[al]);
-      cfma(acc, w, x);
+  const BlkDesc *blk = ly.blk + gp.blk0;
+  const long long ebase = ly.base[g].e;
+  for (int it = threadIdx.x; it < nitem; it += blockDim.x) {
+    int r = 0;
+    while (s_item[r + 1] <= it) ++r;
+    // consecutive threads take consecutive b of one q0 (coalesced Gamma_{j+1} reads)
+    const int off = it - s_item[r];
+    const int len = s_len[r];
+    const int b = s_b0[r] + off % len;
+    const int n0b = ca0 - 2 * d + 2 + r;                      // c_b0
+    const int q0 = max(n0b, ca0 - d + 1) + off / len;
+    const int cb = cR[b];
+    const int cb1 = charge_np(cb);
+    const int n0 = ca0 - n0b, n1 = ca1 - cb1;
+    if (n1 < 0 || n1 > 2 * d - 2) continue;
+    const int i0 = ca0 - q0;
+    // p0 range (also the q0 box), p1 / q1 range
+    const int p0lo = max(max(n0b, ca0 - d + 1), gt.c0lo), p0hi = min(min(n0b + d - 1, ca0), gt.c0hi);
+    const int q1lo = max(cb1, ca1 - d + 1), q1hi = min(cb1 + d - 1, ca1);
+    const int nq1 = q1hi - q1lo + 1;
+    const cd *Gb = st.gam + (size_t)(j + 1) * chi * chi + b;
+    cd acc[DMAX];
+#pragma unroll
+    for (int u = 0; u < DMAX; ++u) acc[u] = cmk(0.0, 0.0);
+    for (int p0 = p0lo; p0 <= p0hi; ++p0) {
+      const int *Tp = T + (size_t)(p0 - gt.c0lo) * W1;
+      cd H[DMAX];
+#pragma unroll
+      for (int u = 0; u < DMAX; ++u) H[u] = cmk(0.0, 0.0);
+      bool any = false;
+      for (int p1 = q1lo; p1 <= q1hi; ++p1) {
+        if (p1 > gt.c1hi) break;
+        const int al0 = Tp[p1], al1 = Tp[p1 + 1];
+        if (al0 >= al1) continue;
+        cd G = cmk(0.0, 0.0);
+        for (int al = al0; al < al1; ++al)
+          cfma(G, Ga[al], cscale(Gb[(size_t)al * chi], lC[al]));
+        any = true;
+        // H[q1] += conj(U[n1][ca1 - q1][ca1 - p1]) G
+        const cd *Bcol = tab + (size_t)n1 * d * d + (ca1 - p1);
+#pragma unroll
+        for (int u = 0; u < DMAX; ++u)
+          if (u < nq1) cfma(H[u], cconj(Bcol[(size_t)(ca1 - q1lo - u) * d]), G);
+      }
+      if (!any) continue;
+      const cd K = tab[((size_t)n0 * d + i0) * d + (ca0 - p0)];
+#pragma unroll
+      for (int u = 0; u < DMAX; ++u)
+        if (u < nq1) cfma(acc[u], K, H[u]);
+    }
+    // write Theta(q0, q1)[a, b] into every computed block (q0, q1)
+    const double sc = la * st.lam[(size_t)(j + 2) * chi + b];
+#pragma unroll
+    for (int u = 0; u < DMAX; ++u) {
+      if (u >= nq1) continue;
+      const int q = pack_charge(q0, q1lo + u);
+      int lo = 0, hi = gt.nblk;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (blk[mid].q < q) lo = mid + 1; else hi = mid;
+      }
+      if (lo >= gt.nblk || blk[lo].q != q) continue;
+      const BlkDesc &B = blk[lo];
+      if (!B.comp) continue;
+      const int *run = ly.runs + (size_t)(gp.blk0 + lo) * RUNS_PER_BLOCK;
+      const int ka = ca0 - q0, kb = q0 - n0b;
+      const int ia = run[ka] + (a - run[16 + ka]);
+      const int ib = run[32 + kb] + (b - run[48 + kb]);
+      const size_t at = !B.t ? (size_t)ib * B.m + ia       // Theta, m = r rows
+                             : (size_t)ia * B.m + ib;      // Theta^T, m = s rows
+      const cd v = cscale(acc[u], sc);
+      ly.A[ebase + B.eoff + at] = v;
+      ly.A0[ebase + B.eoff + at] = v;
     }
   }
-  const double sc = st.lam[(size_t)j * chi + a] * st.lam[(size_t)(j + 2) * chi + b];
-  acc = cscale(acc, sc);
-  const size_t at = !B.t ? (size_t)ib * B.m + ia       // Theta, m = r rows
-                         : (size_t)ia * B.m + ib;      // Theta^T, m = s rows
-  ly.A[gb.e + B.eoff + at] = acc;
-  ly.A0[gb.e + B.eoff + at] = acc;
+}
+
+hipError_t launch_contract(Layer ly, int max_chi, int max_d, hipStream_t s) {
+  if (ly.total_blocks == 0) return hipSuccess;
+  const dim3 grid((unsigned)(ly.ngates * max_chi));
+  if (max_d <= 4)
+    hipLaunchKernelGGL(k_contract<4>, grid, dim3(256), 0, s, ly, max_chi);
+  else if (max_d <= 8)
+    hipLaunchKernelGGL(k_contract<8>, grid, dim3(256), 0, s, ly, max_chi);
+  else
+    hipLaunchKernelGGL(k_contract<16>, grid, dim3(256), 0, s, ly, max_chi);
+  return hipGetLastError();
 }
 
 // Centre-bond run table of every gate: T[x][y] = first index of the sorted
@@ -572,11 +663,6 @@ hipError_t launch_ctab(Layer ly, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_contract(Layer ly, hipStream_t s) {
-  if (ly.total_chunks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_contract, dim3((unsigned)ly.total_chunks), dim3(CHUNK), 0, s, ly);
-  return hipGetLastError();
-}
 
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {

@@ -91,6 +91,7 @@ struct Layer {
   GateBase *base;    // ngates
   int *rows, *cols;  // per-gate row / column index lists (at lst0)
   int *mirL, *mirR;  // per gate: mirror index on the left / right bond, -1 if none (at mir0)
+  int *runs;         // per block (at 64 x the flat block index): row / column runs by charge
   int *ctab;         // per gate (at ct0): first centre-bond index with charge >= (c0lo + x, y),
                      // [x][y] for x in [0, c0hi - c0lo + 2), y in [0, c1hi + 2)
   cd *A;             // sector operands (overwritten by U * Sigma)
@@ -138,7 +139,7 @@ hipError_t launch_fock(Layer ly, hipStream_t s);
 hipError_t launch_plan_count(Layer ly, hipStream_t s);
 hipError_t launch_plan_fill(Layer ly, hipStream_t s);
 hipError_t launch_ctab(Layer ly, hipStream_t s);
-hipError_t launch_contract(Layer ly, hipStream_t s);
+hipError_t launch_contract(Layer ly, int max_chi, int max_d, hipStream_t s);
 hipError_t launch_qr(Layer ly, int max_chi, hipStream_t s);
 hipError_t launch_leftvec(Layer ly, int max_chi, hipStream_t s);
 hipError_t launch_svd_small(Layer ly, hipStream_t s);
