@@ -98,12 +98,16 @@ constexpr int RUNS_PER_BLOCK = 64;   // 4 tables of up to 16 (d <= 16) per block
 __host__ __device__ inline size_t svd_small_need(int m, int n, int esz) {
   return (size_t)esz * m * n + sizeof(double) * (size_t)n;
 }
-// Widest panel (32, 16, ..., 1) whose pair (2 w columns of m elements of esz
-// bytes) fits in lds_bytes.
-__host__ __device__ inline int panel_width(int m, int lds_bytes, int esz) {
-  int w = 32;
-  while (w > 1 && 2 * (size_t)w * m * esz > (size_t)lds_bytes) w >>= 1;
-  return w;
+// Panel width of an n-column operand of m rows: the fewest panels (an even
+// count when more than one, so that no panel idles in a round) whose pair
+// (2 w columns of m elements of esz bytes) fits in lds_bytes, at most 32
+// columns each, and then the narrowest width giving that count.
+__host__ __device__ inline int panel_width(int m, int n, int lds_bytes, int esz) {
+  int wmax = (int)min((size_t)32, (size_t)lds_bytes / (2 * (size_t)m * esz));
+  if (wmax < 1) wmax = 1;
+  int np = (n + wmax - 1) / wmax;
+  if (np > 1 && (np & 1)) ++np;
+  return (n + np - 1) / np;
 }
 
 // Route of a computed block's SVD.  A block whose operand does not fit in LDS
@@ -268,7 +272,7 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
           if (big && 2LL * mj * ly.esz > panel_lds) atomicOr(st.err, ERR_WORKSPACE);
           if (big) {
             ++bgb;
-            const int w = panel_width(mj, min(lds_bytes, panel_lds), ly.esz);
+            const int w = panel_width(mj, n, min(lds_bytes, panel_lds), ly.esz);
             const int np = (n + w - 1) / w;
             maxpp = max(maxpp, np + (np & 1));
           }
@@ -365,7 +369,7 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
         svd_route(B.m, B.n, lds_bytes, qr_ok, ly.esz, qr, bg, mj);
         if (qr) re = (long long)B.n * B.n;
         if (bg) {
-          w = panel_width(mj, min(lds_bytes, panel_lds), ly.esz);
+          w = panel_width(mj, B.n, min(lds_bytes, panel_lds), ly.esz);
           npan = (B.n + w - 1) / w;
         }
       }
@@ -677,19 +681,49 @@ __device__ __forceinline__ float dpp_d(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false));
 }
 
+// v plus the value of the lane 16 (ROW16) or 32 lanes away, through the
+// gfx950 lane swaps (VALU ops, no LDS crossbar round trip).  Swapping v with
+// itself leaves in the first result, in every lane, the value of the lower
+// row (half) of its pair and in the second the value of the upper one, so the
+// sum is the same expression in both lanes of a pair.
+template <bool ROW16>
+__device__ __forceinline__ double swap_sum(double v) {
+  const unsigned lo = __double2loint(v), hi = __double2hiint(v);
+  if (ROW16) {
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+  } else {
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+  }
+}
+template <bool ROW16>
+__device__ __forceinline__ float swap_sum(float v) {
+  const unsigned x = __float_as_uint(v);
+  if (ROW16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+}
+
 // Sum over a group of L lanes: xor 1 and xor 2 inside each quad, the row
 // mirror (quad q with quad 3 - q), the half-row mirror (quad 0 with 1, 2
-// with 3), then xor 16 and xor 32 across rows.  Every step adds two values
-// in an order-independent way, so all lanes of the group end with bitwise
-// the same sum (the callers branch on it).
+// with 3), then across rows (16 lanes) and halves (32 lanes).  Every step
+// adds two values in an order-independent way, so all lanes of the group end
+// with bitwise the same sum (the callers branch on it).
 template <int L, typename R>
 __device__ __forceinline__ R group_sum(R v) {
   v += dpp_d<0xB1>(v);
   v += dpp_d<0x4E>(v);
   v += dpp_d<0x140>(v);
   v += dpp_d<0x141>(v);
-  if (L >= 32) v += __shfl_xor(v, 16, 64);
-  if (L >= 64) v += __shfl_xor(v, 32, 64);
+  if (L >= 32) v = swap_sum<true>(v);
+  if (L >= 64) v = swap_sum<false>(v);
   return v;
 }
 
@@ -949,10 +983,10 @@ __device__ __forceinline__ void jacobi_pair(T *xp, T *xq, double *nx, double *ny
   const double grd = group_sum<L>(gr), gid = group_sum<L>(gi);
   const double ga2 = grd * grd + gid * gid;
   if (!(ga2 > tol * tol * (al * be)) || !(ga2 > 1e-300)) return;
-  const double ga = sqrt(ga2), rga = 1.0 / ga;
+  const double rga = rsqrt(ga2), ga = ga2 * rga;
   const double zeta = (be - al) * (0.5 * rga);
   const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double cd_ = 1.0 / sqrt(1.0 + t * t);
+  const double cd_ = rsqrt(1.0 + t * t);
   const R c = (R)cd_, s = (R)(cd_ * t);
   const T e = T{(R)(grd * rga), (R)(-gid * rga)};    // e^{-i psi}
   double al2 = al - t * ga, be2 = be + t * ga;
