@@ -14,7 +14,9 @@
 
 namespace gbs {
 
-struct cd {
+// 16-byte aligned so that one lane moves a whole element with one 128-bit
+// access (two 64-bit halves at a 16-byte lane stride hit every LDS bank twice).
+struct __attribute__((aligned(16))) cd {
   double re, im;
 };
 
@@ -38,7 +40,7 @@ __host__ __device__ inline void cfma(cd &acc, cd a, cd b) {
 }
 
 // Single-precision complex (the mixed-precision Jacobi's LDS operand).
-struct cf {
+struct __attribute__((aligned(8))) cf {
   float re, im;
 };
 

@@ -756,7 +756,7 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly) {
   cd *A = ly.A + gb.e + B.eoff;
   cd *tau = ly.tau + gp.lst0 + B.svoff;
   int *piv = ly.piv + gp.lst0 + B.svoff;
-  extern __shared__ double s_dyn[];
+  extern __shared__ __attribute__((aligned(16))) double s_dyn[];
   cd *v = reinterpret_cast<cd *>(s_dyn);             // current reflector, m - k entries
   double *cn = reinterpret_cast<double *>(v + m);    // remaining column norms^2
   __shared__ double s_red[16];
@@ -1256,9 +1256,9 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly, int lo, int
     if (need <= lo || need > hi) return;
   }
   const int m = B.mj, n = B.n;
-  extern __shared__ double s_dyn[];
-  double *sig = s_dyn;                                   // n column norms^2
-  T *sA = reinterpret_cast<T *>(s_dyn + n);              // m x n operand
+  extern __shared__ __attribute__((aligned(16))) double s_dyn[];
+  T *sA = reinterpret_cast<T *>(s_dyn);                  // m x n operand
+  double *sig = reinterpret_cast<double *>(sA + (size_t)m * n);   // n column norms^2
   __shared__ int s_rot;
   __shared__ double s_red[16];
   cd *A = jacobi_operand(ly, gb, B);
@@ -1364,7 +1364,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
   const int i0 = hasI ? I * w : 0, wI = hasI ? min(w, n - I * w) : 0;
   const int j0 = hasJ ? J * w : 0, wJ = hasJ ? min(w, n - J * w) : 0;
   const int nc = wI + wJ;
-  extern __shared__ double s_dyn[];
+  extern __shared__ __attribute__((aligned(16))) double s_dyn[];
   T *sA = reinterpret_cast<T *>(s_dyn);
   cd *A = jacobi_operand(ly, ly.base[g], B);
   // the two panels are contiguous column ranges of the operand
@@ -1438,7 +1438,7 @@ __global__ __launch_bounds__(256) void k_big_finish(Layer ly, int sweeps_run) {
   BlkDesc *Bp = ly.blk + gp.blk0 + bi;
   const BlkDesc B = *Bp;
   cd *A = jacobi_operand(ly, ly.base[g], B);
-  extern __shared__ double s_sig[];
+  extern __shared__ __attribute__((aligned(16))) double s_sig[];
   if (!B.qr && charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym) self_mirror_phase(ly, gp, B, A);
   sort_values(st.err, A, B.mj, B.n, s_sig, ly.sv + gp.lst0 + B.svoff, ly.perm + gp.lst0 + B.svoff);
   if (threadIdx.x == 0) {
@@ -1693,7 +1693,7 @@ __global__ __launch_bounds__(256) void k_leftvec(Layer ly, int nchunk) {
   const int *mx = (!B.t ? ly.mirR : ly.mirL) + gp.mir0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int *piv = ly.piv + gp.lst0 + B.svoff;
-  extern __shared__ double s_dyn[];
+  extern __shared__ __attribute__((aligned(16))) double s_dyn[];
   cd *sV = reinterpret_cast<cd *>(s_dyn);    // LV_CHUNK right vectors, [c][x]
   __shared__ double s_red[16];
   // 1. right vectors (conjugated, original column order), one wavefront each
@@ -1865,7 +1865,7 @@ __global__ __launch_bounds__(256) void k_scatter(Layer ly) {
   const double *lamR = st.lam + (size_t)(j + 2) * chi;
   cd *G1 = st.gam + (size_t)j * chi * chi;
   cd *G2 = st.gam + (size_t)(j + 1) * chi * chi;
-  extern __shared__ double s_dyn[];
+  extern __shared__ __attribute__((aligned(16))) double s_dyn[];
   cd *sv_x = reinterpret_cast<cd *>(s_dyn);          // v[x], n entries
   __shared__ double s_red[16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
