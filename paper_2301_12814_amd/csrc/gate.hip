@@ -520,6 +520,15 @@ __global__ __launch_bounds__(256) void k_contract(Layer ly, int max_chi) {
   const int *cR = st.chg + (size_t)(j + 2) * chi;
   const int ca = cL[a];
   const int ca0 = charge_n(ca), ca1 = charge_np(ca);
+  // row a of Gamma_j scaled by lam_C, shared by every item of the row
+  extern __shared__ __attribute__((aligned(16))) double s_dyn[];
+  cd *sGa = reinterpret_cast<cd *>(s_dyn);
+  {
+    const cd *Ga = st.gam + (size_t)j * chi * chi + (size_t)a * chi;
+    const double *lC = st.lam + (size_t)(j + 1) * chi;
+    const int DC = st.dim[j + 1];
+    for (int al = threadIdx.x; al < DC; al += blockDim.x) sGa[al] = cscale(Ga[al], lC[al]);
+  }
   // runs of b: for each n0 in [ca0 - 2d + 2, ca0], the indices with n1 in
   // [ca1 - 2d + 2, ca1]; a run of n0 contributes len * |Q0| (b, q0) items
   __shared__ int s_b0[32], s_len[32], s_nq[32], s_item[33];
@@ -549,8 +558,6 @@ __global__ __launch_bounds__(256) void k_contract(Layer ly, int max_chi) {
   __syncthreads();
   const int nitem = s_item[nrun];
   const cd *tab = ly.fock + gp.fock0;
-  const cd *Ga = st.gam + (size_t)j * chi * chi + (size_t)a * chi;
-  const double *lC = st.lam + (size_t)(j + 1) * chi;
   const double la = st.lam[(size_t)j * chi + a];
   const int W1 = gt.c1hi + 2;
   const int *T = ly.ctab + gp.ct0;
@@ -588,9 +595,18 @@ __global__ __launch_bounds__(256) void k_contract(Layer ly, int max_chi) {
         if (p1 > gt.c1hi) break;
         const int al0 = Tp[p1], al1 = Tp[p1 + 1];
         if (al0 >= al1) continue;
+        // four Gamma_{j+1} loads in flight per step
         cd G = cmk(0.0, 0.0);
-        for (int al = al0; al < al1; ++al)
-          cfma(G, Ga[al], cscale(Gb[(size_t)al * chi], lC[al]));
+        int al = al0;
+        for (; al + 3 < al1; al += 4) {
+          const cd b0 = Gb[(size_t)al * chi], b1 = Gb[(size_t)(al + 1) * chi];
+          const cd b2 = Gb[(size_t)(al + 2) * chi], b3 = Gb[(size_t)(al + 3) * chi];
+          cfma(G, sGa[al], b0);
+          cfma(G, sGa[al + 1], b1);
+          cfma(G, sGa[al + 2], b2);
+          cfma(G, sGa[al + 3], b3);
+        }
+        for (; al < al1; ++al) cfma(G, sGa[al], Gb[(size_t)al * chi]);
         any = true;
         // H[q1] += conj(U[n1][ca1 - q1][ca1 - p1]) G
         const cd *Bcol = tab + (size_t)n1 * d * d + (ca1 - p1);
@@ -631,15 +647,19 @@ __global__ __launch_bounds__(256) void k_contract(Layer ly, int max_chi) {
   }
 }
 
+int svd_lds_bytes();
+
 hipError_t launch_contract(Layer ly, int max_chi, int max_d, hipStream_t s) {
   if (ly.total_blocks == 0) return hipSuccess;
+  svd_lds_bytes();   // dynamic LDS limits of the kernels (set once)
   const dim3 grid((unsigned)(ly.ngates * max_chi));
+  const size_t lds = sizeof(cd) * (size_t)max_chi;
   if (max_d <= 4)
-    hipLaunchKernelGGL(k_contract<4>, grid, dim3(256), 0, s, ly, max_chi);
+    hipLaunchKernelGGL(k_contract<4>, grid, dim3(256), lds, s, ly, max_chi);
   else if (max_d <= 8)
-    hipLaunchKernelGGL(k_contract<8>, grid, dim3(256), 0, s, ly, max_chi);
+    hipLaunchKernelGGL(k_contract<8>, grid, dim3(256), lds, s, ly, max_chi);
   else
-    hipLaunchKernelGGL(k_contract<16>, grid, dim3(256), 0, s, ly, max_chi);
+    hipLaunchKernelGGL(k_contract<16>, grid, dim3(256), lds, s, ly, max_chi);
   return hipGetLastError();
 }
 
@@ -970,14 +990,14 @@ __device__ __forceinline__ void jacobi_pair(T *xp, T *xq, double *nx, double *ny
       const int i = gl + L * k;
       rx[k] = i < m ? xp[i] : T{0, 0};
       ry[k] = i < m ? xq[i] : T{0, 0};
-      gr += rx[k].re * ry[k].re + rx[k].im * ry[k].im;
-      gi += rx[k].re * ry[k].im - rx[k].im * ry[k].re;
+      gr = fma(rx[k].re, ry[k].re, fma(rx[k].im, ry[k].im, gr));
+      gi = fma(rx[k].re, ry[k].im, fma(-rx[k].im, ry[k].re, gi));
     }
   } else {
     for (int i = gl; i < m; i += L) {
       const T x = xp[i], y = xq[i];
-      gr += x.re * y.re + x.im * y.im;
-      gi += x.re * y.im - x.im * y.re;
+      gr = fma(x.re, y.re, fma(x.im, y.im, gr));
+      gi = fma(x.re, y.im, fma(-x.im, y.re, gi));
     }
   }
   const double grd = group_sum<L>(gr), gid = group_sum<L>(gi);
@@ -987,35 +1007,47 @@ __device__ __forceinline__ void jacobi_pair(T *xp, T *xq, double *nx, double *ny
   const double zeta = (be - al) * (0.5 * rga);
   const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   const double cd_ = rsqrt(1.0 + t * t);
+  const double er = grd * rga, ei = -gid * rga;      // e^{-i psi}
+  // x' = c x - (s e) y,  y' = s x + (c e) y
   const R c = (R)cd_, s = (R)(cd_ * t);
-  const T e = T{(R)(grd * rga), (R)(-gid * rga)};    // e^{-i psi}
+  const R ser = (R)(cd_ * t * er), sei = (R)(cd_ * t * ei);
+  const R cer = (R)(cd_ * er), cei = (R)(cd_ * ei);
   double al2 = al - t * ga, be2 = be + t * ga;
+  // the tracked norms lose accuracy when a column loses more than half of
+  // its weight; then both are summed afresh from the rotated columns
   const bool exact = !(al2 >= 0.5 * al) || !(be2 >= 0.5 * be);
   R na = 0, nb = 0;
+  auto rotate = [&](const T x, const T y, T &x2, T &y2) {
+    x2.re = fma(-ser, y.re, fma(sei, y.im, c * x.re));
+    x2.im = fma(-ser, y.im, fma(-sei, y.re, c * x.im));
+    y2.re = fma(cer, y.re, fma(-cei, y.im, s * x.re));
+    y2.im = fma(cer, y.im, fma(cei, y.re, s * x.im));
+  };
   if (cached) {
 #pragma unroll
     for (int k = 0; k < CE; ++k) {
       const int i = gl + L * k;
       if (i < m) {
-        const T y = cmul(e, ry[k]);
-        const T x2 = csub(cscale(rx[k], c), cscale(y, s));
-        const T y2 = cadd(cscale(rx[k], s), cscale(y, c));
+        T x2, y2;
+        rotate(rx[k], ry[k], x2, y2);
         xp[i] = x2;
         xq[i] = y2;
-        na += cabs2(x2);
-        nb += cabs2(y2);
+        if (exact) {
+          na += cabs2(x2);
+          nb += cabs2(y2);
+        }
       }
     }
   } else {
     for (int i = gl; i < m; i += L) {
-      const T x = xp[i];
-      const T y = cmul(e, xq[i]);
-      const T x2 = csub(cscale(x, c), cscale(y, s));
-      const T y2 = cadd(cscale(x, s), cscale(y, c));
+      T x2, y2;
+      rotate(xp[i], xq[i], x2, y2);
       xp[i] = x2;
       xq[i] = y2;
-      na += cabs2(x2);
-      nb += cabs2(y2);
+      if (exact) {
+        na += cabs2(x2);
+        nb += cabs2(y2);
+      }
     }
   }
   if (exact) {               // uniform over the group
@@ -1466,6 +1498,9 @@ int svd_lds_bytes() {
     hipFuncSetAttribute((const void *)k_leftvec, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_scatter, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_big_finish, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    hipFuncSetAttribute((const void *)k_contract<4>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    hipFuncSetAttribute((const void *)k_contract<8>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    hipFuncSetAttribute((const void *)k_contract<16>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     return b;
   }();
   return bytes;
