@@ -490,22 +490,26 @@ __device__ inline int find_gate_big(const GateBase *base, int ng, int flat) {
 }
 
 // ----------------------------------------------------------------------------
-// Theta(q) blocks in two stages.  For a pair (a, b) of outer indices the
+// Theta(q) blocks in three steps.  For a pair (a, b) of outer indices the
 // centre charges p that connect them form the box P(a, b) = [max(c_b,
 // c_a - d + 1), min(c_b + d - 1, c_a)] (componentwise), and the new centre
 // charges q of the blocks holding (a, b) form the same box.  The weight
 // factorises into a ket and a bra part, W = K_q0[p0] conj(B_q1[p1]) with
 // K = U[n0][c_a0 - q0][c_a0 - p0], B = U[n1][c_a1 - q1][c_a1 - p1],
-// (n0, n1) = c_a - c_b.  So per (a, b, q0):
-//   G_p   = sum_{alpha of charge p} Gamma_j[a, alpha] lam_C[alpha] Gamma_{j+1}[alpha, b]
-//   H[q1] = sum_{p1} conj(B_q1[p1]) G_(p0, p1)            (for each p0)
-//   Theta(q0, q1)[a, b] = lam_L[a] lam_R[b] sum_{p0} K_q0[p0] H[q1]
-// each G_p is formed once instead of once per q1, and the Fock weights are
-// applied to charge sums instead of to every alpha term.  One workgroup per
-// (gate, row a); its threads run over the (b, q0) pairs of the row.
+// (n0, n1) = c_a - c_b.  So
+//   G_p        = sum_{alpha of charge p} Gamma_j[a, alpha] lam_C[alpha] Gamma_{j+1}[alpha, b]
+//   H_p0[q1]   = sum_{p1} conj(B_q1[p1]) G_(p0, p1)
+//   Theta(q0, q1)[a, b] = lam_L[a] lam_R[b] sum_{p0} K_q0[p0] H_p0[q1]
+// and every G_p and H_p0 is formed once per (a, b).  One workgroup per
+// (gate, row a).  The columns b with charge n0 = c_b0 form one run of the
+// right bond; a tile takes up to 256 / |box0| consecutive b of one run: its
+// threads first form H for every (b, p0) into LDS, then the sums over p0
+// for every (b, q0).
 // ----------------------------------------------------------------------------
+constexpr int CT_THREADS = 256;
+
 template <int DMAX>
-__global__ __launch_bounds__(256) void k_contract(Layer ly, int max_chi) {
+__global__ __launch_bounds__(CT_THREADS) void k_contract(Layer ly, int max_chi) {
   const int g = blockIdx.x / max_chi;
   const int a = blockIdx.x % max_chi;
   const GateParam gp = ly.gates[g];
@@ -520,129 +524,132 @@ __global__ __launch_bounds__(256) void k_contract(Layer ly, int max_chi) {
   const int *cR = st.chg + (size_t)(j + 2) * chi;
   const int ca = cL[a];
   const int ca0 = charge_n(ca), ca1 = charge_np(ca);
-  // row a of Gamma_j scaled by lam_C, shared by every item of the row
+  // row a of Gamma_j scaled by lam_C (shared by the whole row), then the
+  // H values of one tile
   extern __shared__ __attribute__((aligned(16))) double s_dyn[];
   cd *sGa = reinterpret_cast<cd *>(s_dyn);
+  cd *sH = sGa + max_chi;
   {
     const cd *Ga = st.gam + (size_t)j * chi * chi + (size_t)a * chi;
     const double *lC = st.lam + (size_t)(j + 1) * chi;
     const int DC = st.dim[j + 1];
     for (int al = threadIdx.x; al < DC; al += blockDim.x) sGa[al] = cscale(Ga[al], lC[al]);
   }
-  // runs of b: for each n0 in [ca0 - 2d + 2, ca0], the indices with n1 in
-  // [ca1 - 2d + 2, ca1]; a run of n0 contributes len * |Q0| (b, q0) items
-  __shared__ int s_b0[32], s_len[32], s_nq[32], s_item[33];
+  // runs of b: for each c_b0 in [ca0 - 2d + 2, ca0], the indices with c_b1
+  // in [ca1 - 2d + 2, ca1]
+  __shared__ int s_b0[32], s_len[32];
   const int nrun = 2 * d - 1;
   if (threadIdx.x < nrun) {
     const int n0 = ca0 - 2 * d + 2 + (int)threadIdx.x;
-    int b0 = 0, len = 0, nq = 0;
+    int b0 = 0, len = 0;
     if (n0 >= 0) {
       b0 = lower_bound(cR, DR, pack_charge(n0, max(ca1 - 2 * d + 2, 0)));
       len = lower_bound(cR, DR, pack_charge(n0, ca1 + 1)) - b0;
-      // q0 in [max(n0, ca0 - d + 1), min(n0 + d - 1, ca0)]
-      nq = min(n0 + d - 1, ca0) - max(n0, ca0 - d + 1) + 1;
     }
     s_b0[threadIdx.x] = b0;
     s_len[threadIdx.x] = len;
-    s_nq[threadIdx.x] = nq;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int r = 0; r < nrun; ++r) {
-      s_item[r] = acc;
-      acc += s_len[r] * s_nq[r];
-    }
-    s_item[nrun] = acc;
-  }
-  __syncthreads();
-  const int nitem = s_item[nrun];
   const cd *tab = ly.fock + gp.fock0;
   const double la = st.lam[(size_t)j * chi + a];
   const int W1 = gt.c1hi + 2;
   const int *T = ly.ctab + gp.ct0;
   const BlkDesc *blk = ly.blk + gp.blk0;
   const long long ebase = ly.base[g].e;
-  for (int it = threadIdx.x; it < nitem; it += blockDim.x) {
-    int r = 0;
-    while (s_item[r + 1] <= it) ++r;
-    // consecutive threads take consecutive b of one q0 (coalesced Gamma_{j+1} reads)
-    const int off = it - s_item[r];
+  const cd *G1 = st.gam + (size_t)(j + 1) * chi * chi;
+  for (int r = 0; r < nrun; ++r) {
     const int len = s_len[r];
-    const int b = s_b0[r] + off % len;
-    const int n0b = ca0 - 2 * d + 2 + r;                      // c_b0
-    const int q0 = max(n0b, ca0 - d + 1) + off / len;
-    const int cb = cR[b];
-    const int cb1 = charge_np(cb);
-    const int n0 = ca0 - n0b, n1 = ca1 - cb1;
-    if (n1 < 0 || n1 > 2 * d - 2) continue;
-    const int i0 = ca0 - q0;
-    // p0 range (also the q0 box), p1 / q1 range
-    const int p0lo = max(max(n0b, ca0 - d + 1), gt.c0lo), p0hi = min(min(n0b + d - 1, ca0), gt.c0hi);
-    const int q1lo = max(cb1, ca1 - d + 1), q1hi = min(cb1 + d - 1, ca1);
-    const int nq1 = q1hi - q1lo + 1;
-    const cd *Gb = st.gam + (size_t)(j + 1) * chi * chi + b;
-    cd acc[DMAX];
+    if (len == 0) continue;
+    const int n0b = ca0 - 2 * d + 2 + r;                       // c_b0 of the run
+    const int base0 = max(n0b, ca0 - d + 1);                   // box0 = [base0, base0 + nq)
+    const int nq = min(n0b + d - 1, ca0) - base0 + 1;
+    const int n0 = ca0 - n0b;
+    const int tb = CT_THREADS / nq;
+    for (int bt = 0; bt < len; bt += tb) {
+      const int nb = min(tb, len - bt);
+      const int lt = threadIdx.x;
+      const bool act = lt < nq * nb;
+      const int k = act ? lt / nb : 0, bi = act ? lt % nb : 0;
+      const int b = s_b0[r] + bt + bi;
+      const int cb1 = act ? charge_np(cR[b]) : 0;
+      const int n1 = ca1 - cb1;
+      const int q1lo = max(cb1, ca1 - d + 1), q1hi = min(cb1 + d - 1, ca1);
+      const int nq1 = q1hi - q1lo + 1;
+      if (act) {
+        // step 1 and 2 for (b, p0 = base0 + k)
+        const int p0 = base0 + k;
+        cd H[DMAX];
 #pragma unroll
-    for (int u = 0; u < DMAX; ++u) acc[u] = cmk(0.0, 0.0);
-    for (int p0 = p0lo; p0 <= p0hi; ++p0) {
-      const int *Tp = T + (size_t)(p0 - gt.c0lo) * W1;
-      cd H[DMAX];
+        for (int u = 0; u < DMAX; ++u) H[u] = cmk(0.0, 0.0);
+        if (p0 >= gt.c0lo && p0 <= gt.c0hi) {
+          const int *Tp = T + (size_t)(p0 - gt.c0lo) * W1;
+          const cd *Gb = G1 + b;
+          for (int p1 = q1lo; p1 <= q1hi && p1 <= gt.c1hi; ++p1) {
+            const int al0 = Tp[p1], al1 = Tp[p1 + 1];
+            if (al0 >= al1) continue;
+            // four Gamma_{j+1} loads in flight per step
+            cd G = cmk(0.0, 0.0);
+            int al = al0;
+            for (; al + 3 < al1; al += 4) {
+              const cd b0 = Gb[(size_t)al * chi], b1 = Gb[(size_t)(al + 1) * chi];
+              const cd b2 = Gb[(size_t)(al + 2) * chi], b3 = Gb[(size_t)(al + 3) * chi];
+              cfma(G, sGa[al], b0);
+              cfma(G, sGa[al + 1], b1);
+              cfma(G, sGa[al + 2], b2);
+              cfma(G, sGa[al + 3], b3);
+            }
+            for (; al < al1; ++al) cfma(G, sGa[al], Gb[(size_t)al * chi]);
+            // H[q1] += conj(U[n1][ca1 - q1][ca1 - p1]) G
+            const cd *Bcol = tab + (size_t)n1 * d * d + (ca1 - p1);
 #pragma unroll
-      for (int u = 0; u < DMAX; ++u) H[u] = cmk(0.0, 0.0);
-      bool any = false;
-      for (int p1 = q1lo; p1 <= q1hi; ++p1) {
-        if (p1 > gt.c1hi) break;
-        const int al0 = Tp[p1], al1 = Tp[p1 + 1];
-        if (al0 >= al1) continue;
-        // four Gamma_{j+1} loads in flight per step
-        cd G = cmk(0.0, 0.0);
-        int al = al0;
-        for (; al + 3 < al1; al += 4) {
-          const cd b0 = Gb[(size_t)al * chi], b1 = Gb[(size_t)(al + 1) * chi];
-          const cd b2 = Gb[(size_t)(al + 2) * chi], b3 = Gb[(size_t)(al + 3) * chi];
-          cfma(G, sGa[al], b0);
-          cfma(G, sGa[al + 1], b1);
-          cfma(G, sGa[al + 2], b2);
-          cfma(G, sGa[al + 3], b3);
+            for (int u = 0; u < DMAX; ++u)
+              if (u < nq1) cfma(H[u], cconj(Bcol[(size_t)(ca1 - q1lo - u) * d]), G);
+          }
         }
-        for (; al < al1; ++al) cfma(G, sGa[al], Gb[(size_t)al * chi]);
-        any = true;
-        // H[q1] += conj(U[n1][ca1 - q1][ca1 - p1]) G
-        const cd *Bcol = tab + (size_t)n1 * d * d + (ca1 - p1);
 #pragma unroll
         for (int u = 0; u < DMAX; ++u)
-          if (u < nq1) cfma(H[u], cconj(Bcol[(size_t)(ca1 - q1lo - u) * d]), G);
+          if (u < nq1) sH[(size_t)lt * DMAX + u] = H[u];
       }
-      if (!any) continue;
-      const cd K = tab[((size_t)n0 * d + i0) * d + (ca0 - p0)];
+      __syncthreads();
+      if (act) {
+        // step 3 for (b, q0 = base0 + k)
+        const int q0 = base0 + k, i0 = ca0 - q0;
+        cd acc[DMAX];
 #pragma unroll
-      for (int u = 0; u < DMAX; ++u)
-        if (u < nq1) cfma(acc[u], K, H[u]);
-    }
-    // write Theta(q0, q1)[a, b] into every computed block (q0, q1)
-    const double sc = la * st.lam[(size_t)(j + 2) * chi + b];
+        for (int u = 0; u < DMAX; ++u) acc[u] = cmk(0.0, 0.0);
+        for (int kp = 0; kp < nq; ++kp) {
+          const cd K = tab[((size_t)n0 * d + i0) * d + (ca0 - base0 - kp)];
+          const cd *Hr = sH + (size_t)(kp * nb + bi) * DMAX;
 #pragma unroll
-    for (int u = 0; u < DMAX; ++u) {
-      if (u >= nq1) continue;
-      const int q = pack_charge(q0, q1lo + u);
-      int lo = 0, hi = gt.nblk;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (blk[mid].q < q) lo = mid + 1; else hi = mid;
+          for (int u = 0; u < DMAX; ++u)
+            if (u < nq1) cfma(acc[u], K, Hr[u]);
+        }
+        // write Theta(q0, q1)[a, b] into every computed block (q0, q1)
+        const double sc = la * st.lam[(size_t)(j + 2) * chi + b];
+#pragma unroll
+        for (int u = 0; u < DMAX; ++u) {
+          if (u >= nq1) continue;
+          const int q = pack_charge(q0, q1lo + u);
+          int lo = 0, hi = gt.nblk;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (blk[mid].q < q) lo = mid + 1; else hi = mid;
+          }
+          if (lo >= gt.nblk || blk[lo].q != q) continue;
+          const BlkDesc &B = blk[lo];
+          if (!B.comp) continue;
+          const int *run = ly.runs + (size_t)(gp.blk0 + lo) * RUNS_PER_BLOCK;
+          const int ka = ca0 - q0, kb = q0 - n0b;
+          const int ia = run[ka] + (a - run[16 + ka]);
+          const int ib = run[32 + kb] + (b - run[48 + kb]);
+          const size_t at = !B.t ? (size_t)ib * B.m + ia       // Theta, m = r rows
+                                 : (size_t)ia * B.m + ib;      // Theta^T, m = s rows
+          const cd v = cscale(acc[u], sc);
+          ly.A[ebase + B.eoff + at] = v;
+          ly.A0[ebase + B.eoff + at] = v;
+        }
       }
-      if (lo >= gt.nblk || blk[lo].q != q) continue;
-      const BlkDesc &B = blk[lo];
-      if (!B.comp) continue;
-      const int *run = ly.runs + (size_t)(gp.blk0 + lo) * RUNS_PER_BLOCK;
-      const int ka = ca0 - q0, kb = q0 - n0b;
-      const int ia = run[ka] + (a - run[16 + ka]);
-      const int ib = run[32 + kb] + (b - run[48 + kb]);
-      const size_t at = !B.t ? (size_t)ib * B.m + ia       // Theta, m = r rows
-                             : (size_t)ia * B.m + ib;      // Theta^T, m = s rows
-      const cd v = cscale(acc[u], sc);
-      ly.A[ebase + B.eoff + at] = v;
-      ly.A0[ebase + B.eoff + at] = v;
+      __syncthreads();
     }
   }
 }
@@ -653,13 +660,14 @@ hipError_t launch_contract(Layer ly, int max_chi, int max_d, hipStream_t s) {
   if (ly.total_blocks == 0) return hipSuccess;
   svd_lds_bytes();   // dynamic LDS limits of the kernels (set once)
   const dim3 grid((unsigned)(ly.ngates * max_chi));
-  const size_t lds = sizeof(cd) * (size_t)max_chi;
+  // scaled Gamma row (max_chi) and one tile of H values (CT_THREADS x DMAX)
+  const size_t row = sizeof(cd) * (size_t)max_chi, tile = sizeof(cd) * CT_THREADS;
   if (max_d <= 4)
-    hipLaunchKernelGGL(k_contract<4>, grid, dim3(256), lds, s, ly, max_chi);
+    hipLaunchKernelGGL(k_contract<4>, grid, dim3(CT_THREADS), row + 4 * tile, s, ly, max_chi);
   else if (max_d <= 8)
-    hipLaunchKernelGGL(k_contract<8>, grid, dim3(256), lds, s, ly, max_chi);
+    hipLaunchKernelGGL(k_contract<8>, grid, dim3(CT_THREADS), row + 8 * tile, s, ly, max_chi);
   else
-    hipLaunchKernelGGL(k_contract<16>, grid, dim3(256), lds, s, ly, max_chi);
+    hipLaunchKernelGGL(k_contract<16>, grid, dim3(CT_THREADS), row + 16 * tile, s, ly, max_chi);
   return hipGetLastError();
 }
 
