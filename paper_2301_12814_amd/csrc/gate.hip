@@ -773,6 +773,75 @@ constexpr int QC = 16;   // column elements per lane kept in registers (m - k <=
 
 __device__ __forceinline__ double block_sum(double v, double *s_red);
 
+// Trailing update of QR step k for the columns j > k: a_j -= conj(tau) v (v^H a_j)
+// on rows k.., and the squared norm of a_j below row k.  Each wave takes CPW
+// columns at a time (their loads in flight together), QCL elements per lane
+// of each held in registers between the dot product and the update
+// (len <= 64 QCL).
+template <int QCL, int CPW>
+__device__ __forceinline__ void qr_update(cd *A, int m, int n, int k, int len, const cd *v, cd ct,
+                                          bool skip, double *cn, int wave, int nw, int lane) {
+  for (int j0 = k + 1 + wave * CPW; j0 < n; j0 += nw * CPW) {
+    cd ra[CPW][QCL];
+    double wr[CPW], wi[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const cd *a = A + (size_t)(j0 + c) * m + k;
+      const bool has = j0 + c < n;
+#pragma unroll
+      for (int u = 0; u < QCL; ++u) {
+        const int y = lane + 64 * u;
+        ra[c][u] = (has && y < len) ? a[y] : cmk(0.0, 0.0);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      wr[c] = 0.0;
+      wi[c] = 0.0;
+      if (!skip) {
+#pragma unroll
+        for (int u = 0; u < QCL; ++u) {
+          const int y = lane + 64 * u;
+          if (y < len) {
+            const cd q = cmulc(v[y], ra[c][u]);
+            wr[c] += q.re;
+            wi[c] += q.im;
+          }
+        }
+      }
+    }
+    if (!skip) {
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        wr[c] = group_sum<64>(wr[c]);
+        wi[c] = group_sum<64>(wi[c]);
+      }
+    }
+    double nb[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int j = j0 + c;
+      cd *a = A + (size_t)j * m + k;
+      const cd f = cmul(ct, cmk(wr[c], wi[c]));    // conj(tau) v^H a
+      nb[c] = 0.0;
+#pragma unroll
+      for (int u = 0; u < QCL; ++u) {
+        const int y = lane + 64 * u;
+        if (j < n && y < len) {
+          const cd an = skip ? ra[c][u] : csub(ra[c][u], cmul(f, v[y]));
+          if (!skip) a[y] = an;
+          if (y >= 1) nb[c] += cabs2(an);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const double t = group_sum<64>(nb[c]);
+      if (lane == 0 && j0 + c < n) cn[j0 + c] = t;
+    }
+  }
+}
+
 __global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly) {
   const int flat = blockIdx.x;
   const int g = find_gate_blk(ly.base, ly.ngates, flat);
@@ -872,7 +941,11 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly) {
     }
     __syncthreads();
     const cd ct = skip ? cmk(0.0, 0.0) : cconj(s_tau);
-    if (len <= 64 * QC) {
+    if (len <= 64 * 4)
+      qr_update<4, 4>(A, m, n, k, len, v, ct, skip, cn, wave, nw, lane);
+    else if (len <= 64 * 8)
+      qr_update<8, 2>(A, m, n, k, len, v, ct, skip, cn, wave, nw, lane);
+    else if (len <= 64 * QC) {
       // column segment held in registers between the dot product and the update
       for (int j = k + 1 + wave; j < n; j += nw) {
         cd *a = A + (size_t)j * m + k;
