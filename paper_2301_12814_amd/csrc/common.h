@@ -93,10 +93,66 @@ enum : int {
   ERR_WORKSPACE = 16,
 };
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, GBS_WAVE);
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(h2, l2);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_d(float v) {
+  const int x = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false));
+}
+
+// v plus the value of the lane 16 (ROW16) or 32 lanes away, through the
+// gfx950 lane swaps (VALU ops, no LDS crossbar round trip).  Swapping v with
+// itself leaves in the first result, in every lane, the value of the lower
+// row (half) of its pair and in the second the value of the upper one, so the
+// sum is the same expression in both lanes of a pair.
+template <bool ROW16>
+__device__ __forceinline__ double swap_sum(double v) {
+  const unsigned lo = __double2loint(v), hi = __double2hiint(v);
+  if (ROW16) {
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+  } else {
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+  }
+}
+template <bool ROW16>
+__device__ __forceinline__ float swap_sum(float v) {
+  const unsigned x = __float_as_uint(v);
+  if (ROW16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+}
+
+// Sum over a group of L lanes: xor 1 and xor 2 inside each quad, the row
+// mirror (quad q with quad 3 - q), the half-row mirror (quad 0 with 1, 2
+// with 3), then across rows (16 lanes) and halves (32 lanes).  Every step
+// adds two values in an order-independent way, so all lanes of the group end
+// with bitwise the same sum (the callers branch on it).
+template <int L, typename R>
+__device__ __forceinline__ R group_sum(R v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x140>(v);
+  v += dpp_d<0x141>(v);
+  if (L >= 32) v = swap_sum<true>(v);
+  if (L >= 64) v = swap_sum<false>(v);
   return v;
 }
+
+// Sum over the 64 lanes of a wave (every lane active), the same in every lane.
+__device__ inline double wave_sum(double v) { return group_sum<64>(v); }
 
 }  // namespace gbs

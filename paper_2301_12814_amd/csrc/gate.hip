@@ -696,64 +696,6 @@ hipError_t launch_ctab(Layer ly, hipStream_t s) {
 }
 
 
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
-  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
-  return __hiloint2double(h2, l2);
-}
-template <int CTRL>
-__device__ __forceinline__ float dpp_d(float v) {
-  const int x = __float_as_int(v);
-  return __int_as_float(__builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false));
-}
-
-// v plus the value of the lane 16 (ROW16) or 32 lanes away, through the
-// gfx950 lane swaps (VALU ops, no LDS crossbar round trip).  Swapping v with
-// itself leaves in the first result, in every lane, the value of the lower
-// row (half) of its pair and in the second the value of the upper one, so the
-// sum is the same expression in both lanes of a pair.
-template <bool ROW16>
-__device__ __forceinline__ double swap_sum(double v) {
-  const unsigned lo = __double2loint(v), hi = __double2hiint(v);
-  if (ROW16) {
-    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-    return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
-  } else {
-    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-    return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
-  }
-}
-template <bool ROW16>
-__device__ __forceinline__ float swap_sum(float v) {
-  const unsigned x = __float_as_uint(v);
-  if (ROW16) {
-    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  } else {
-    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
-    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  }
-}
-
-// Sum over a group of L lanes: xor 1 and xor 2 inside each quad, the row
-// mirror (quad q with quad 3 - q), the half-row mirror (quad 0 with 1, 2
-// with 3), then across rows (16 lanes) and halves (32 lanes).  Every step
-// adds two values in an order-independent way, so all lanes of the group end
-// with bitwise the same sum (the callers branch on it).
-template <int L, typename R>
-__device__ __forceinline__ R group_sum(R v) {
-  v += dpp_d<0xB1>(v);
-  v += dpp_d<0x4E>(v);
-  v += dpp_d<0x140>(v);
-  v += dpp_d<0x141>(v);
-  if (L >= 32) v = swap_sum<true>(v);
-  if (L >= 64) v = swap_sum<false>(v);
-  return v;
-}
 
 // ----------------------------------------------------------------------------
 // Householder QR with column pivoting of the large blocks: A P = Q R with
@@ -772,6 +714,56 @@ constexpr int QR_THREADS = 1024;
 constexpr int QC = 16;   // column elements per lane kept in registers (m - k <= 1024)
 
 __device__ __forceinline__ double block_sum(double v, double *s_red);
+
+// Largest value over the 64 lanes of a wave with, among equal values, the
+// lowest index; the same pair in every lane.  Each step merges a lane with
+// its partner under one total order, so both end with the same pair.
+__device__ __forceinline__ void amax_merge(double &bv, int &bi, double ov, int oi) {
+  if (ov > bv || (ov == bv && oi < bi)) {
+    bv = ov;
+    bi = oi;
+  }
+}
+template <int CTRL>
+__device__ __forceinline__ void amax_dpp(double &bv, int &bi) {
+  const double ov = dpp_d<CTRL>(bv);
+  const int oi = __builtin_amdgcn_update_dpp(bi, bi, CTRL, 0xF, 0xF, false);
+  amax_merge(bv, bi, ov, oi);
+}
+template <bool ROW16>
+__device__ __forceinline__ void amax_swap(double &bv, int &bi) {
+  const unsigned lo = __double2loint(bv), hi = __double2hiint(bv), ix = (unsigned)bi;
+  double v0, v1;
+  int i0, i1;
+  if (ROW16) {
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const auto x = __builtin_amdgcn_permlane16_swap(ix, ix, false, false);
+    v0 = __hiloint2double(h[0], l[0]);
+    v1 = __hiloint2double(h[1], l[1]);
+    i0 = (int)x[0];
+    i1 = (int)x[1];
+  } else {
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    const auto x = __builtin_amdgcn_permlane32_swap(ix, ix, false, false);
+    v0 = __hiloint2double(h[0], l[0]);
+    v1 = __hiloint2double(h[1], l[1]);
+    i0 = (int)x[0];
+    i1 = (int)x[1];
+  }
+  bv = v0;
+  bi = i0;
+  amax_merge(bv, bi, v1, i1);
+}
+__device__ __forceinline__ void wave_argmax(double &bv, int &bi) {
+  amax_dpp<0xB1>(bv, bi);
+  amax_dpp<0x4E>(bv, bi);
+  amax_dpp<0x140>(bv, bi);
+  amax_dpp<0x141>(bv, bi);
+  amax_swap<true>(bv, bi);
+  amax_swap<false>(bv, bi);
+}
 
 // Trailing update of QR step k for the columns j > k: a_j -= conj(tau) v (v^H a_j)
 // on rows k.., and the squared norm of a_j below row k.  Each wave takes CPW
@@ -876,12 +868,7 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly) {
     int bi = n;
     for (int c = k + threadIdx.x; c < n; c += blockDim.x)
       if (cn[c] > bv) { bv = cn[c]; bi = c; }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(bv, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-    }
+    wave_argmax(bv, bi);
     if (lane == 0) { s_bv[wave] = bv; s_bi[wave] = bi; }
     __syncthreads();
     if (threadIdx.x == 0) {
