@@ -279,8 +279,12 @@ class DenseMPO:
             self.G[j] = self.G[j][keep[j]][:, :, :, keep[j + 1]]
 
     # ---------------- gates ----------------
-    def apply_gate(self, m: int, theta: float, phi: float, chi: int):
-        """Beam splitter T(theta, phi) on modes (m, m+1): App. D two-site update."""
+    def theta_matrix(self, m: int, theta: float, phi: float) -> np.ndarray:
+        """Two-site tensor after the beam splitter T(theta, phi) on modes
+        (m, m+1) (App. D, Eq. Theta; the vectorised unitary U (x) conj(U) of
+        Sec. II on the (ket, bra) pairs of both modes), as the matrix
+        X[(a, I, K), (J, L, b)] with I, K the ket / bra occupations of mode m
+        and J, L those of mode m+1."""
         d = self.d
         j = m
         A, B = self.G[j], self.G[j + 1]
@@ -290,7 +294,15 @@ class DenseMPO:
         # vectorised unitary U (x) conj(U) on (ket, bra) of both modes
         Theta = np.einsum('IJij,KLkl,aikjlb->aIKJLb', Uf, Uf.conj(), Theta, optimize=True)
         Dl, Dr = len(lL), len(lR)
-        X = Theta.reshape(Dl * d * d, d * d * Dr)
+        return Theta.reshape(Dl * d * d, d * d * Dr)
+
+    def apply_gate(self, m: int, theta: float, phi: float, chi: int):
+        """Beam splitter T(theta, phi) on modes (m, m+1): App. D two-site update."""
+        d = self.d
+        j = m
+        lL, lR = self.lam[j], self.lam[j + 2]
+        Dl, Dr = len(lL), len(lR)
+        X = self.theta_matrix(m, theta, phi)
         V, S, Wh = np.linalg.svd(X, full_matrices=False)
         keep = S >= RANK_CUT * S[0] if len(S) and S[0] > 0 else np.zeros(len(S), bool)
         V, S, Wh = V[:, keep], S[keep], Wh[keep]
@@ -416,3 +428,57 @@ def product_bonds(rhos, chi: int):
         keep = select(ch, lam, chi)
         out.append((ch[keep], lam[keep]))
     return out
+
+
+# --------------------------------------------------------------------------
+# one charge sector of the two-site tensor, in the charge-blocked form
+# --------------------------------------------------------------------------
+def sector_theta(Gj, Gj1, lamL, lamC, lamR, cL, cC, cR, theta: float, phi: float, d: int, q):
+    """Charge sector q of the two-site tensor after a beam splitter, from the
+    charge-blocked Vidal form (App. D, Eq. Theta restricted to one new centre
+    charge; beam splitter as in Sec. II).
+
+    In the blocked form a site is a bond-by-bond matrix, Gj[a, alpha], whose
+    local (ket, bra) occupations are fixed by the charges: m = c_a - c_alpha.
+    With p = c_alpha and n = c_a - c_b,
+        Theta(q)[a, b] = lamL[a] lamR[b] sum_alpha Gj[a, alpha] lamC[alpha] Gj1[alpha, b]
+                         U[c_a0 - q0, q0 - c_b0, c_a0 - p0, p0 - c_b0]
+                         conj(U[c_a1 - q1, q1 - c_b1, c_a1 - p1, p1 - c_b1])
+    where U[I, J, i, j] is the two-mode Fock matrix (outputs I, J, inputs
+    i, j) and every occupation lies in [0, d).  Rows are the left-bond
+    indices a with c_a - q in [0, d)^2, columns the right-bond indices b
+    with q - c_b in [0, d)^2.  Returns (rows, cols, Theta(q)).
+
+    Slow and direct: one matrix product per centre charge p (no blocking
+    beyond the charge grouping the definition implies).
+    """
+    Uf = fock.fock_bs(fock.bs_matrix(theta, phi), d)
+    cL, cC, cR = np.asarray(cL), np.asarray(cC), np.asarray(cR)
+    q = np.asarray(q)
+
+    def inside(x):
+        return np.all((x >= 0) & (x < d), axis=-1)
+
+    rows = np.nonzero(inside(cL - q))[0]
+    cols = np.nonzero(inside(q - cR))[0]
+    Th = np.zeros((len(rows), len(cols)), dtype=complex)
+    if len(rows) == 0 or len(cols) == 0:
+        return rows, cols, Th
+    ca = cL[rows][:, None, :]          # (r, 1, 2)
+    cb = cR[cols][None, :, :]          # (1, s, 2)
+    for p in np.unique(cC, axis=0):
+        al = np.nonzero(np.all(cC == p, axis=1))[0]
+        i_in = ca - p                   # occupation of mode m before the gate
+        j_in = p - cb                   # occupation of mode m+1 before the gate
+        ok = inside(i_in) & inside(j_in)
+        if not ok.any():
+            continue
+        Gp = (Gj[np.ix_(rows, al)] * lamC[al][None, :]) @ Gj1[np.ix_(al, cols)]
+        I_out = np.broadcast_to(ca - q, ok.shape + (2,))
+        J_out = np.broadcast_to(q - cb, ok.shape + (2,))
+        ii = np.where(ok[..., None], i_in, 0)
+        jj = np.where(ok[..., None], j_in, 0)
+        ket = Uf[I_out[..., 0], J_out[..., 0], ii[..., 0], jj[..., 0]]
+        bra = Uf[I_out[..., 1], J_out[..., 1], ii[..., 1], jj[..., 1]]
+        Th += np.where(ok, ket * np.conj(bra) * Gp, 0.0)
+    return rows, cols, Th * lamL[rows][:, None] * lamR[cols][None, :]

@@ -118,6 +118,32 @@ def test_gpu_untruncated_matches_brute_force(M, d, r, eta, seed):
     assert np.abs(P - bP).max() < 1e-12
 
 
+@pytest.mark.parametrize("M,d,chi,r,eta,seed", [(5, 10, 8, 0.9, 0.5, 21),
+                                                 (4, 12, 6, 1.0, 0.6, 22),
+                                                 (4, 16, 4, 1.1, 0.7, 23)])
+def test_gpu_high_cutoff_matches_oracle(M, d, chi, r, eta, seed):
+    """Fock cutoffs above 8 (the contraction's wide-register variant), whole
+    runs at small chi, every bond after every layer against the oracle."""
+    U = inputs.haar_unitary(M, seed)
+    layers, phase = gbsmpo.clements(U)
+    og, oph = oclem.decompose(U)
+    olayers = oclem.layers(M, og)
+    o = omp.DenseMPO.product([states.lossy_squeezed_rho(r, eta, d)] * M, chi)
+    with gbsmpo.MPO(M, [r] * M, eta, d, chi) as g:
+        for li, (S, T, P) in enumerate(layers):
+            say("high cutoff", d, "layer", li)
+            g.apply_layer(S, T, P)
+            for (k, th, ph) in olayers[li]:
+                o.apply_gate(k, th, ph, chi)
+            compare_state(g, o, f"d={d} layer {li}")
+        g.apply_phases(phase)
+        o.apply_phases(oph)
+        P, tr = g.marginals()
+        oP, otr, _ = o.marginals()
+        assert abs(tr - otr) < 1e-10 * abs(otr)
+        assert np.abs(P - oP).max() < 1e-10
+
+
 @pytest.mark.parametrize("lds", [0, 2500])
 def test_gpu_medium_shape_reduced_chi_matches_oracle(svd_route, lds):
     """Medium shape (M=32, d=8, r=0.8, sqrt-scaling eta) at chi=16 so that the
@@ -199,6 +225,46 @@ def test_gpu_large_first_layers_invariants():
         assert tr <= tr0 * (1 + 1e-12)
         S, smax = g.entropy()
         assert np.all(np.isfinite(S)) and smax > 0
+
+
+def test_gpu_large_sampled_sectors_match_oracle():
+    """Large workload (M=64, d=8, chi=1024) at full size, in the configuration
+    the benchmark times: after seven layers, the middle gate of the eighth.
+    For its six largest charge sectors, the values the library keeps on the
+    new bond equal the leading singular values of the oracle's sector
+    Theta(q) (App. D), formed from the library's own state before the layer
+    (sampled parity of contraction + block SVD at full size)."""
+    w = inputs.workload("large")
+    U = inputs.haar_unitary(w.M, w.seed)
+    layers, _ = gbsmpo.clements(U)
+    with gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi) as g:
+        for li in range(7):
+            g.apply_layer(*layers[li])
+        S, T, P = layers[7]
+        k = len(S) // 2
+        j, th, ph = int(S[k]), float(T[k]), float(P[k])
+        (lL, cL), (lC, cC), (lR, cR) = g.bond(j), g.bond(j + 1), g.bond(j + 2)
+        Gj, Gj1 = g.site(j), g.site(j + 1)
+        say("large sampled sectors, gate at", j, "bond sizes", len(lL), len(lC), len(lR))
+        g.apply_layer(S, T, P)
+        nlam, nch = g.bond(j + 1)
+    assert len(nlam) == w.chi
+    qs, counts = np.unique(nch, axis=0, return_counts=True)
+    sizes = []
+    for q in qs:
+        r = np.all((cL - q >= 0) & (cL - q < w.d), axis=1).sum()
+        c = np.all((q - cR >= 0) & (q - cR < w.d), axis=1).sum()
+        sizes.append(r * c)
+    order = np.argsort(sizes)[::-1][:6]
+    for i in order:
+        q = qs[i]
+        rows, cols, Th = omp.sector_theta(Gj, Gj1, lL, lC, lR, cL, cC, cR, th, ph, w.d, q)
+        sv = np.linalg.svd(Th, compute_uv=False)
+        got = nlam[np.all(nch == q, axis=1)]
+        say("sector", q.tolist(), Th.shape, "kept", len(got))
+        assert 0 < len(got) <= len(sv)
+        err = np.abs(got - sv[: len(got)])
+        assert np.all(err <= 1e-10 * sv[: len(got)] + 1e-12 * sv[0]), (q, float(err.max()))
 
 
 def test_gpu_edge_cases():

@@ -290,3 +290,55 @@ def test_special_cases():
     assert np.allclose(m.entropies(), 0)
     P, tr, _ = m.marginals()
     assert abs(tr - 1) < 1e-15 and np.allclose(P[:, 0], 1) and np.allclose(P[:, 1:], 0)
+
+
+# ------------------------------------------------------- charge-sector Theta
+def _blocked_sites(o, j):
+    """Charge-blocked site matrix Gj[a, alpha] of the dense site tensor
+    G[a, m, m', alpha]: the entry at the occupations the charges fix."""
+    G = o.G[j]
+    cL, cR = o.charge[j], o.charge[j + 1]
+    d = o.d
+    out = np.zeros((G.shape[0], G.shape[3]), dtype=complex)
+    for a in range(G.shape[0]):
+        for al in range(G.shape[3]):
+            m0, m1 = cL[a] - cR[al]
+            if 0 <= m0 < d and 0 <= m1 < d:
+                out[a, al] = G[a, m0, m1, al]
+    return out
+
+
+@pytest.mark.parametrize("M,d,chi,seed", [(5, 4, 24, 3), (4, 5, 40, 4)])
+def test_sector_theta_matches_dense_theta(M, d, chi, seed):
+    """Every charge sector of the blocked two-site tensor equals the rows
+    (a, c_a - q) and columns (q - c_b, b) of the dense tensor after the gate,
+    on a state that earlier gates have entangled."""
+    rng = np.random.default_rng(seed)
+    o = mpo.DenseMPO.product(_rhos(M, d, [0.8, 0.5, 0.9, 0.6, 0.7][:M], 0.6), chi)
+    for k in (0, 2, 1):
+        if k + 1 < M:
+            o.apply_gate(k, float(rng.uniform(0, 1.5)), float(rng.uniform(-3, 3)), chi)
+    j = 1
+    th, ph = 0.83, -1.2
+    X = o.theta_matrix(j, th, ph)
+    cL, cC, cR = o.charge[j], o.charge[j + 1], o.charge[j + 2]
+    Gj, Gj1 = _blocked_sites(o, j), _blocked_sites(o, j + 1)
+    Dr = len(cR)
+    qs = {tuple(int(x) for x in cL[a] - np.array([i, k]))
+          for a in range(len(cL)) for i in range(d) for k in range(d)}
+    scale = np.abs(X).max()
+    seen = 0
+    covered = np.zeros(X.shape, dtype=bool)
+    for q in sorted(qs):
+        rows, cols, Th = mpo.sector_theta(Gj, Gj1, o.lam[j], o.lam[j + 1], o.lam[j + 2],
+                                          cL, cC, cR, th, ph, d, q)
+        if len(rows) == 0 or len(cols) == 0:
+            continue
+        ri = [(a * d + (cL[a][0] - q[0])) * d + (cL[a][1] - q[1]) for a in rows]
+        ci = [((q[0] - cR[b][0]) * d + (q[1] - cR[b][1])) * Dr + b for b in cols]
+        assert np.abs(X[np.ix_(ri, ci)] - Th).max() <= 1e-12 * scale, q
+        covered[np.ix_(ri, ci)] = True
+        seen += 1
+    assert seen > 5
+    # the sectors hold the whole tensor: nothing outside them
+    assert np.abs(X[~covered]).max() <= 1e-12 * scale
