@@ -176,9 +176,11 @@ int mpo_layer_blocks(gbs_mpo *h, int max_blocks, int *out);
  * SVD'd; these knobs only choose which kernels do it, the results agree to
  * rounding).  lds_limit_bytes > 0 lowers the LDS budget below the device's:
  * a block whose Jacobi operand exceeds it takes the multi-workgroup panel
- * rounds, and a block exceeding it with at least 1.2x more rows than columns
- * is first reduced by a Householder QR when qr_enable != 0.  0 restores the
- * device budget.  Affects layers planned after the call; not thread-safe. */
+ * rounds.  With qr_enable != 0 a block exceeding it, or with at least 16
+ * columns, is first reduced by a Householder QR with column pivoting;
+ * qr_enable = 0 runs every Jacobi on the block itself.  lds_limit_bytes = 0
+ * restores the device budget.  Affects layers planned after the call; not
+ * thread-safe. */
 int gbs_set_svd_route(int lds_limit_bytes, int qr_enable);
 
 /* Free and total bytes of the current device's memory (hipMemGetInfo), for

@@ -110,17 +110,20 @@ __host__ __device__ inline int panel_width(int m, int n, int lds_bytes, int esz)
   return (n + np - 1) / np;
 }
 
-// Route of a computed block's SVD.  A block whose operand does not fit in LDS
-// is first reduced by a Householder QR, A = Q R, and the Jacobi rotates the
-// n x n operand X = R^H: its columns are far closer to orthogonal than those
-// of A (the Jacobi needs about a third of the sweeps) and the work per sweep
-// drops by m / n.  The Jacobi runs in one workgroup from LDS when its operand
-// fits there, otherwise as multi-workgroup panel rounds.
+// Route of a computed block's SVD.  A block with at least 16 columns, or
+// whose operand does not fit in LDS, is first reduced by a Householder QR,
+// A = Q R, and the Jacobi rotates the n x n operand X = R^H: its columns are
+// far closer to orthogonal than those of A (the Jacobi needs about half the
+// sweeps) and the work per sweep drops by m / n.  The Jacobi runs in one
+// workgroup from LDS when its operand fits there, otherwise as
+// multi-workgroup panel rounds.
+constexpr int QR_MIN_COLS = 16;
+
 __host__ __device__ inline void svd_route(int m, int n, int lds_bytes, int qr_ok, int esz,
                                           int &qr, int &big, int &mj) {
   qr = 0;
   mj = m;
-  if (qr_ok && svd_small_need(m, n, esz) > (size_t)lds_bytes) {
+  if (qr_ok && (svd_small_need(m, n, esz) > (size_t)lds_bytes || n >= QR_MIN_COLS)) {
     qr = 1;
     mj = n;
   }
