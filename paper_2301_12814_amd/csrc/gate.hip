@@ -837,7 +837,277 @@ __device__ __forceinline__ void qr_update(cd *A, int m, int n, int k, int len, c
   }
 }
 
-__global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly) {
+// Householder QR with column pivoting by panels of nb columns (delayed
+// update, in the manner of LAPACK's xLAQPS): inside a panel the reflectors
+// are not applied to the trailing columns; instead F = A^H V T collects them
+// (A the trailing columns as they were when the panel started, V the panel's
+// reflectors, T the triangular factor of Q = H_0 ... H_{nb-1} = I - V T V^H),
+// so that Q^H A = A - V F^H.  Step k of the panel
+//   brings the column of largest remaining norm to position k,
+//   applies the panel's earlier reflectors to column k alone,
+//   forms H_k from it,
+//   appends column tau_k A^H v_k - tau_k F (V^H v_k) to F,
+//   and updates row k of the trailing columns (it becomes a row of R), so
+//   that their remaining norms drop by |R[k, j]|^2.
+// At the end of the panel the trailing columns receive A -= V F^H in one
+// pass, which also recomputes their norms exactly.  A panel ends early when
+// a norm loses more than half of its digits to the downdate.  The trailing
+// columns are read once per step (the product A^H v_k) and written once per
+// panel instead of read and written once per step.
+// LDS: v (m), remaining and reference norms (2 n doubles), F (n x nb, column
+// stride n), per-wave partial norms (16 x 64 doubles).
+constexpr int QR_NB = 8;
+
+// X = R^H (n x n, column-major, lower triangle) from the factored operand.
+__device__ __forceinline__ void qr_write_x(cd *X, const cd *A, int m, int n) {
+  for (long long idx = threadIdx.x; idx < (long long)n * n; idx += blockDim.x) {
+    const int c = (int)(idx / n), i = (int)(idx % n);
+    X[idx] = c <= i ? cconj(A[(size_t)i * m + c]) : cmk(0.0, 0.0);
+  }
+}
+
+__host__ __device__ inline int qr_panel_width(int m, int n, int lds_bytes) {
+  const long long room = (long long)lds_bytes - 16LL * m - 16LL * n - 8 * 16 * 64 - 256;
+  if (n <= 0 || room < 32LL * n) return 1;
+  const long long w = room / (16LL * n);
+  return w < QR_NB ? (int)w : QR_NB;
+}
+
+// LDS of one k_qr_panel workgroup given the device budget.
+__host__ __device__ inline int svd_panel_half(int lds_bytes) { return lds_bytes / 2 - 1024; }
+
+__device__ void qr_blocked(cd *A, int m, int n, cd *tau, int *piv, int nb, double *lds) {
+  cd *v = reinterpret_cast<cd *>(lds);                    // reflector of the step (rows k..)
+  double *cn = reinterpret_cast<double *>(v + m);          // remaining norms^2 (downdated)
+  double *cr = cn + n;                                     // norms^2 at the last exact sum
+  cd *F = reinterpret_cast<cd *>(cr + n);                  // F[j + c n]
+  double *part = reinterpret_cast<double *>(F + (size_t)n * nb);   // [16][64]
+  __shared__ double s_red[16];
+  __shared__ double s_bv[16];
+  __shared__ int s_bi[16];
+  __shared__ cd s_tau, s_scale, s_aux[QR_NB];
+  __shared__ int s_skip, s_piv, s_flag;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int c = wave; c < n; c += nw) {
+    double acc = 0.0;
+    for (int y = lane; y < m; y += 64) acc += cabs2(A[(size_t)c * m + y]);
+    acc = wave_sum(acc);
+    if (lane == 0) cn[c] = cr[c] = acc;
+  }
+  for (int c = threadIdx.x; c < n; c += blockDim.x) piv[c] = c;
+  if (threadIdx.x == 0) s_flag = 0;
+  __syncthreads();
+  int k0 = 0;
+  while (k0 < n) {
+    const int nbk = min(nb, n - k0);
+    int kb = nbk;
+    for (int i = 0; i < nbk; ++i) {
+      const int k = k0 + i;
+      // pivot: largest remaining norm, lowest index on ties
+      double bv = -1.0;
+      int bi = n;
+      for (int c = k + threadIdx.x; c < n; c += blockDim.x)
+        if (cn[c] > bv) { bv = cn[c]; bi = c; }
+      wave_argmax(bv, bi);
+      if (lane == 0) { s_bv[wave] = bv; s_bi[wave] = bi; }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double b = s_bv[0];
+        int p = s_bi[0];
+        for (int w2 = 1; w2 < nw; ++w2)
+          if (s_bv[w2] > b || (s_bv[w2] == b && s_bi[w2] < p)) { b = s_bv[w2]; p = s_bi[w2]; }
+        s_piv = p < n ? p : k;
+      }
+      __syncthreads();
+      const int p = s_piv;
+      if (p != k) {
+        for (int y = threadIdx.x; y < m; y += blockDim.x) {
+          const cd t = A[(size_t)k * m + y];
+          A[(size_t)k * m + y] = A[(size_t)p * m + y];
+          A[(size_t)p * m + y] = t;
+        }
+        for (int c = threadIdx.x; c < i; c += blockDim.x) {
+          const cd t = F[k + (size_t)c * n];
+          F[k + (size_t)c * n] = F[p + (size_t)c * n];
+          F[p + (size_t)c * n] = t;
+        }
+        if (threadIdx.x == 0) {
+          double t = cn[k]; cn[k] = cn[p]; cn[p] = t;
+          t = cr[k]; cr[k] = cr[p]; cr[p] = t;
+          const int ti = piv[k]; piv[k] = piv[p]; piv[p] = ti;
+        }
+        __syncthreads();
+      }
+      // column k: the panel's earlier reflectors, A[k:, k] -= V[k:, :i] F[k, :i]^H
+      cd *x = A + (size_t)k * m + k;
+      const int len = m - k;
+      double s2 = 0.0;
+      for (int y = threadIdx.x; y < len; y += blockDim.x) {
+        cd a = x[y];
+        for (int c = 0; c < i; ++c)
+          a = csub(a, cmul(A[(size_t)(k0 + c) * m + k + y], cconj(F[k + (size_t)c * n])));
+        if (i > 0) x[y] = a;
+        if (y >= 1) s2 += cabs2(a);
+      }
+      s2 = block_sum(s2, s_red);
+      if (threadIdx.x == 0) {
+        const cd al = x[0];
+        if (s2 == 0.0 && al.im == 0.0) {
+          s_skip = 1;
+          s_tau = cmk(0.0, 0.0);
+          tau[k] = cmk(0.0, 0.0);
+        } else {
+          const double nrm = sqrt(al.re * al.re + al.im * al.im + s2);
+          const double beta = al.re >= 0.0 ? -nrm : nrm;
+          const cd t = cmk((beta - al.re) / beta, -al.im / beta);
+          const cd dn = cmk(al.re - beta, al.im);
+          const double dd = cabs2(dn);
+          s_tau = t;
+          s_scale = cmk(dn.re / dd, -dn.im / dd);
+          tau[k] = t;
+          x[0] = cmk(beta, 0.0);
+          s_skip = 0;
+        }
+      }
+      __syncthreads();
+      const bool skip = s_skip != 0;
+      {
+        const cd sc = s_scale;
+        for (int y = 1 + threadIdx.x; y < len; y += blockDim.x) {
+          const cd t = skip ? x[y] : cmul(x[y], sc);
+          if (!skip) x[y] = t;
+          v[y] = t;
+        }
+        if (threadIdx.x == 0) v[0] = cmk(1.0, 0.0);
+      }
+      __syncthreads();
+      // F[j, i] = tau_k A[k:, j]^H v (trailing j > k) and s_aux[c] = -tau_k V[k:, c]^H v
+      const cd tk = s_tau;
+      const int ntr = n - k - 1;
+      for (int t = wave; t < ntr + i; t += nw) {
+        const int col = t < ntr ? k + 1 + t : k0 + (t - ntr);
+        const cd *a = A + (size_t)col * m + k;
+        double wr = 0.0, wi = 0.0;
+        int y = lane;
+        for (; y + 192 < len; y += 256) {
+          const cd a0 = a[y], a1 = a[y + 64], a2 = a[y + 128], a3 = a[y + 192];
+          const cd q0 = cmulc(a0, v[y]), q1 = cmulc(a1, v[y + 64]);
+          const cd q2 = cmulc(a2, v[y + 128]), q3 = cmulc(a3, v[y + 192]);
+          wr += (q0.re + q1.re) + (q2.re + q3.re);
+          wi += (q0.im + q1.im) + (q2.im + q3.im);
+        }
+        for (; y < len; y += 64) {
+          const cd q = cmulc(a[y], v[y]);
+          wr += q.re;
+          wi += q.im;
+        }
+        wr = group_sum<64>(wr);
+        wi = group_sum<64>(wi);
+        if (lane == 0) {
+          const cd f = cmul(tk, cmk(wr, wi));
+          if (t < ntr) F[col + (size_t)i * n] = f;
+          else s_aux[t - ntr] = cmk(-f.re, -f.im);
+        }
+      }
+      __syncthreads();
+      // F[j, i] += F[j, :i] s_aux, then row k of the trailing columns and
+      // their remaining norms
+      for (int j = k + 1 + threadIdx.x; j < n; j += blockDim.x) {
+        cd f = F[j + (size_t)i * n];
+        for (int c = 0; c < i; ++c) cfma(f, F[j + (size_t)c * n], s_aux[c]);
+        F[j + (size_t)i * n] = f;
+        cd a = A[(size_t)j * m + k];
+        for (int c = 0; c < i; ++c)
+          a = csub(a, cmul(A[(size_t)(k0 + c) * m + k], cconj(F[j + (size_t)c * n])));
+        a = csub(a, cconj(f));                 // v_k[0] = 1
+        A[(size_t)j * m + k] = a;
+        const double rest = cn[j] - cabs2(a);
+        if (cr[j] > 0.0 && !(rest > 1e-8 * cr[j])) s_flag = 1;
+        cn[j] = fmax(rest, 0.0);
+      }
+      __syncthreads();
+      if (s_flag) {
+        kb = i + 1;
+        break;
+      }
+    }
+    // trailing columns j >= k1, rows y >= k1: A -= V F^H, exact norms.
+    // Waves own 64-row chunks (their V rows in registers) and, when the
+    // chunks are fewer than the waves, interleaved column groups.
+    const int k1 = k0 + kb;
+    const int R = m - k1, N2 = n - k1;
+    if (R > 0 && N2 > 0) {
+      const int nrc = (R + 63) / 64;
+      const int ncg = nrc >= nw ? 1 : nw / nrc;
+      const int nchunk_w = nrc >= nw ? nw : nrc;    // rows of part in use
+      const int chunk0 = nrc >= nw ? wave : wave % nrc;
+      const int grp = nrc >= nw ? 0 : wave / nrc;
+      const bool active = grp < ncg;
+      for (int jb = 0; jb < N2; jb += 64) {
+        const int nj = min(64, N2 - jb);
+        if (active) {
+          // partial norms of this wave's columns over its chunks, in chunk order
+          for (int jl = grp; jl < nj; jl += ncg)
+            if (lane == 0) part[(size_t)(nrc >= nw ? wave : chunk0) * 64 + jl] = 0.0;
+          for (int ch = chunk0; ch < nrc; ch += (nrc >= nw ? nw : nrc)) {
+            const int y = k1 + ch * 64 + lane;
+            const bool row = y < m;
+            cd vr[QR_NB];
+#pragma unroll
+            for (int c = 0; c < QR_NB; ++c)
+              vr[c] = (c < kb && row) ? A[(size_t)(k0 + c) * m + y] : cmk(0.0, 0.0);
+            for (int jl = grp; jl < nj; jl += ncg) {
+              const int j = k1 + jb + jl;
+              cd a = row ? A[(size_t)j * m + y] : cmk(0.0, 0.0);
+#pragma unroll
+              for (int c = 0; c < QR_NB; ++c)
+                if (c < kb) a = csub(a, cmul(vr[c], cconj(F[j + (size_t)c * n])));
+              if (row) A[(size_t)j * m + y] = a;
+              const double pn = group_sum<64>(row ? cabs2(a) : 0.0);
+              if (lane == 0) part[(size_t)(nrc >= nw ? wave : chunk0) * 64 + jl] += pn;
+            }
+            if (nrc < nw) break;                    // one chunk per wave
+          }
+        }
+        __syncthreads();
+        for (int jl = threadIdx.x; jl < nj; jl += blockDim.x) {
+          double t = 0.0;
+          for (int r = 0; r < nchunk_w; ++r) t += part[(size_t)r * 64 + jl];
+          cn[k1 + jb + jl] = cr[k1 + jb + jl] = t;
+        }
+        __syncthreads();
+      }
+    }
+    if (threadIdx.x == 0) s_flag = 0;
+    __syncthreads();
+    k0 = k1;
+  }
+}
+
+// QR of every block whose panel of F fits in LDS (the others: k_qr).
+// Two workgroups of 512 threads share a CU (each with half of its LDS): the
+// factorisation is a chain of short dependent steps, and the second
+// workgroup's steps fill the first one's waits.
+constexpr int QRP_THREADS = 512;
+
+__global__ __launch_bounds__(QRP_THREADS, 4) void k_qr_panel(Layer ly, int lds_bytes) {
+  const int flat = blockIdx.x;
+  const int g = find_gate_blk(ly.base, ly.ngates, flat);
+  const GateBase gb = ly.base[g];
+  const GateParam gp = ly.gates[g];
+  const BlkDesc B = ly.blk[gp.blk0 + (flat - gb.blk)];
+  if (!B.comp || !B.qr) return;
+  const int m = B.m, n = B.n;
+  const int nb = qr_panel_width(m, n, lds_bytes);
+  if (nb < 2) return;
+  cd *A = ly.A + gb.e + B.eoff;
+  extern __shared__ __attribute__((aligned(16))) double s_dyn[];
+  qr_blocked(A, m, n, ly.tau + gp.lst0 + B.svoff, ly.piv + gp.lst0 + B.svoff, nb, s_dyn);
+  __syncthreads();
+  qr_write_x(ly.R + gb.r + B.joff, A, m, n);
+}
+
+__global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly, int lds_bytes) {
   const int flat = blockIdx.x;
   const int g = find_gate_blk(ly.base, ly.ngates, flat);
   const GateBase gb = ly.base[g];
@@ -849,6 +1119,8 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly) {
   cd *tau = ly.tau + gp.lst0 + B.svoff;
   int *piv = ly.piv + gp.lst0 + B.svoff;
   extern __shared__ __attribute__((aligned(16))) double s_dyn[];
+  if (qr_panel_width(m, n, svd_panel_half(lds_bytes)) >= 2) return;   // k_qr_panel's block
+  // one column at a time (operands too large for a panel of F in LDS)
   cd *v = reinterpret_cast<cd *>(s_dyn);             // current reflector, m - k entries
   double *cn = reinterpret_cast<double *>(v + m);    // remaining column norms^2
   __shared__ double s_red[16];
@@ -995,17 +1267,19 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly) {
     }
     __syncthreads();
   }
-  cd *X = ly.R + gb.r + B.joff;    // X[i, c] = conj(R[c, i]), column-major
-  for (long long idx = threadIdx.x; idx < (long long)n * n; idx += blockDim.x) {
-    const int c = (int)(idx / n), i = (int)(idx % n);
-    X[idx] = c <= i ? cconj(A[(size_t)i * m + c]) : cmk(0.0, 0.0);
-  }
+  qr_write_x(ly.R + gb.r + B.joff, A, m, n);
 }
 
 hipError_t launch_qr(Layer ly, int max_chi, hipStream_t s) {
   if (ly.total_blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_qr, dim3(ly.total_blocks), dim3(QR_THREADS),
-                     (sizeof(cd) + sizeof(double)) * (size_t)max_chi, s, ly);
+  (void)max_chi;
+  const int lb = svd_lds_bytes();
+  const int half = svd_panel_half(lb);
+  hipLaunchKernelGGL(k_qr_panel, dim3(ly.total_blocks), dim3(QRP_THREADS), (size_t)half, s, ly,
+                     half);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_qr, dim3(ly.total_blocks), dim3(QR_THREADS), (size_t)lb, s, ly, lb);
   return hipGetLastError();
 }
 
@@ -1566,6 +1840,7 @@ int svd_lds_bytes() {
     hipFuncSetAttribute((const void *)k_panel<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_panel<cf>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_qr, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    hipFuncSetAttribute((const void *)k_qr_panel, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_leftvec, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_scatter, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_big_finish, hipFuncAttributeMaxDynamicSharedMemorySize, b);
@@ -1613,7 +1888,7 @@ hipError_t launch_svd_big_prep(Layer ly, hipStream_t s) {
 int panel_lds_bytes(int max_chi) {
   const int lb = svd_lds_bytes();
   if (!GBS_PANEL_HALF_LDS) return lb;
-  const int half = lb / 2 - 1024;
+  const int half = svd_panel_half(lb);
   // two columns of the longest operand must fit at panel width 1
   return 2 * (int)sizeof(cd) * max_chi <= half ? half : lb;
 }
