@@ -1881,8 +1881,12 @@ hipError_t launch_svd_big_prep(Layer ly, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Panel workgroups take half the LDS (and 512 threads) so that two share a
+// CU: each round is a chain of short barrier-separated sub-rounds, and the
+// second workgroup fills the first one's waits; the narrower panels cost
+// more rounds but less than they return.
 #ifndef GBS_PANEL_HALF_LDS
-#define GBS_PANEL_HALF_LDS 0
+#define GBS_PANEL_HALF_LDS 1
 #endif
 
 int panel_lds_bytes(int max_chi) {
