@@ -172,14 +172,17 @@ def run_batch(args, prec):
     p50, p99 = _percentiles(list(done_at.values()))
     return {
         "metric": "batched simulations/s (256 instances of the batch law)",
-        "value": len(ids) / elapsed, "unit": "simulations/s", "n_gpus": 1, "steps": 1,
+        "value": (len(ids) - len(failed)) / elapsed, "unit": "simulations/s", "n_gpus": 1,
+        "steps": 1,
         "warmup": 0, "ms_per_step": elapsed * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if prec == gbsmpo.MPO_FP64 else "mixed",
         "data": "synthetic (seeded Haar interferometers, batch law)",
         "config": {"workload": f"batch of {len(ids)}: M~U{{16..48}}, r~U[0.3,1.2], "
                                f"eta~U[0.2,0.8], d~U{{6,8,10}}, chi~U{{64,...,512}}, seeds 1000+i; "
                                f"{n_gates} beam splitters"},
-        "gate_updates_per_s": n_gates / elapsed,
+        "gate_updates_per_s": (n_gates - sum(ws[i].M * (ws[i].M - 1) // 2 for i, s in
+                                             enumerate(ids) if s in {f[0] for f in failed}))
+                              / elapsed,
         "completion_s": {"p50": p50, "p99": p99},
         "engine_steps": step,
         "phase_ms": ms,
@@ -279,6 +282,8 @@ def run_serve(args, prec):
                         k = running.pop(sid)
                         eng.release(sid)
                         with lock:
+                            if r == "failed":     # counted apart, not as served
+                                continue
                             lat[k] = now - reqs[k][0]
                             if len(lat) % 10 == 0:
                                 print(f"{len(lat)} done at {now:.1f} s ({name} lane: "
@@ -396,12 +401,13 @@ def main():
     launches = max(phase_n[dom], 1)
     avg_ms = phase_ms[dom] / launches
     if dom == "svd":
-        # one "launch" = the SVD stage of one layer: k_qr, the k_svd_small size
-        # classes, k_big_prep, the k_panel steps with their k_big_count checks
-        # and k_big_finish, timed by HIP events on the library's stream
+        # one "launch" = the SVD stage of one layer: k_qr_panel and k_qr, the
+        # k_svd_small size classes, k_big_prep, the k_panel steps with their
+        # k_big_count checks and k_big_finish, timed by HIP events on the
+        # library's stream
         per_launch = work["svd_flops"] / launches
         achieved = per_launch / (avg_ms * 1e-3) / 1e12
-        roof = {"kernel": "svd stage per layer (k_qr + k_svd_small + k_panel steps + k_big_*)",
+        roof = {"kernel": "svd stage per layer (k_qr_panel + k_qr + k_svd_small + k_panel steps + k_big_*)",
                 "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFS,
                 "traffic": stage_traffic(w.name, args.precision, len(layers)),

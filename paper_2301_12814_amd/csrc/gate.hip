@@ -117,7 +117,10 @@ __host__ __device__ inline int panel_width(int m, int n, int lds_bytes, int esz)
 // sweeps) and the work per sweep drops by m / n.  The Jacobi runs in one
 // workgroup from LDS when its operand fits there, otherwise as
 // multi-workgroup panel rounds.
-constexpr int QR_MIN_COLS = 16;
+#ifndef GBS_QR_MIN_COLS
+#define GBS_QR_MIN_COLS 16
+#endif
+constexpr int QR_MIN_COLS = GBS_QR_MIN_COLS;
 
 __host__ __device__ inline void svd_route(int m, int n, int lds_bytes, int qr_ok, int esz,
                                           int &qr, int &big, int &mj) {
@@ -714,6 +717,23 @@ hipError_t launch_ctab(Layer ly, hipStream_t s) {
 // The column pivoting grades R, so that the Jacobi on X needs few sweeps.
 // ----------------------------------------------------------------------------
 constexpr int QR_THREADS = 1024;
+
+// Reflector of the column x = (al, rest), |rest|^2 = s2 (formulas above).
+// Returns false (no reflection, H = I) when x is already a multiple of e_1,
+// or when x is so small that |x|^2 underflows and the reflector cannot be
+// formed in finite arithmetic: such a column is rounding noise (its
+// entries below the diagonal, left in place, never reach X = R^H).
+__device__ inline bool householder(cd al, double s2, cd &tau, cd &scale, double &beta) {
+  if (s2 == 0.0 && al.im == 0.0) return false;
+  const double nrm = sqrt(al.re * al.re + al.im * al.im + s2);
+  beta = al.re >= 0.0 ? -nrm : nrm;
+  tau = cmk((beta - al.re) / beta, -al.im / beta);
+  const cd dn = cmk(al.re - beta, al.im);
+  const double dd = cabs2(dn);
+  scale = cmk(dn.re / dd, -dn.im / dd);
+  return nrm > 0.0 && isfinite(tau.re) && isfinite(tau.im) && isfinite(scale.re) &&
+         isfinite(scale.im);
+}
 constexpr int QC = 16;   // column elements per lane kept in registers (m - k <= 1024)
 
 __device__ __forceinline__ double block_sum(double v, double *s_red);
@@ -866,7 +886,12 @@ __device__ __forceinline__ void qr_write_x(cd *X, const cd *A, int m, int n) {
   }
 }
 
+#ifndef GBS_QR_PANELS
+#define GBS_QR_PANELS 1
+#endif
+
 __host__ __device__ inline int qr_panel_width(int m, int n, int lds_bytes) {
+  if (!GBS_QR_PANELS) return 1;
   const long long room = (long long)lds_bytes - 16LL * m - 16LL * n - 8 * 16 * 64 - 256;
   if (n <= 0 || room < 32LL * n) return 1;
   const long long w = room / (16LL * n);
@@ -951,19 +976,15 @@ __device__ void qr_blocked(cd *A, int m, int n, cd *tau, int *piv, int nb, doubl
       }
       s2 = block_sum(s2, s_red);
       if (threadIdx.x == 0) {
-        const cd al = x[0];
-        if (s2 == 0.0 && al.im == 0.0) {
+        cd t, sc;
+        double beta;
+        if (!householder(x[0], s2, t, sc, beta)) {
           s_skip = 1;
           s_tau = cmk(0.0, 0.0);
           tau[k] = cmk(0.0, 0.0);
         } else {
-          const double nrm = sqrt(al.re * al.re + al.im * al.im + s2);
-          const double beta = al.re >= 0.0 ? -nrm : nrm;
-          const cd t = cmk((beta - al.re) / beta, -al.im / beta);
-          const cd dn = cmk(al.re - beta, al.im);
-          const double dd = cabs2(dn);
           s_tau = t;
-          s_scale = cmk(dn.re / dd, -dn.im / dd);
+          s_scale = sc;
           tau[k] = t;
           x[0] = cmk(beta, 0.0);
           s_skip = 0;
@@ -1173,18 +1194,14 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly, int lds_bytes) {
     for (int y = 1 + threadIdx.x; y < len; y += blockDim.x) s2 += cabs2(x[y]);
     s2 = block_sum(s2, s_red);
     if (threadIdx.x == 0) {
-      const cd al = x[0];
-      if (s2 == 0.0 && al.im == 0.0) {
+      cd t, sc;
+      double beta;
+      if (!householder(x[0], s2, t, sc, beta)) {
         s_skip = 1;
         tau[k] = cmk(0.0, 0.0);
       } else {
-        const double nrm = sqrt(al.re * al.re + al.im * al.im + s2);
-        const double beta = al.re >= 0.0 ? -nrm : nrm;
-        const cd t = cmk((beta - al.re) / beta, -al.im / beta);
-        const cd dn = cmk(al.re - beta, al.im);
-        const double dd = cabs2(dn);
         s_tau = t;
-        s_scale = cmk(dn.re / dd, -dn.im / dd);
+        s_scale = sc;
         tau[k] = t;
         x[0] = cmk(beta, 0.0);
         s_skip = 0;
@@ -1881,12 +1898,12 @@ hipError_t launch_svd_big_prep(Layer ly, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Panel workgroups take half the LDS (and 512 threads) so that two share a
-// CU: each round is a chain of short barrier-separated sub-rounds, and the
-// second workgroup fills the first one's waits; the narrower panels cost
-// more rounds but less than they return.
+// GBS_PANEL_HALF_LDS = 1: panel workgroups take half the LDS (and 512
+// threads) so that two share a CU.  Over whole evolutions the narrower
+// panels' extra rounds cancel what the shared CU returns, and they double
+// the panels' HBM traffic, so the default keeps one panel workgroup per CU.
 #ifndef GBS_PANEL_HALF_LDS
-#define GBS_PANEL_HALF_LDS 1
+#define GBS_PANEL_HALF_LDS 0
 #endif
 
 int panel_lds_bytes(int max_chi) {

@@ -411,6 +411,32 @@ def test_gpu_noise_level_sectors_converge(idx):
                 assert np.allclose(v, m, rtol=1e-12, atol=1e-14 * lam.max()), (b, a, c)
 
 
+@pytest.mark.parametrize("idx", [29, 34])
+def test_gpu_underflowing_sectors_through_qr(svd_route, idx):
+    """Batch-law instances (M=34/35, d=10, chi=512) whose outer sectors hold
+    values near the bottom of the double range: the QR route must not turn
+    them into non-finite reflectors, and the whole run must agree with the
+    route that runs every Jacobi on the block itself."""
+    w = inputs.batch_workloads(idx + 1)[idx]
+    U = inputs.haar_unitary(w.M, w.seed)
+    layers, phase = gbsmpo.clements(U)
+    out = []
+    for qr in (True, False):
+        svd_route(0, qr)
+        say("underflow case", idx, (w.M, w.d, w.chi), "qr", qr)
+        with gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi) as g:
+            for (S, T, P) in layers:
+                g.apply_layer(S, T, P)
+            g.apply_phases(phase)
+            S, smax = g.entropy()
+            P, tr = g.marginals()
+        assert np.all(np.isfinite(S)) and np.all(np.isfinite(P)) and math.isfinite(tr)
+        out.append((S, P, tr))
+    (S1, P1, t1), (S2, P2, t2) = out
+    assert np.abs(S1 - S2).max() < 1e-8
+    assert np.abs(P1 - P2).max() < 1e-8 and abs(t1 - t2) < 1e-8 * abs(t2)
+
+
 @pytest.mark.parametrize("lds", [0, 3000])
 def test_gpu_mixed_precision_small_matches_oracle(svd_route, lds):
     """Mixed-precision path (FP32 Jacobi on the operand normalised to unit
