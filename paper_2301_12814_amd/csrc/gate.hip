@@ -1500,6 +1500,9 @@ __device__ __forceinline__ void round_robin_pass_l(T *A, double *nrm, int m, int
 #ifndef GBS_PANEL_LANES
 #define GBS_PANEL_LANES 32
 #endif
+#ifndef GBS_PANEL_WIDE
+#define GBS_PANEL_WIDE 1
+#endif
 
 // Cross pairs of two panels held in LDS (wI columns then wJ columns, panel
 // width w): w sub-rounds, column t of the first panel with (t + sr) mod w of
@@ -1770,7 +1773,15 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
   __shared__ double s_nrm[64];
   column_norms(sA, m, nc, s_nrm);
   int rot = 0;
-  if (round == 0) {
+  // panels of at most one pair per 64-lane slot take whole wavefronts per
+  // pair: half the elements per lane (long columns stay in registers) for
+  // one more, cheap, lane-swap step of every reduction
+  if (w * 64 <= (int)blockDim.x && GBS_PANEL_WIDE) {
+    if (round == 0)
+      round_robin_pass_l<64>(sA, s_nrm, m, nc, tol, tiny, rot);
+    else
+      cross_pass_l<64>(sA, s_nrm, m, w, wI, wJ, tol, tiny, rot);
+  } else if (round == 0) {
     round_robin_pass_l<GBS_PANEL_LANES>(sA, s_nrm, m, nc, tol, tiny, rot);
   } else {
     cross_pass_l<GBS_PANEL_LANES>(sA, s_nrm, m, w, wI, wJ, tol, tiny, rot);
