@@ -2085,6 +2085,7 @@ hipError_t launch_select(Layer ly, hipStream_t s) {
 // the V pool (at the R offset), each lane owning fixed rows.
 // ----------------------------------------------------------------------------
 constexpr int LV_CHUNK = 8;    // kept vectors per pass over the pristine sector
+constexpr int LV_XCHUNK = 256; // vector entries staged in LDS at a time
 
 __global__ __launch_bounds__(256) void k_leftvec(Layer ly, int nchunk) {
   const int flat = blockIdx.x;
@@ -2153,34 +2154,57 @@ __global__ __launch_bounds__(256) void k_leftvec(Layer ly, int nchunk) {
     }
     __syncthreads();
   }
-  // 2. U = A0 V, LV_CHUNK vectors per pass over A0 (v from LDS, A0 read once per pass)
+  // 2. U = A0 V, LV_CHUNK vectors per pass over A0 (A0 read once per pass);
+  // the vectors are staged in LDS LV_XCHUNK entries at a time, so that the
+  // workgroup's LDS does not scale with the bond dimension
   for (int c0 = 0; c0 < B.kq; c0 += nchunk) {
     const int nc = min(nchunk, B.kq - c0);
-    for (int idx = threadIdx.x; idx < nc * n; idx += blockDim.x) {
-      const int c = idx / n, x = idx % n;
-      sV[(size_t)c * n + x] = cconj(V[(size_t)(c0 + c) * n + x]);    // v
-    }
-    __syncthreads();
     double nu[LV_CHUNK];
 #pragma unroll
     for (int c = 0; c < LV_CHUNK; ++c) nu[c] = 0.0;
-    for (int y = threadIdx.x; y < m; y += blockDim.x) {
+    for (int y0 = 0; y0 < m; y0 += blockDim.x) {
+      const int y = y0 + threadIdx.x;
+      const bool row = y < m;
       cd acc[LV_CHUNK];
 #pragma unroll
       for (int c = 0; c < LV_CHUNK; ++c) acc[c] = cmk(0.0, 0.0);
-      for (int x = 0; x < n; ++x) {
-        const cd a = A0[(size_t)x * m + y];
+      for (int x0 = 0; x0 < n; x0 += LV_XCHUNK) {
+        const int nx = min(LV_XCHUNK, n - x0);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < nc * nx; idx += blockDim.x) {
+          const int c = idx / nx, xl = idx % nx;
+          sV[(size_t)c * LV_XCHUNK + xl] = cconj(V[(size_t)(c0 + c) * n + x0 + xl]);    // v
+        }
+        __syncthreads();
+        if (row) {
+          const cd *a0 = A0 + (size_t)x0 * m + y;
+          int xl = 0;
+          for (; xl + 3 < nx; xl += 4) {
+            const cd a[4] = {a0[(size_t)xl * m], a0[(size_t)(xl + 1) * m],
+                             a0[(size_t)(xl + 2) * m], a0[(size_t)(xl + 3) * m]};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int c = 0; c < LV_CHUNK; ++c)
+                if (c < nc) cfma(acc[c], a[u], sV[(size_t)c * LV_XCHUNK + xl + u]);
+          }
+          for (; xl < nx; ++xl) {
+            const cd a = a0[(size_t)xl * m];
+#pragma unroll
+            for (int c = 0; c < LV_CHUNK; ++c)
+              if (c < nc) cfma(acc[c], a, sV[(size_t)c * LV_XCHUNK + xl]);
+          }
+        }
+      }
+      if (row) {
 #pragma unroll
         for (int c = 0; c < LV_CHUNK; ++c)
-          if (c < nc) cfma(acc[c], a, sV[(size_t)c * n + x]);
+          if (c < nc) {
+            const double s1 = ly.mixed ? 1.0 : 1.0 / sv[c0 + c];
+            U[(size_t)(c0 + c) * m + y] = cscale(acc[c], s1);
+            nu[c] += cabs2(acc[c]);
+          }
       }
-#pragma unroll
-      for (int c = 0; c < LV_CHUNK; ++c)
-        if (c < nc) {
-          const double s1 = ly.mixed ? 1.0 : 1.0 / sv[c0 + c];
-          U[(size_t)(c0 + c) * m + y] = cscale(acc[c], s1);
-          nu[c] += cabs2(acc[c]);
-        }
     }
     if (ly.mixed) {
       // sigma_i refined in FP64 as |A0 v_i|, u_i normalised
@@ -2204,11 +2228,9 @@ __global__ __launch_bounds__(256) void k_leftvec(Layer ly, int nchunk) {
 
 hipError_t launch_leftvec(Layer ly, int max_chi, hipStream_t s) {
   if (ly.total_blocks == 0) return hipSuccess;
-  // as many vectors per pass as the LDS holds (n <= max_chi entries each)
-  int nchunk = svd_lds_bytes() / (int)(sizeof(cd) * (size_t)max_chi);
-  nchunk = nchunk < 1 ? 1 : (nchunk > LV_CHUNK ? LV_CHUNK : nchunk);
+  (void)max_chi;
   hipLaunchKernelGGL(k_leftvec, dim3(ly.total_blocks), dim3(256),
-                     sizeof(cd) * (size_t)nchunk * max_chi, s, ly, nchunk);
+                     sizeof(cd) * (size_t)LV_CHUNK * LV_XCHUNK, s, ly, LV_CHUNK);
   return hipGetLastError();
 }
 
