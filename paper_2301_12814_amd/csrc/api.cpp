@@ -584,7 +584,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
       ++c1;
     }
     const int ng = c1 - c0;
-    long long e = 0, ch = 0, blk0 = 0, lst0 = 0, re = 0;
+    long long e = 0, blk0 = 0, lst0 = 0, re = 0;
     int blkb = 0, bigb = 0, maxpp = 0;
     for (int g = c0; g < c1; ++g) {
       const GateTot &t = E.h_tot[g];
@@ -593,10 +593,9 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
       gp.lst0 = lst0;
       blk0 += std::max(t.nblk, 1);
       lst0 += std::max(std::max(t.rows, t.cols), std::max(t.sv, 1));
-      E.h_base[g - c0] = GateBase{e, blkb, bigb, ch, re};
+      E.h_base[g - c0] = GateBase{e, blkb, bigb, re};
       e += t.elems;
       re += t.relems;
-      ch += t.chunks;
       blkb += t.nblk;
       bigb += t.nbig;
       maxpp = std::max(maxpp, t.maxpp);
@@ -654,7 +653,6 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     C.task_pre = E.d_tasks.p + std::max(bigb, 1);
     C.nact = 0;
     C.ntask = 0;
-    C.total_chunks = ch;
     C.total_blocks = blkb;
     C.total_big = bigb;
     C.maxpp = maxpp;

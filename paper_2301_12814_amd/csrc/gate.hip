@@ -90,7 +90,6 @@ __device__ inline int count_window(const int *c, int D, int n, int lo, int hi) {
   return lower_bound(c, D, pack_charge(n, hi + 1)) - lower_bound(c, D, pack_charge(n, lo));
 }
 
-constexpr int CHUNK = 256;
 constexpr int RUNS_PER_BLOCK = 64;   // 4 tables of up to 16 (d <= 16) per block
 
 // LDS bytes of the one-workgroup Jacobi (operand + column norms) and the
@@ -244,7 +243,7 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
   BlkDesc *blk = ly.blk + gp.blk0;
   // pass 1: the non-empty blocks in charge order (counted, or compacted)
   long long nb = 0, eb = 0, reb = 0;
-  int svb = 0, rb = 0, cb = 0, chb = 0, bgb = 0, maxr = 0, maxc = 0, maxpp = 0;
+  int svb = 0, rb = 0, cb = 0, bgb = 0, maxr = 0, maxc = 0, maxpp = 0;
   double fl = 0.0;
   for (long long c0 = 0; c0 < area; c0 += blockDim.x) {
     const long long cell = c0 + threadIdx.x;
@@ -270,7 +269,6 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
         if (comp) {
           eb += (long long)r * s;
           svb += n;
-          chb += (int)(((long long)r * s + CHUNK - 1) / CHUNK);
           fl += 16.0 * m * (double)n * n + 36.0 * (double)n * n * n;
           int qr, big, mj;
           svd_route(m, n, lds_bytes, qr_ok, ly.esz, qr, big, mj);
@@ -305,10 +303,10 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
   if (!FILL) {
     // block-wide totals
     __shared__ long long s_nb, s_eb, s_re;
-    __shared__ int s_sv, s_rb, s_cb, s_ch, s_bg, s_mr, s_mc, s_pp;
+    __shared__ int s_sv, s_rb, s_cb, s_bg, s_mr, s_mc, s_pp;
     __shared__ double s_fl;
     if (threadIdx.x == 0) {
-      s_nb = 0; s_eb = 0; s_re = 0; s_sv = 0; s_rb = 0; s_cb = 0; s_ch = 0; s_bg = 0; s_mr = 0; s_mc = 0;
+      s_nb = 0; s_eb = 0; s_re = 0; s_sv = 0; s_rb = 0; s_cb = 0; s_bg = 0; s_mr = 0; s_mc = 0;
       s_pp = 0; s_fl = 0.0;
     }
     __syncthreads();
@@ -318,7 +316,6 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
     atomicAdd(&s_sv, svb);
     atomicAdd(&s_rb, rb);
     atomicAdd(&s_cb, cb);
-    atomicAdd(&s_ch, chb);
     atomicAdd(&s_bg, bgb);
     atomicMax(&s_mr, maxr);
     atomicMax(&s_mc, maxc);
@@ -334,7 +331,6 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
       tot.maxc = s_mc;
       tot.elems = s_eb;
       tot.relems = s_re;
-      tot.chunks = s_ch;
       tot.nbig = s_bg;
       tot.maxpp = s_pp;
       tot.svd_flops = s_fl;
@@ -360,18 +356,17 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
   // pass 2: offsets; each computed block goes either to the one-workgroup LDS
   // Jacobi (operand fits in LDS) or to the multi-workgroup panel rounds
   int *bigl = ly.bigl + gp.lst0;
-  eb = 0; reb = 0; svb = 0; rb = 0; cb = 0; chb = 0; bgb = 0;
+  eb = 0; reb = 0; svb = 0; rb = 0; cb = 0; bgb = 0;
   for (int b0 = 0; b0 < nblk; b0 += blockDim.x) {
     const int bi = b0 + threadIdx.x;
     long long e = 0, re = 0;
-    int sv = 0, r = 0, c = 0, ch = 0, bg = 0, w = 0, npan = 0, qr = 0, mj = 0;
+    int sv = 0, r = 0, c = 0, bg = 0, w = 0, npan = 0, qr = 0, mj = 0;
     if (bi < nblk) {
       const BlkDesc &B = blk[bi];
       mj = B.m;
       if (B.comp) {
         e = (long long)B.r * B.s;
         sv = B.n;
-        ch = (int)((e + CHUNK - 1) / CHUNK);
         svd_route(B.m, B.n, lds_bytes, qr_ok, ly.esz, qr, bg, mj);
         if (qr) re = (long long)B.n * B.n;
         if (bg) {
@@ -383,13 +378,12 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
       c = B.s;
     }
     long long te, tre;
-    int tsv, tr, tc, tch, tbg;
+    int tsv, tr, tc, tbg;
     const long long pe = eb + block_exclusive_scan<long long>(e, s_scan, te);
     const long long pre = reb + block_exclusive_scan<long long>(re, s_scan, tre);
     const int psv = svb + block_exclusive_scan<int>(sv, s_iscan, tsv);
     const int pr = rb + block_exclusive_scan<int>(r, s_iscan, tr);
     const int pc = cb + block_exclusive_scan<int>(c, s_iscan, tc);
-    const int pch = chb + block_exclusive_scan<int>(ch, s_iscan, tch);
     const int pbg = bgb + block_exclusive_scan<int>(bg, s_iscan, tbg);
     if (bi < nblk) {
       BlkDesc &B = blk[bi];
@@ -397,7 +391,6 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
       B.svoff = psv;
       B.roff = pr;
       B.coff = pc;
-      B.uoff = pch;   // chunk offset until the select kernel reuses the field
       B.big = bg;
       B.w = w;
       B.npan = npan;
@@ -408,7 +401,7 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
       B.sweeps = 0;
       if (bg) bigl[pbg] = bi;
     }
-    eb += te; reb += tre; svb += tsv; rb += tr; cb += tc; chb += tch; bgb += tbg;
+    eb += te; reb += tre; svb += tsv; rb += tr; cb += tc; bgb += tbg;
   }
   __syncthreads();
   // pass 3: row / column index lists (ascending) and, per block, the run
@@ -475,14 +468,6 @@ __device__ inline int find_gate_blk(const GateBase *base, int ng, int flat) {
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (base[mid].blk <= flat) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-__device__ inline int find_gate_chunk(const GateBase *base, int ng, long long flat) {
-  int lo = 0, hi = ng;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (base[mid].echunk <= flat) lo = mid; else hi = mid;
   }
   return lo;
 }

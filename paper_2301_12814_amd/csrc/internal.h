@@ -50,7 +50,7 @@ struct BlkDesc {
 
 // Per-gate plan totals (device -> host).
 struct GateTot {
-  int nblk, sv, rows, cols, maxr, maxc, chunks, sym;
+  int nblk, sv, rows, cols, maxr, maxc, sym;
   int nbig, maxpp;    // big blocks, largest even panel count among them
   long long elems;
   long long relems;   // R factors of the QR'd blocks (sum of n^2)
@@ -63,7 +63,6 @@ struct GateBase {
   long long e;        // first operand element of the gate in the A / A0 pools
   int blk;            // first block (flat over the layer)
   int big;            // first big block (flat over the layer)
-  long long echunk;   // first 256-element chunk of the gate
   long long r;        // first element of the gate in the R pool
 };
 
@@ -117,7 +116,6 @@ struct Layer {
   unsigned long long *uval;   // selection units: value bits
   unsigned long long *ukey;   // selection units: tie key
   int *usize;                 // selection units: size (1 or 2)
-  long long total_chunks;     // 256-element chunks in the layer
   int total_blocks;
 };
 
