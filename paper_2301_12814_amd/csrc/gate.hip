@@ -13,8 +13,10 @@
 // and Gamma~_j = V / lam_L, Gamma~_{j+1} = W^dag / lam_R (App. D).
 //
 // Kernels, in launch order: k_fock (Fock tables), k_plan (sector planning),
-// k_contract (Theta blocks), k_svd (one-sided Jacobi), k_select (truncation),
-// k_zero + k_scatter (new tensors), k_entropy_layer (EE of the new bonds).
+// k_ctab + k_contract (Theta blocks), k_qr_panel / k_qr (pivoted QR),
+// k_svd_small and the k_panel rounds (one-sided Jacobi), k_big_finish,
+// k_select (truncation), k_leftvec (kept vectors of QR'd blocks), k_zero +
+// k_scatter (new tensors), k_entropy_layer (EE of the new bonds).
 #include <math.h>
 
 #include "blockops.h"
