@@ -464,21 +464,25 @@ def sector_theta(Gj, Gj1, lamL, lamC, lamR, cL, cC, cR, theta: float, phi: float
     Th = np.zeros((len(rows), len(cols)), dtype=complex)
     if len(rows) == 0 or len(cols) == 0:
         return rows, cols, Th
-    ca = cL[rows][:, None, :]          # (r, 1, 2)
-    cb = cR[cols][None, :, :]          # (1, s, 2)
+    ca = cL[rows]                      # (r, 2)
+    cb = cR[cols]                      # (s, 2)
     for p in np.unique(cC, axis=0):
-        al = np.nonzero(np.all(cC == p, axis=1))[0]
-        i_in = ca - p                   # occupation of mode m before the gate
-        j_in = p - cb                   # occupation of mode m+1 before the gate
-        ok = inside(i_in) & inside(j_in)
-        if not ok.any():
+        # the delta factors of Eq. theta admit a term only on the rows whose
+        # old occupation c_a - p and the columns whose c_b side p - c_b lie in
+        # the cutoff; the term is evaluated on that sub-block alone
+        ri = np.nonzero(inside(ca - p))[0]
+        ci = np.nonzero(inside(p - cb))[0]
+        if len(ri) == 0 or len(ci) == 0:
             continue
-        Gp = (Gj[np.ix_(rows, al)] * lamC[al][None, :]) @ Gj1[np.ix_(al, cols)]
-        I_out = np.broadcast_to(ca - q, ok.shape + (2,))
-        J_out = np.broadcast_to(q - cb, ok.shape + (2,))
-        ii = np.where(ok[..., None], i_in, 0)
-        jj = np.where(ok[..., None], j_in, 0)
-        ket = Uf[I_out[..., 0], J_out[..., 0], ii[..., 0], jj[..., 0]]
-        bra = Uf[I_out[..., 1], J_out[..., 1], ii[..., 1], jj[..., 1]]
-        Th += np.where(ok, ket * np.conj(bra) * Gp, 0.0)
+        al = np.nonzero(np.all(cC == p, axis=1))[0]
+        Gp = (Gj[np.ix_(rows[ri], al)] * lamC[al][None, :]) @ Gj1[np.ix_(al, cols[ci])]
+        a_ = ca[ri][:, None, :]         # (r', 1, 2)
+        b_ = cb[ci][None, :, :]         # (1, s', 2)
+        I_out = np.broadcast_to(a_ - q, (len(ri), len(ci), 2))
+        J_out = np.broadcast_to(q - b_, (len(ri), len(ci), 2))
+        i_in = np.broadcast_to(a_ - p, (len(ri), len(ci), 2))   # mode m before the gate
+        j_in = np.broadcast_to(p - b_, (len(ri), len(ci), 2))   # mode m+1 before the gate
+        ket = Uf[I_out[..., 0], J_out[..., 0], i_in[..., 0], j_in[..., 0]]
+        bra = Uf[I_out[..., 1], J_out[..., 1], i_in[..., 1], j_in[..., 1]]
+        Th[np.ix_(ri, ci)] += ket * np.conj(bra) * Gp
     return rows, cols, Th * lamL[rows][:, None] * lamR[cols][None, :]

@@ -61,3 +61,44 @@ def output_mode_moments(U: np.ndarray, r, eta: float):
     N = (np.abs(U) ** 2) @ n_in
     A = np.abs((U ** 2) @ m_in)
     return N, A
+
+
+def gaussian_rho(N: float, A: complex, d: int, K: int = 96) -> np.ndarray:
+    """Fock matrix [0, d)^2 of the zero-mean single-mode Gaussian state with
+    <a^dag a> = N and <a a> = A (complex), built as a squeezed thermal state
+    S(z) rho_th S(z)^dag in a K-level Fock space by matrix exponentials.
+
+    With S(z) = exp((conj(z) a^2 - z a^dag^2) / 2), z = t e^{i th}:
+    S^dag a S = a cosh t - a^dag e^{i th} sinh t, so for a thermal state of
+    mean n_th, with nu = n_th + 1/2:
+        <a^dag a> = nu cosh 2t - 1/2,   <a a> = -nu e^{i th} sinh 2t,
+    hence nu = sqrt((N + 1/2)^2 - |A|^2), cosh 2t = (N + 1/2) / nu and
+    e^{i th} = -A / |A|.  The levels used (n < d) are far from the K-level
+    edge, so the truncation of the exponential does not reach them.
+    """
+    from scipy.linalg import expm
+
+    nu = math.sqrt((N + 0.5) ** 2 - abs(A) ** 2)
+    nth = nu - 0.5
+    t = 0.5 * math.acosh(max((N + 0.5) / nu, 1.0))
+    eth = -A / abs(A) if abs(A) > 0 else 1.0
+    z = t * eth
+    a = np.diag(np.sqrt(np.arange(1, K)), 1).astype(complex)
+    ad = a.conj().T
+    S = expm(0.5 * (np.conj(z) * (a @ a) - z * (ad @ ad)))
+    x = nth / (nth + 1.0)
+    th = np.diag((1.0 - x) * x ** np.arange(K)).astype(complex)
+    rho = S @ th @ S.conj().T
+    return rho[:d, :d]
+
+
+def output_mode_coherences(U: np.ndarray, r, eta: float):
+    """<b_i^dag b_i> and the complex <b_i b_i> after loss then the
+    interferometer U (a_j^dag -> sum_i U[i, j] a_i^dag): with independent
+    inputs, U^dag b_i U = sum_j U[i, j] a_j gives <b_i b_i> = sum_j U[i, j]^2
+    <a_j a_j>, and <a a> = eta sinh r cosh r for the squeezed vacuum with
+    positive amplitudes thinned by the loss."""
+    r = np.asarray(r, dtype=float)
+    n_in = eta * np.sinh(r) ** 2
+    m_in = eta * np.sinh(r) * np.cosh(r)
+    return (np.abs(U) ** 2) @ n_in, (U ** 2) @ m_in
