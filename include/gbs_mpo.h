@@ -9,9 +9,9 @@
  * of M optical modes is held in U(1)-symmetric Vidal form (App. D, charged
  * MPS): site matrices Gamma_j (mode j, no physical index), Schmidt values
  * lam_b and photon-number charges c_b = (n, n') on bonds b = 0..M, where
- * c_b counts the ket and bra photons in modes b..M-1 (App. D, "particles to
- * the right").  Bond 0 is an auxiliary leg that carries the total photon
- * numbers ("the left-most charge is the sum of all photons", App. A).
+ * c_b counts the ket and bra photons in modes b..M-1 (App. D counts the
+ * photons on the right of a bond).  Bond 0 is an auxiliary leg that carries
+ * the total photon numbers (App. A).
  * Each mode has a per-mode Fock cutoff d (local index [0, d)^2, ket x bra).
  *
  * Conventions.
@@ -117,6 +117,34 @@ int mpo_entropy(gbs_mpo *h, double *S, double *S_max_so_far);
  * Synchronises the handle's stream.
  */
 int mpo_photon_marginals(gbs_mpo *h, double *P, double *trace);
+
+/*
+ * Renyi-alpha operator entropies S_b = log2(sum p^alpha) / (1 - alpha) of the
+ * same normalised spectra p = lam^2 / sum lam^2 as mpo_entropy (Sec. III.B and
+ * App. B: Renyi entropies of the vectorised state), on bonds b = 1..M-1, in
+ * bits.  alpha >= 0; alpha = 1 gives the EE, alpha = 0 log2 of the bond size.
+ * S: host array [M-1].  Synchronises.
+ */
+int mpo_renyi(gbs_mpo *h, double alpha, double *S);
+
+/*
+ * Asymptotic estimate of the operator EE from a single input mode (App. C;
+ * no device state needed).  A squeezed vacuum of squeezing r with loss
+ * transmission mu, both the state and the Kraus operators on photon numbers
+ * 0..n_max, is split by the basis transform of App. B (Eq. transform) with
+ * cos(theta) on the up side and sin(theta) on the down side (App. C:
+ * theta = pi/4 for the middle cut of a large Haar interferometer); the
+ * entropy (alpha = 1) or Renyi-alpha entropy of the vectorised output
+ * operator across the up/down cut, times n_inputs, is written to *S (bits).
+ *   0 <= r <= 20, 0 < mu <= 1, 1 <= n_max <= 31, n_inputs >= 0, alpha >= 0
+ *   spectrum (nullable) host [(n_max+1)^2]: the normalised eigenvalues of the
+ *            reduced operator (unsorted)
+ * Runs one workgroup on the current device (its own stream, synchronised;
+ * temporary device buffers of 8 (n_max+1)^4 bytes).  MPO_ENUMERIC if its
+ * Jacobi SVD does not converge.
+ */
+int gbs_asymptotic_ee(double r, double mu, int n_max, double theta, int n_inputs, double alpha,
+                      double *S, double *spectrum);
 
 /* Waits for the handle's queued work; returns a latched device error if any. */
 int mpo_sync(gbs_mpo *h);
@@ -236,6 +264,14 @@ int mpo_engine_result(gbs_engine *e, int id, int *done, double *S_max, double *t
 
 /* Forgets a retired simulation (MPO_EBUSY while it runs). */
 int mpo_engine_release(gbs_engine *e, int id);
+
+/* Failure injection for tests of failure isolation: lowers the Jacobi sweep
+ * limit (normally 60) of every block SVD of one running simulation to
+ * max_sweeps in [1, 60].  A block that has not converged within it latches
+ * MPO_ENUMERIC on that simulation only (every kernel still exits normally);
+ * the engine retires it with that error at the end of the step, and the other
+ * simulations of the batch are unaffected.  Takes effect at the next step. */
+int mpo_engine_set_sweep_limit(gbs_engine *e, int id, int max_sweeps);
 
 /* Phase profiling of the engine's steps (same layout as mpo_get_profile). */
 int mpo_engine_set_profiling(gbs_engine *e, int enable);

@@ -10,8 +10,8 @@ the vectorised density operator |rho>> = sum rho[k, k'] |k, k'> is written as
 
 with site tensors G_j[a, m, m', b] (a on bond j, b on bond j+1, ket m, bra m')
 and Schmidt values lam_b on bonds b = 0..M.  Bond 0 is an auxiliary left leg
-whose index carries the total photon numbers, because "the left-most charge is
-the sum of all photons" (App. A); the physical state is the sum over that leg.
+whose index carries the total photon numbers (App. A: the charge of the
+leftmost bond counts every photon); the physical state is the sum over that leg.
 Charges c_b = (photons, photons') to the right of bond b (App. D) are carried
 only as labels: every tensor here is dense and every contraction and SVD runs
 on the full dense matrices.
@@ -341,6 +341,21 @@ class DenseMPO:
             p = p / p.sum()
             p = p[p > 0]
             out.append(float(-(p * np.log2(p)).sum()))
+        return np.array(out)
+
+    def renyi(self, alpha: float):
+        """Renyi-alpha operator entropies on bonds 1..M-1, in bits, of the same
+        normalised spectra p = lam^2 / sum lam^2 (Sec. III.B, App. B):
+        log2(sum p^alpha) / (1 - alpha); alpha = 1 is the EE above."""
+        out = []
+        for b in range(1, self.M):
+            p = self.lam[b] ** 2
+            p = p / p.sum()
+            p = p[p > 0]
+            if alpha == 1.0:
+                out.append(float(-(p * np.log2(p)).sum()))
+            else:
+                out.append(float(math.log2((p ** alpha).sum()) / (1.0 - alpha)))
         return np.array(out)
 
     def marginals(self):

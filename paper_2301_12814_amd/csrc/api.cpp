@@ -372,6 +372,7 @@ int instance_create(Engine &E, int slot, int M, const double *r, double eta, int
   st.M = M;
   st.d = d;
   st.chi = chi;
+  st.max_sweeps = JACOBI_MAX_SWEEPS;
   HIPCHK(ialloc(I, &st.gam, (size_t)M * chi * chi));
   HIPCHK(ialloc(I, &st.lam, (size_t)(M + 1) * chi));
   HIPCHK(ialloc(I, &st.chg, (size_t)(M + 1) * chi));
@@ -675,8 +676,8 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
         // counted every 16 launches
         HIPCHK(launch_svd_big_prep(C, E.stream));
         const int tmax = svd_max_steps(C);
-        auto check = [&](int last) -> int {
-          HIPCHK(launch_svd_count(C, last, E.stream));
+        auto check = [&](int last, int next_step) -> int {
+          HIPCHK(launch_svd_count(C, last, next_step, E.stream));
           HIPCHK(hipMemcpyAsync(E.h_small + 2, E.d_active.p, 2 * sizeof(int),
                                 hipMemcpyDeviceToHost, E.stream));
           HIPCHK(hipStreamSynchronize(E.stream));
@@ -684,14 +685,14 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
           C.ntask = E.h_small[3];
           return MPO_OK;
         };
-        int crc = check(0);
+        int crc = check(0, 0);
         if (crc != MPO_OK) return crc;
         for (int t = 0; t < tmax && C.nact > 0; ++t) {
           HIPCHK(launch_svd_panel_step(C, t, E.stream));
           sweeps_run = t + 1;
           const bool last = t == tmax - 1;
           if ((t & 15) == 15 || last) {
-            crc = check(last ? 1 : 0);
+            crc = check(last ? 1 : 0, t + 1);
             if (crc != MPO_OK) return crc;
           }
         }
@@ -893,6 +894,61 @@ extern "C" int mpo_photon_marginals(gbs_mpo *h, double *P, double *trace) {
   int rc = sync_and_check(h->eng);
   if (rc != MPO_OK) return rc;
   return readout_marginals(h->eng, h->eng.inst[h->slot], P, trace);
+}
+
+extern "C" int mpo_renyi(gbs_mpo *h, double alpha, double *S) {
+  if (!h || !S) return fail(MPO_EINVAL, "NULL argument");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(MPO_EINVAL, "alpha must be finite and >= 0");
+  int rc = sync_and_check(h->eng);
+  if (rc != MPO_OK) return rc;
+  Instance &I = h->eng.inst[h->slot];
+  const int M = I.st.M;
+  // the marginals' output buffer (M * d doubles) holds the M - 1 values
+  HIPCHK(launch_renyi(I.st, alpha, I.dP, h->eng.stream));
+  HIPCHK(hipMemcpyAsync(S, I.dP, sizeof(double) * (M - 1), hipMemcpyDeviceToHost, h->eng.stream));
+  HIPCHK(hipStreamSynchronize(h->eng.stream));
+  return MPO_OK;
+}
+
+extern "C" int gbs_asymptotic_ee(double r, double mu, int n_max, double theta, int n_inputs,
+                                 double alpha, double *S, double *spectrum) {
+  if (!S) return fail(MPO_EINVAL, "S is NULL");
+  if (!(r >= 0.0 && r <= 20.0)) return fail(MPO_EINVAL, "r must be in [0, 20]");
+  if (!(mu > 0.0 && mu <= 1.0)) return fail(MPO_EINVAL, "mu must be in (0, 1]");
+  if (n_max < 1 || n_max > 31) return fail(MPO_EINVAL, "n_max must be in [1, 31]");
+  if (n_inputs < 0) return fail(MPO_EINVAL, "n_inputs must be >= 0");
+  if (!std::isfinite(theta)) return fail(MPO_EINVAL, "theta must be finite");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(MPO_EINVAL, "alpha must be finite and >= 0");
+  const int D = (n_max + 1) * (n_max + 1);
+  double *X = nullptr, *spec = nullptr, *out = nullptr;
+  int *err = nullptr;
+  hipStream_t s = nullptr;
+  auto release = [&]() {
+    if (s) hipStreamSynchronize(s);
+    if (X) hipFree(X);
+    if (spec) hipFree(spec);
+    if (out) hipFree(out);
+    if (err) hipFree(err);
+    if (s) hipStreamDestroy(s);
+  };
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc((void **)&X, sizeof(double) * (size_t)D * D);
+  if (e == hipSuccess) e = hipMalloc((void **)&spec, sizeof(double) * D);
+  if (e == hipSuccess) e = hipMalloc((void **)&out, sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void **)&err, sizeof(int));
+  if (e == hipSuccess) e = hipMemsetAsync(err, 0, sizeof(int), s);
+  if (e == hipSuccess) e = launch_asym(r, mu, n_max, theta, n_inputs, alpha, X, spec, out, err, s);
+  int herr = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(S, out, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && spectrum)
+    e = hipMemcpyAsync(spectrum, spec, sizeof(double) * D, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  release();
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? MPO_ENOMEM : MPO_EDEVICE, hipGetErrorString(e));
+  if (herr) return fail(MPO_ENUMERIC, err_text(herr));
+  return MPO_OK;
 }
 
 extern "C" int mpo_get_bond(gbs_mpo *h, int b, int *dim, double *lam, int *charges) {
@@ -1155,6 +1211,21 @@ extern "C" int mpo_engine_release(gbs_engine *e, int id) {
     if (I.id != id) continue;
     if (I.live) return fail(MPO_EBUSY, "simulation still running");
     I = Instance();
+    return MPO_OK;
+  }
+  return fail(MPO_EINVAL, "unknown simulation id");
+}
+
+extern "C" int mpo_engine_set_sweep_limit(gbs_engine *e, int id, int max_sweeps) {
+  if (!e) return fail(MPO_EINVAL, "engine is NULL");
+  if (max_sweeps < 1 || max_sweeps > JACOBI_MAX_SWEEPS)
+    return fail(MPO_EINVAL, "sweep limit must be in [1, 60]");
+  Engine &E = e->eng;
+  for (auto &I : E.inst) {
+    if (I.id != id) continue;
+    if (!I.live || I.done) return fail(MPO_EINVAL, "simulation is not running");
+    I.st.max_sweeps = max_sweeps;
+    E.states_dirty = true;
     return MPO_OK;
   }
   return fail(MPO_EINVAL, "unknown simulation id");

@@ -1304,7 +1304,7 @@ hipError_t launch_qr(Layer ly, int max_chi, hipStream_t s) {
 //     each panel, later rounds only the cross pairs).
 // ----------------------------------------------------------------------------
 constexpr int SVD_THREADS = 512;
-constexpr int MAX_SWEEPS = 60;
+constexpr int MAX_SWEEPS = JACOBI_MAX_SWEEPS;
 constexpr int RPL = 8;          // column rows cached per lane (m <= 512)
 
 // Column pairs are rotated by groups of L lanes (L = 16: one DPP row, four
@@ -1654,8 +1654,9 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly, int lo, int
   __syncthreads();
   const double tol = jacobi_tol<T>(m), tiny = jacobi_floor<T>(m, f2 * sc * sc);
   int sweep = 0;
+  const int msw = min(MAX_SWEEPS, st.max_sweeps);
   if (n > 1) {
-    for (sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
+    for (sweep = 0; sweep < msw; ++sweep) {
       if (threadIdx.x == 0) s_rot = 0;
       column_norms(sA, m, n, sig);
       int rot = 0;
@@ -1666,7 +1667,7 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly, int lo, int
       __syncthreads();
       if (!any) break;
     }
-    if (sweep == MAX_SWEEPS && threadIdx.x == 0) atomicOr(st.err, ERR_SVD_NOT_CONVERGED);
+    if (sweep == msw && threadIdx.x == 0) atomicOr(st.err, ERR_SVD_NOT_CONVERGED);
   }
   if (!B.qr && charge_n(B.q) == charge_np(B.q) && ly.tot[g].sym) self_mirror_phase(ly, gp, B, sA);
   sort_values(st.err, sA, m, n, sig, ly.sv + gp.lst0 + B.svoff, ly.perm + gp.lst0 + B.svoff,
@@ -1724,7 +1725,7 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
   const int P = B.npan, Pp = P + (P & 1);
   if (kpair >= Pp / 2) return;
   const int sweep = step / (Pp - 1), round = step % (Pp - 1);
-  if (sweep >= MAX_SWEEPS) return;
+  if (sweep >= min(MAX_SWEEPS, ly.states[ly.gates[g].inst].max_sweeps)) return;
   int *rf = ly.rotf + 4 * (size_t)kbig;
   if (rf[3]) return;
   if (round == 0 && sweep > 0 && rf[(sweep - 1) % 3] == 0) {   // previous sweep: no rotation
@@ -1791,7 +1792,9 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
 // task_pre[i] = its first task (Pp / 2 panel pairs each), task_pre[n] = all
 // tasks; active[0] = blocks, active[1] = tasks.  With `last`, the simulations
 // owning a block that still rotates get their error latched (sweep limit).
-__global__ __launch_bounds__(1024) void k_big_count(Layer ly, int last) {
+// A block whose simulation has a lower sweep limit and has used it up by
+// launch `next_step` is retired here with its simulation's error latched.
+__global__ __launch_bounds__(1024) void k_big_count(Layer ly, int last, int next_step) {
   __shared__ int s_iscan[17];
   int nb = 0, nt = 0;
   for (int b0 = 0; b0 < ly.total_big; b0 += blockDim.x) {
@@ -1801,9 +1804,17 @@ __global__ __launch_bounds__(1024) void k_big_count(Layer ly, int last) {
       int g, bi;
       big_block_of(ly, k, g, bi);
       const BlkDesc &B = ly.blk[ly.gates[g].blk0 + bi];
-      act = 1;
-      tasks = (B.npan + (B.npan & 1)) / 2;
-      if (last) atomicOr(ly.states[ly.gates[g].inst].err, ERR_SVD_NOT_CONVERGED);
+      const State &st = ly.states[ly.gates[g].inst];
+      const int Pp = B.npan + (B.npan & 1);
+      const int msw = min(MAX_SWEEPS, st.max_sweeps);
+      if (msw < MAX_SWEEPS && next_step / (Pp > 1 ? Pp - 1 : 1) >= msw) {
+        ly.rotf[4 * (size_t)k + 3] = msw;
+        atomicOr(st.err, ERR_SVD_NOT_CONVERGED);
+      } else {
+        act = 1;
+        tasks = Pp / 2;
+        if (last) atomicOr(st.err, ERR_SVD_NOT_CONVERGED);
+      }
     }
     int tb, tt;
     const int pb = nb + block_exclusive_scan<int>(act, s_iscan, tb);
@@ -1929,8 +1940,8 @@ hipError_t launch_svd_panel_step(Layer ly, int step, hipStream_t s) {
 
 int svd_max_steps(Layer ly) { return MAX_SWEEPS * (ly.maxpp > 1 ? ly.maxpp - 1 : 1) + 1; }
 
-hipError_t launch_svd_count(Layer ly, int last, hipStream_t s) {
-  hipLaunchKernelGGL(k_big_count, dim3(1), dim3(1024), 0, s, ly, last);
+hipError_t launch_svd_count(Layer ly, int last, int next_step, hipStream_t s) {
+  hipLaunchKernelGGL(k_big_count, dim3(1), dim3(1024), 0, s, ly, last, next_step);
   return hipGetLastError();
 }
 

@@ -6,8 +6,8 @@
 //   k(m,l) = sqrt(binom(m+l, m) eta^m (1-eta)^l),
 // evaluated in an internal Fock space of nint levels, then cropped to [0,d)^2.
 //
-// Product state with the auxiliary total-charge leg (App. D charges, App. A
-// "left-most charge is the sum of all photons"): every bond has one Schmidt
+// Product state with the auxiliary total-charge leg (App. D charges; App. A:
+// the leftmost bond's charge counts every photon): every bond has one Schmidt
 // vector per right charge q, with
 //   lam_b[q] = A_b sqrt(w_b(q)),  A_b = prod_{j<b} ||rho_j||_F,
 //   w_b = |rho_b|^2 (*) w_{b+1}   (2-D convolution, w_M = delta_0),

@@ -10,6 +10,9 @@
 
 namespace gbs {
 
+// Sweep limit of the one-sided Jacobi of every block SVD.
+constexpr int JACOBI_MAX_SWEEPS = 60;
+
 // One beam splitter of a batched layer.
 struct GateParam {
   int site;        // acts on modes (site, site + 1)
@@ -76,6 +79,8 @@ struct State {
   double *ee;       // (M+1) operator EE per bond (bits)
   unsigned long long *ee_max;  // running max of EE (double bits)
   int *err;         // latched error bits
+  int max_sweeps;   // Jacobi sweep limit of this simulation (JACOBI_MAX_SWEEPS
+                    // unless lowered by the failure-injection hook)
 };
 
 // Workspace of one chunk of a batched layer: gates of one or many instances.
@@ -145,7 +150,7 @@ hipError_t launch_svd_big_prep(Layer ly, hipStream_t s);
 hipError_t launch_svd_panel_step(Layer ly, int step, hipStream_t s);
 int svd_max_steps(Layer ly);
 int panel_lds_bytes(int max_chi);
-hipError_t launch_svd_count(Layer ly, int last, hipStream_t s);
+hipError_t launch_svd_count(Layer ly, int last, int next_step, hipStream_t s);
 hipError_t launch_svd_big_finish(Layer ly, int sweeps_run, int max_chi, hipStream_t s);
 hipError_t launch_select(Layer ly, hipStream_t s);
 hipError_t launch_scatter(Layer ly, int max_chi, hipStream_t s);
@@ -155,6 +160,9 @@ void set_svd_route(int lds_limit_bytes, int qr_enable);
 
 // readouts
 hipError_t launch_entropy_all(State st, hipStream_t s);
+hipError_t launch_renyi(State st, double alpha, double *out, hipStream_t s);
+hipError_t launch_asym(double r, double mu, int nmax, double theta, int n_inputs, double alpha,
+                       double *X, double *spec, double *out, int *err, hipStream_t s);
 hipError_t launch_phases(State st, const double *phase, hipStream_t s);
 size_t marginals_scratch(int M, int d, int chi);   // doubles
 hipError_t launch_marginals(State st, cd *envL, cd *envR, double *part, double *P,

@@ -44,6 +44,9 @@ def lib() -> ctypes.CDLL:
         L.mpo_apply_phases.argtypes = [c_void_p, pd]
         L.mpo_entropy.argtypes = [c_void_p, pd, pd]
         L.mpo_photon_marginals.argtypes = [c_void_p, pd, pd]
+        L.mpo_renyi.argtypes = [c_void_p, c_double, pd]
+        L.gbs_asymptotic_ee.argtypes = [c_double, c_double, c_int, c_double, c_int, c_double,
+                                        pd, pd]
         L.mpo_sync.argtypes = [c_void_p]
         L.mpo_get_bond.argtypes = [c_void_p, c_int, pi, pd, pi]
         L.mpo_get_site.argtypes = [c_void_p, c_int, pd]
@@ -69,14 +72,16 @@ def lib() -> ctypes.CDLL:
         L.mpo_engine_step.argtypes = [c_void_p, pi]
         L.mpo_engine_result.argtypes = [c_void_p, c_int, pi, pd, pd, pd]
         L.mpo_engine_release.argtypes = [c_void_p, c_int]
+        L.mpo_engine_set_sweep_limit.argtypes = [c_void_p, c_int, c_int]
         L.mpo_engine_set_profiling.argtypes = [c_void_p, c_int]
         L.mpo_engine_get_profile.argtypes = [c_void_p, pd, pll, pd]
         for name in ("mpo_engine_create", "mpo_engine_add", "mpo_engine_step",
-                     "mpo_engine_result", "mpo_engine_release", "mpo_engine_set_profiling",
+                     "mpo_engine_result", "mpo_engine_release", "mpo_engine_set_sweep_limit",
+                     "mpo_engine_set_profiling",
                      "mpo_engine_get_profile"):
             getattr(L, name).restype = c_int
         for name in ("mpo_layer_blocks", "mpo_set_profiling", "mpo_get_profile", "mpo_init_lossy_squeezed", "mpo_apply_bs_layer", "mpo_apply_phases",
-                     "mpo_entropy", "mpo_photon_marginals", "mpo_sync", "mpo_get_bond",
+                     "mpo_entropy", "mpo_photon_marginals", "mpo_sync", "mpo_get_bond", "mpo_renyi", "gbs_asymptotic_ee",
                      "mpo_get_site", "mpo_layer_stats", "gbs_clements_decompose"):
             getattr(L, name).restype = c_int
         _lib = L
@@ -178,6 +183,12 @@ class MPO:
         _check(lib().mpo_photon_marginals(self._h, _dp(P), ctypes.byref(tr)))
         return P.reshape(self.M, self.d), tr.value
 
+    def renyi(self, alpha):
+        """Renyi-alpha operator entropies of bonds 1..M-1 (bits)."""
+        S = np.zeros(max(self.M - 1, 1))
+        _check(lib().mpo_renyi(self._h, float(alpha), _dp(S)))
+        return S[: self.M - 1]
+
     def bond(self, b):
         D = ctypes.c_int()
         lam = np.zeros(self.chi)
@@ -225,6 +236,16 @@ class MPO:
                                      _dp(work)))
         return (dict(zip(self.PHASES, ms.tolist())), dict(zip(self.PHASES, n.tolist())),
                 dict(svd_flops=work[0], elements=work[1], candidates=work[2], layers=work[3]))
+
+
+def asymptotic_ee(r, mu, n_max, n_inputs, alpha=1.0, theta=np.pi / 4):
+    """App. C single-mode estimate of the operator EE (or Renyi-alpha entropy)
+    times n_inputs; returns (S, normalised spectrum)."""
+    S = ctypes.c_double()
+    spec = np.zeros((int(n_max) + 1) ** 2)
+    _check(lib().gbs_asymptotic_ee(float(r), float(mu), int(n_max), float(theta), int(n_inputs),
+                                   float(alpha), ctypes.byref(S), _dp(spec)))
+    return S.value, spec
 
 
 def device_memory():
@@ -304,6 +325,10 @@ class Engine:
     def release(self, sid):
         _check(lib().mpo_engine_release(self._h, int(sid)))
         self.meta.pop(sid, None)
+
+    def set_sweep_limit(self, sid, max_sweeps):
+        """Failure injection: Jacobi sweep limit of one running simulation."""
+        _check(lib().mpo_engine_set_sweep_limit(self._h, int(sid), int(max_sweeps)))
 
     def set_profiling(self, on=True):
         _check(lib().mpo_engine_set_profiling(self._h, 1 if on else 0))
