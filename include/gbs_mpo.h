@@ -119,6 +119,20 @@ int mpo_entropy(gbs_mpo *h, double *S, double *S_max_so_far);
 int mpo_photon_marginals(gbs_mpo *h, double *P, double *trace);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as mpo_photon_marginals, computed by the same kernels, with every
+ * intermediate (trace environments, partial sums, raw marginals, trace) in a
+ * static device array of 16 MiB that the library holds on each GPU it runs on
+ * until the process ends.  Calls no hipMalloc / hipFree and no allocating
+ * library routine.  The state needs 2 (M+1) chi 16 + M d ceil(chi/4) 8 +
+ * M d 8 + 8 bytes (each part rounded up to 256); a larger state returns
+ * MPO_EINVAL.  All calls on one GPU share that array: calls that overlap on
+ * one GPU (from several threads or streams) race.  Synchronises.
+ */
+int mpo_photon_marginals_noalloc(gbs_mpo *h, double *P, double *trace);
+
+/*
  * Renyi-alpha operator entropies S_b = log2(sum p^alpha) / (1 - alpha) of the
  * same normalised spectra p = lam^2 / sum lam^2 as mpo_entropy (Sec. III.B and
  * App. B: Renyi entropies of the vectorised state), on bonds b = 1..M-1, in

@@ -828,6 +828,8 @@ extern "C" int mpo_init_lossy_squeezed(int M, const double *r, double eta, int d
     return fail(MPO_ENOMEM, "projected device memory exceeds the free HBM");
   gbs_mpo *h = new gbs_mpo();
   rc = engine_init(h->eng, hip_stream, precision, 0);
+  if (rc == MPO_OK && noalloc_scratch_init() != hipSuccess)
+    rc = fail(MPO_EDEVICE, "device address of the static scratch array not found");
   if (rc == MPO_OK) {
     h->slot = engine_reserve_slot(h->eng);
     if (h->slot < 0) rc = fail(MPO_ENOMEM, "state table allocation failed");
@@ -875,6 +877,29 @@ extern "C" int mpo_apply_phases(gbs_mpo *h, const double *phase) {
                         h->eng.stream));
   HIPCHK(launch_phases(I.st, I.dPhase, h->eng.stream));
   return sync_and_check(h->eng);
+}
+
+extern "C" int mpo_photon_marginals_noalloc(gbs_mpo *h, double *P, double *trace) {
+  if (!h || !P) return fail(MPO_EINVAL, "NULL argument");
+  const State &st = h->eng.inst[h->slot].st;
+  if (marginals_noalloc_bytes(st.M, st.d, st.chi) > NOALLOC_SCRATCH_BYTES)
+    return fail(MPO_EINVAL, "state too large for the static scratch array (needs " +
+                                std::to_string(marginals_noalloc_bytes(st.M, st.d, st.chi)) +
+                                " bytes, limit " + std::to_string(NOALLOC_SCRATCH_BYTES) + ")");
+  int rc = sync_and_check(h->eng);
+  if (rc != MPO_OK) return rc;
+  double *dP = nullptr, *dT = nullptr;
+  HIPCHK(launch_marginals_noalloc(st, &dP, &dT, h->eng.stream));
+  double tr = 0.0;
+  const int n = st.M * st.d;
+  HIPCHK(hipMemcpyAsync(P, dP, sizeof(double) * n, hipMemcpyDeviceToHost, h->eng.stream));
+  HIPCHK(hipMemcpyAsync(&tr, dT, sizeof(double), hipMemcpyDeviceToHost, h->eng.stream));
+  HIPCHK(hipStreamSynchronize(h->eng.stream));
+  if (!std::isfinite(tr)) return fail(MPO_ENUMERIC, "non-finite trace");
+  if (tr != 0.0)
+    for (int i = 0; i < n; ++i) P[i] /= tr;
+  if (trace) *trace = tr;
+  return MPO_OK;
 }
 
 extern "C" int mpo_sync(gbs_mpo *h) {

@@ -167,5 +167,12 @@ hipError_t launch_phases(State st, const double *phase, hipStream_t s);
 size_t marginals_scratch(int M, int d, int chi);   // doubles
 hipError_t launch_marginals(State st, cd *envL, cd *envR, double *part, double *P,
                             double *trace, hipStream_t s);
+// marginals on the library's static scratch array (no allocation)
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;
+size_t marginals_noalloc_bytes(int M, int d, int chi);
+hipError_t noalloc_scratch_init();    // once per device, with that device current
+// enqueues the marginal kernels on the scratch array; *P (M*d raw marginals)
+// and *trace receive the device addresses of the results inside it
+hipError_t launch_marginals_noalloc(State st, double **P, double **trace, hipStream_t s);
 
 }  // namespace gbs

@@ -10,6 +10,8 @@
 //   L_0 = 1,  L_{j+1}[b] = sum_a L_j[a] lam_j[a] Gamma_j[a, b],
 //   Tr rho = sum_a lam_0[a] E_0[a],
 //   Tr(rho Pi_{j,n}) = sum_{c_a - c_b = (n,n)} L_j[a] lam_j[a] Gamma_j[a,b] lam_{j+1}[b] E_{j+1}[b].
+#include <mutex>
+
 #include "internal.h"
 
 namespace gbs {
@@ -143,6 +145,78 @@ hipError_t launch_marginals(State st, cd *envL, cd *envR, double *part, double *
   hipLaunchKernelGGL(k_marg_reduce, dim3(st.M), dim3(64), 0, s, st, part, nx, P);
   hipLaunchKernelGGL(k_trace, dim3(1), dim3(256), 0, s, st, envR, trace);
   return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Marginals without allocation.  The trace environments, the per-workgroup
+// partial sums, the raw marginals and the trace live in one file-scope device
+// array of NOALLOC_SCRATCH_BYTES (each GPU holds its own copy until the
+// process ends).  Host code never passes the array's name to a kernel: its
+// device address is looked up once per device with hipGetSymbolAddress and
+// kept in g_scratch_ptr.  Every call on a device shares that device's array,
+// so calls that overlap on one GPU race.
+// ----------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
+
+size_t marginals_noalloc_bytes(int M, int d, int chi) {
+  const size_t env = align256(sizeof(cd) * (size_t)(M + 1) * chi);
+  const size_t part = align256(sizeof(double) * marginals_scratch(M, d, chi));
+  const size_t P = align256(sizeof(double) * (size_t)M * d);
+  return 2 * env + part + P + align256(sizeof(double));
+}
+
+hipError_t noalloc_scratch_init() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void *ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = ptr;
+  return hipSuccess;
+}
+
+hipError_t launch_marginals_noalloc(State st, double **P, double **trace, hipStream_t s) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  void *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    base = g_scratch_ptr[dev];
+  }
+  if (!base) {
+    e = noalloc_scratch_init();
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    base = g_scratch_ptr[dev];
+  }
+  if (marginals_noalloc_bytes(st.M, st.d, st.chi) > (size_t)NOALLOC_SCRATCH_BYTES)
+    return hipErrorInvalidValue;
+  unsigned char *p = static_cast<unsigned char *>(base);
+  const size_t env = align256(sizeof(cd) * (size_t)(st.M + 1) * st.chi);
+  cd *envL = reinterpret_cast<cd *>(p);
+  cd *envR = reinterpret_cast<cd *>(p + env);
+  double *part = reinterpret_cast<double *>(p + 2 * env);
+  double *dP = reinterpret_cast<double *>(
+      p + 2 * env + align256(sizeof(double) * marginals_scratch(st.M, st.d, st.chi)));
+  double *dT = reinterpret_cast<double *>(reinterpret_cast<unsigned char *>(dP) +
+                                          align256(sizeof(double) * (size_t)st.M * st.d));
+  *P = dP;
+  *trace = dT;
+  return launch_marginals(st, envL, envR, part, dP, dT, s);
 }
 
 // Output phase screen: Gamma_j[a, b] *= e^{i phase_j (m - m')}, (m, m') = c_a - c_b.

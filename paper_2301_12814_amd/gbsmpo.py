@@ -44,6 +44,7 @@ def lib() -> ctypes.CDLL:
         L.mpo_apply_phases.argtypes = [c_void_p, pd]
         L.mpo_entropy.argtypes = [c_void_p, pd, pd]
         L.mpo_photon_marginals.argtypes = [c_void_p, pd, pd]
+        L.mpo_photon_marginals_noalloc.argtypes = [c_void_p, pd, pd]
         L.mpo_renyi.argtypes = [c_void_p, c_double, pd]
         L.gbs_asymptotic_ee.argtypes = [c_double, c_double, c_int, c_double, c_int, c_double,
                                         pd, pd]
@@ -81,7 +82,8 @@ def lib() -> ctypes.CDLL:
                      "mpo_engine_get_profile"):
             getattr(L, name).restype = c_int
         for name in ("mpo_layer_blocks", "mpo_set_profiling", "mpo_get_profile", "mpo_init_lossy_squeezed", "mpo_apply_bs_layer", "mpo_apply_phases",
-                     "mpo_entropy", "mpo_photon_marginals", "mpo_sync", "mpo_get_bond", "mpo_renyi", "gbs_asymptotic_ee",
+                     "mpo_entropy", "mpo_photon_marginals", "mpo_photon_marginals_noalloc",
+                     "mpo_sync", "mpo_get_bond", "mpo_renyi", "gbs_asymptotic_ee",
                      "mpo_get_site", "mpo_layer_stats", "gbs_clements_decompose"):
             getattr(L, name).restype = c_int
         _lib = L
@@ -188,6 +190,14 @@ class MPO:
         S = np.zeros(max(self.M - 1, 1))
         _check(lib().mpo_renyi(self._h, float(alpha), _dp(S)))
         return S[: self.M - 1]
+
+    def marginals_noalloc(self):
+        """mpo_photon_marginals_noalloc: the marginals from the library's static
+        scratch array (no device allocation)."""
+        P = np.zeros(self.M * self.d)
+        tr = ctypes.c_double()
+        _check(lib().mpo_photon_marginals_noalloc(self._h, _dp(P), ctypes.byref(tr)))
+        return P.reshape(self.M, self.d), tr.value
 
     def bond(self, b):
         D = ctypes.c_int()
