@@ -160,6 +160,37 @@ int mpo_renyi(gbs_mpo *h, double alpha, double *S);
 int gbs_asymptotic_ee(double r, double mu, int n_max, double theta, int n_inputs, double alpha,
                       double *S, double *spectrum);
 
+/*
+ * Experiment drivers (App. A), host orchestration of the calls above.
+ *
+ * EE-saturation stop rule: the initial state (arguments as
+ * mpo_init_lossy_squeezed) is evolved through the Clements layers of U
+ * (U_reim as in gbs_clements_decompose) one layer at a time; after each layer
+ * the largest bond EE is read, and the run stops once it has not exceeded the
+ * best value so far by more than 1e-12 bits for `patience` consecutive layers
+ * (10 in App. A), or when the layers run out.  Outputs: layers applied, the
+ * maximum EE (bits) and the layer count at which it was reached, and the
+ * trace at the stop (nullable).
+ */
+int gbs_run_until_saturation(int M, const double *r, double eta, int d, int chi, int precision,
+                             const double *U_reim, int patience, int *layers_used,
+                             double *S_max, int *layer_of_max, double *trace);
+
+/*
+ * Fixed-accuracy bond-dimension search (App. A): the whole circuit of U is
+ * run at chi0, chi is doubled (capped at chi_max) while 1 - Tr rho exceeds
+ * `target`, then `refine` bisection runs between the last failing and the
+ * first passing chi narrow the estimate.  *chi_found = the smallest passing
+ * chi found (-1 if chi_max fails), *err_found = its 1 - Tr rho (or that of
+ * chi_max).  The first max_trials runs are listed in trial_chi / trial_err
+ * (host arrays, nullable when max_trials = 0), their count in *n_trials
+ * (nullable).
+ */
+int gbs_chi_search(int M, const double *r, double eta, int d, int precision,
+                   const double *U_reim, int chi0, int chi_max, double target, int refine,
+                   int *chi_found, double *err_found, int max_trials, int *n_trials,
+                   int *trial_chi, double *trial_err);
+
 /* Waits for the handle's queued work; returns a latched device error if any. */
 int mpo_sync(gbs_mpo *h);
 

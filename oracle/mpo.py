@@ -126,7 +126,11 @@ def _label_rows(Wh: np.ndarray, S: np.ndarray, col_charge: np.ndarray, V: np.nda
         uk, inv = np.unique(keys, return_inverse=True)
         acc = np.bincount(inv, weights=w, minlength=len(uk))
         best = int(np.argmax(acc))
-        if acc[best] < (1 - 1e-6) * tot:
+        # a dense SVD resolves a vector's charge only up to rounding of the
+        # largest value over the gap to its neighbours: for values near the
+        # rank cut (far below 1e-8 of the largest) the leading charge is the label
+        noisy = S[i] < 1e-8 * S[0] and acc[best] > 0.5 * tot
+        if acc[best] < (1 - 1e-6) * tot and not noisy:
             raise RuntimeError("charge labelling failed: vector is not charge-definite")
         col = np.nonzero(inv == best)[0][0]
         labels[i] = col_charge[col]

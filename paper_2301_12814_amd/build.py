@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgbsmpo.so")
 
-SOURCES = ["init.hip", "gate.hip", "readout.hip", "asymptotic.hip", "api.cpp", "clements.cpp"]
+SOURCES = ["init.hip", "gate.hip", "readout.hip", "asymptotic.hip", "api.cpp", "drivers.cpp",
+           "clements.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

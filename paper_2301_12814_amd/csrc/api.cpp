@@ -21,6 +21,8 @@ static int fail(int code, const std::string &msg) {
   return code;
 }
 
+int gbs::set_error(int code, const char *msg) { return fail(code, msg); }
+
 #define HIPCHK(x)                                                                     \
   do {                                                                                \
     hipError_t e_ = (x);                                                              \

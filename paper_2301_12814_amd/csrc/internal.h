@@ -10,6 +10,9 @@
 
 namespace gbs {
 
+// Sets the thread-local message returned by mpo_last_error; returns code.
+int set_error(int code, const char *msg);
+
 // Sweep limit of the one-sided Jacobi of every block SVD.
 constexpr int JACOBI_MAX_SWEEPS = 60;
 

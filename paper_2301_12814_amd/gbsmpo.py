@@ -48,6 +48,10 @@ def lib() -> ctypes.CDLL:
         L.mpo_renyi.argtypes = [c_void_p, c_double, pd]
         L.gbs_asymptotic_ee.argtypes = [c_double, c_double, c_int, c_double, c_int, c_double,
                                         pd, pd]
+        L.gbs_run_until_saturation.argtypes = [c_int, pd, c_double, c_int, c_int, c_int, pd, c_int,
+                                               pi, pd, pi, pd]
+        L.gbs_chi_search.argtypes = [c_int, pd, c_double, c_int, c_int, pd, c_int, c_int, c_double,
+                                     c_int, pi, pd, c_int, pi, pi, pd]
         L.mpo_sync.argtypes = [c_void_p]
         L.mpo_get_bond.argtypes = [c_void_p, c_int, pi, pd, pi]
         L.mpo_get_site.argtypes = [c_void_p, c_int, pd]
@@ -84,6 +88,7 @@ def lib() -> ctypes.CDLL:
         for name in ("mpo_layer_blocks", "mpo_set_profiling", "mpo_get_profile", "mpo_init_lossy_squeezed", "mpo_apply_bs_layer", "mpo_apply_phases",
                      "mpo_entropy", "mpo_photon_marginals", "mpo_photon_marginals_noalloc",
                      "mpo_sync", "mpo_get_bond", "mpo_renyi", "gbs_asymptotic_ee",
+                     "gbs_run_until_saturation", "gbs_chi_search",
                      "mpo_get_site", "mpo_layer_stats", "gbs_clements_decompose"):
             getattr(L, name).restype = c_int
         _lib = L
@@ -256,6 +261,40 @@ def asymptotic_ee(r, mu, n_max, n_inputs, alpha=1.0, theta=np.pi / 4):
     _check(lib().gbs_asymptotic_ee(float(r), float(mu), int(n_max), float(theta), int(n_inputs),
                                    float(alpha), ctypes.byref(S), _dp(spec)))
     return S.value, spec
+
+
+def _ure(U):
+    U = np.ascontiguousarray(U, dtype=complex)
+    return np.ascontiguousarray(np.stack([U.real, U.imag], axis=-1).reshape(-1))
+
+
+def run_until_saturation(M, r, eta, d, chi, U, patience=10, precision=MPO_FP64):
+    """App. A stop rule; returns (layers_used, S_max, layer_of_max, trace)."""
+    r = np.ascontiguousarray(np.broadcast_to(np.asarray(r, dtype=float), (M,)))
+    ure = _ure(U)
+    used, at = ctypes.c_int(), ctypes.c_int()
+    smax, tr = ctypes.c_double(), ctypes.c_double()
+    _check(lib().gbs_run_until_saturation(int(M), _dp(r), float(eta), int(d), int(chi),
+                                          int(precision), _dp(ure), int(patience),
+                                          ctypes.byref(used), ctypes.byref(smax),
+                                          ctypes.byref(at), ctypes.byref(tr)))
+    return used.value, smax.value, at.value, tr.value
+
+
+def chi_search(M, r, eta, d, U, chi0, chi_max, target, refine, precision=MPO_FP64,
+               max_trials=64):
+    """App. A bond-dimension search; returns (chi_found, error, [(chi, error)])."""
+    r = np.ascontiguousarray(np.broadcast_to(np.asarray(r, dtype=float), (M,)))
+    ure = _ure(U)
+    cf, ef, nt = ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
+    tc = np.zeros(max_trials, dtype=np.int32)
+    te = np.zeros(max_trials)
+    _check(lib().gbs_chi_search(int(M), _dp(r), float(eta), int(d), int(precision), _dp(ure),
+                                int(chi0), int(chi_max), float(target), int(refine),
+                                ctypes.byref(cf), ctypes.byref(ef), int(max_trials),
+                                ctypes.byref(nt), _ip(tc), _dp(te)))
+    n = min(nt.value, max_trials)
+    return cf.value, ef.value, list(zip(tc[:n].tolist(), te[:n].tolist()))
 
 
 def device_memory():
