@@ -83,6 +83,18 @@ int mpo_init_lossy_squeezed(int M, const double *r, double eta, int d, int chi,
                             int precision, void *hip_stream, gbs_mpo **out);
 
 /*
+ * Same, with the cutoff read as a cap on the TOTAL photon number (App. A: the
+ * leftmost charge counts every photon, and the cutoff d bounds it): the
+ * initial state is projected onto at most d - 1 photons in ket and in bra
+ * over all modes (exact Vidal form of the projection, then the top chi per
+ * bond).  Every bond charge then stays <= (d-1, d-1); the interferometer
+ * conserves photon number, so no gate leaks trace and 1 - Tr rho measures
+ * the bond truncation alone.  Arguments as above.
+ */
+int mpo_init_lossy_squeezed_total_cap(int M, const double *r, double eta, int d, int chi,
+                                      int precision, void *hip_stream, gbs_mpo **out);
+
+/*
  * One layer of disjoint nearest-neighbour beam splitters (App. D two-site
  * update with charge-blocked Theta(c), Eq. theta; per-sector SVD truncated to
  * chi; App. D.5 block SVD).  Gates must be disjoint: no two share a mode.
@@ -234,6 +246,17 @@ int mpo_set_profiling(gbs_mpo *h, int enable);
  *     [2] candidate singular values, [3] layers.
  */
 int mpo_get_profile(gbs_mpo *h, double *phase_ms, long long *phase_launches, double *work);
+
+/*
+ * Algorithmic work of the Theta contractions (App. D, Eq. theta) summed over
+ * the layers applied since profiling was enabled, in real flops: 8 per
+ * (a, alpha, b) term whose two local pairs c_a - c_alpha and c_alpha - c_b are
+ * valid, plus 8 m_ket m_bra (m_ket + m_bra) per (a, b) for the Fock weights
+ * applied factorised (m = valid splits of the two-mode photon number in ket /
+ * bra).  No padding and no Hermitian-mirror saving are counted.
+ * Synchronises.
+ */
+int mpo_get_contraction_work(gbs_mpo *h, double *flops);
 
 /*
  * Sector histogram of the last applied layer (synchronises; still answers

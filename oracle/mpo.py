@@ -155,25 +155,30 @@ class DenseMPO:
 
     # ---------------- initial state ----------------
     @classmethod
-    def product(cls, rhos, chi: int):
+    def product(cls, rhos, chi: int, total_cap: int | None = None):
         """Initial state by its definition: the exact Vidal form of the product
         rho_1 (x) ... (x) rho_M with the auxiliary total-charge leg, written
         out from the Schmidt decomposition of a product state on every bond
         (one Schmidt vector per right charge q), then the top-chi
         (mirror-pair rule) charges kept on every bond without re-canonicalising.
 
-        With A_b = prod_{i<b} ||rho_i||_F and w_b(q) the weight of charge q in
-        (x)_{i>=b} rho_i (2-D convolution of |rho_i|^2):
-        lam_b[q] = A_b sqrt(w_b(q)) and
-        G_j[q', m, m', q] = rho_j[m, m'] delta(q' = q + (m, m')) / (A_{j+1} sqrt(w_j(q'))).
-        ``product_by_sweeps`` obtains the same state by dense SVD sweeps.
+        With w_b(q) the weight of charge q in (x)_{i>=b} rho_i (2-D
+        convolution of |rho_i|^2) and V_b(q) the total weight of the left part
+        (aux leg and modes i < b) that goes with right charge q:
+        lam_b[q] = sqrt(w_b(q) V_b(q)) and
+        G_j[q', m, m', q] = rho_j[m, m'] delta(q' = q + (m, m')) / (sqrt(V_{j+1}(q)) sqrt(w_j(q'))).
+        Without a cap V_b(q) = prod_{i<b} ||rho_i||_F^2.  With ``total_cap``
+        = K (App. A reading in which the cutoff bounds the total photon
+        number: the aux charge, i.e. every photon, is at most K in ket and in
+        bra), the state is projected onto totals <= K and V_b(q) is the left
+        weight of charges p <= K - q.  ``product_by_sweeps`` obtains the same
+        state by dense SVD sweeps.
         """
         M = len(rhos)
         d = rhos[0].shape[0]
-        A = [1.0]
-        for j in range(M):
-            A.append(A[-1] * float(np.linalg.norm(rhos[j])))
-        bonds = product_bonds(rhos, chi)
+        w = _weights(rhos)
+        V = _left_weights(rhos, total_cap)
+        bonds = product_bonds(rhos, chi, total_cap)
         charge = [bd[0] for bd in bonds]
         lam = [bd[1] for bd in bonds]
         G = []
@@ -181,18 +186,19 @@ class DenseMPO:
             idx = {tuple(q): i for i, q in enumerate(charge[j])}
             T = np.zeros((len(charge[j]), d, d, len(charge[j + 1])), dtype=complex)
             for qi, q in enumerate(charge[j + 1]):
+                vq = V[j + 1](int(q[0]), int(q[1]))
                 for m in range(d):
                     for mp in range(d):
                         key = (int(q[0]) + m, int(q[1]) + mp)
                         if rhos[j][m, mp] != 0 and key in idx:
                             a = idx[key]
-                            wq = (lam[j][a] / A[j]) ** 2
-                            T[a, m, mp, qi] = rhos[j][m, mp] / (A[j + 1] * math.sqrt(wq))
+                            T[a, m, mp, qi] = rhos[j][m, mp] / (math.sqrt(vq) *
+                                                                math.sqrt(w[j][key]))
             G.append(T)
         return cls(G, lam, charge, d)
 
     @classmethod
-    def product_by_sweeps(cls, rhos, chi: int):
+    def product_by_sweeps(cls, rhos, chi: int, total_cap: int | None = None):
         """Vidal form of rho_1 (x) ... (x) rho_M by dense sweeps, then the top-chi
         (mirror-pair rule) charges kept on every bond, without re-canonicalising.
         Small sizes only: the dense SVD cannot resolve the vectors of Schmidt
@@ -201,7 +207,9 @@ class DenseMPO:
         The charge-bond tensor B_j[q', m, m', q] = rho_j[m, m'] delta(q' = q + (m, m'))
         is the U(1) product MPO (App. D, the delta form of the MPS); the
         sweeps (QR left to right, SVD right to left) bring it to Vidal form
-        exactly as for any MPS (App. D, Eq. MPS in Vidal form).
+        exactly as for any MPS (App. D, Eq. MPS in Vidal form).  With
+        ``total_cap`` = K the auxiliary leg keeps only totals <= K in ket and
+        bra (projection of the state onto at most K photons).
         """
         M = len(rhos)
         d = rhos[0].shape[0]
@@ -215,6 +223,8 @@ class DenseMPO:
                 for (m, mp) in nz:
                     s.add((q[0] + int(m), q[1] + int(mp)))
             ch[b] = sorted(s)
+        if total_cap is not None:
+            ch[0] = [q for q in ch[0] if q[0] <= total_cap and q[1] <= total_cap]
         index = [{q: i for i, q in enumerate(c)} for c in ch]
         B = []
         for j in range(M):
@@ -222,8 +232,9 @@ class DenseMPO:
             for qi, q in enumerate(ch[j + 1]):
                 for m in range(d):
                     for mp in range(d):
-                        if rhos[j][m, mp] != 0:
-                            T[index[j][(q[0] + m, q[1] + mp)], m, mp, qi] = rhos[j][m, mp]
+                        key = (q[0] + m, q[1] + mp)
+                        if rhos[j][m, mp] != 0 and key in index[j]:
+                            T[index[j][key], m, mp, qi] = rhos[j][m, mp]
             B.append(T)
         # left-canonicalise; bond 0 is an open leg (the auxiliary total charge)
         A = [t.copy() for t in B]
@@ -418,28 +429,62 @@ def _weights(rhos):
     return w
 
 
-def product_lambdas(rhos):
-    """Closed form of the untruncated product-state Schmidt values with the
-    auxiliary leg: lam_b[q]^2 = (prod_{j<b} ||rho_j||_F^2) * w_b(q) where w_b is
-    the 2-D convolution of |rho_j|^2 over modes j >= b (App. D charges; the
-    Schmidt decomposition of a product state has one vector per right charge).
-    Returns per bond a dict {q: lam} over the charges with w_b(q) > 0."""
+def _left_weights(rhos, total_cap):
+    """Per bond b a function V_b(q): the squared norm of the left part that
+    goes with right charge q.  Without a cap it is prod_{j<b} ||rho_j||_F^2.
+    With a total cap K the aux charge Q = p + q (p = photons of modes j < b)
+    must stay <= K, so V_b(q) = sum_{p <= K - q} u_b(p), u_b the 2-D
+    convolution of |rho_j|^2 over j < b (u_0 = delta_0); 0 if q exceeds K."""
     M = len(rhos)
-    w = _weights(rhos)
+    if total_cap is None:
+        out, A2 = [], 1.0
+        for b in range(M + 1):
+            out.append(lambda q0, q1, A2=A2: A2)
+            if b < M:
+                A2 *= float((np.abs(rhos[b]) ** 2).sum())
+        return out
+    K = total_cap
+    d = rhos[0].shape[0]
+    u = np.zeros((K + 1, K + 1))
+    u[0, 0] = 1.0
     out = []
-    A2 = 1.0
     for b in range(M + 1):
-        nz = np.argwhere(w[b] > 0)
-        out.append({(int(q0), int(q1)): math.sqrt(A2 * w[b][q0, q1]) for q0, q1 in nz})
+        cum = np.cumsum(np.cumsum(u, axis=0), axis=1)
+        out.append(lambda q0, q1, cum=cum: float(cum[K - q0, K - q1])
+                   if 0 <= q0 <= K and 0 <= q1 <= K else 0.0)
         if b < M:
-            A2 *= float((np.abs(rhos[b]) ** 2).sum())
+            nu = np.zeros_like(u)
+            a2 = np.abs(rhos[b]) ** 2
+            for m in range(min(d, K + 1)):
+                for mp in range(min(d, K + 1)):
+                    nu[m:, mp:] += a2[m, mp] * u[: K + 1 - m, : K + 1 - mp]
+            u = nu
     return out
 
 
-def product_bonds(rhos, chi: int):
+def product_lambdas(rhos, total_cap: int | None = None):
+    """Closed form of the untruncated product-state Schmidt values with the
+    auxiliary leg: lam_b[q]^2 = w_b(q) V_b(q), w_b the 2-D convolution of
+    |rho_j|^2 over modes j >= b and V_b the left weight (``_left_weights``;
+    App. D charges: the Schmidt decomposition of a product state has one
+    vector per right charge).  Returns per bond a dict {q: lam} over the
+    charges with a positive value."""
+    M = len(rhos)
+    w = _weights(rhos)
+    V = _left_weights(rhos, total_cap)
+    out = []
+    for b in range(M + 1):
+        nz = np.argwhere(w[b] > 0)
+        vals = {(int(q0), int(q1)): math.sqrt(V[b](int(q0), int(q1)) * w[b][q0, q1])
+                for q0, q1 in nz}
+        out.append({q: v for q, v in vals.items() if v > 0})
+    return out
+
+
+def product_bonds(rhos, chi: int, total_cap: int | None = None):
     """Bond charges and Schmidt values of the initial state after the top-chi
     (mirror-pair rule) truncation of every bond, without building tensors."""
-    lam_d = product_lambdas(rhos)
+    lam_d = product_lambdas(rhos, total_cap)
     out = []
     for ld in lam_d:
         ch = np.array(sorted(ld.keys()), dtype=int).reshape(-1, 2)

@@ -146,6 +146,7 @@ struct Engine {
   double ph_ms[NPH] = {};
   long long ph_n[NPH] = {};
   double work[4] = {};
+  double contr_flops = 0.0;        // algorithmic contraction flops while profiling
   long long stats[6] = {0, 0, 0, 0, 0, -1};
   std::vector<BlkDesc> last_blk;   // sector histogram of the last layer (single chunk)
   std::vector<int> last_blk_gate;
@@ -365,8 +366,10 @@ int engine_reserve_slot(Engine &E) {
   return (int)n - 1;
 }
 
-// Allocates and builds the initial state of a new simulation in `slot`.
-int instance_create(Engine &E, int slot, int M, const double *r, double eta, int d, int chi) {
+// Allocates and builds the initial state of a new simulation in `slot`
+// (total_cap >= 0: projected onto at most total_cap photons in ket and bra).
+int instance_create(Engine &E, int slot, int M, const double *r, double eta, int d, int chi,
+                    int total_cap = -1) {
   Instance &I = E.inst[slot];
   I = Instance();
   I.live = true;
@@ -404,7 +407,7 @@ int instance_create(Engine &E, int slot, int M, const double *r, double eta, int
   woff[M + 1] = acc;
   const long long W0 = (long long)M * (d - 1) + 1;
   const long long ucap = W0 * W0;
-  double *d_r = nullptr, *d_rho = nullptr, *d_A = nullptr, *d_w = nullptr;
+  double *d_r = nullptr, *d_rho = nullptr, *d_A = nullptr, *d_w = nullptr, *d_V = nullptr;
   int *d_nint = nullptr, *d_us = nullptr;
   long long *d_woff = nullptr;
   unsigned long long *d_uv = nullptr, *d_uk = nullptr;
@@ -429,6 +432,7 @@ int instance_create(Engine &E, int slot, int M, const double *r, double eta, int
   TALLOC(d_uv, (size_t)ucap * (M + 1));
   TALLOC(d_uk, (size_t)ucap * (M + 1));
   TALLOC(d_us, (size_t)ucap * (M + 1));
+  if (total_cap >= 0) TALLOC(d_V, (size_t)(M + 1) * (total_cap + 1) * (total_cap + 1));
 #undef TALLOC
   if (e != hipSuccess) {
     cleanup();
@@ -448,8 +452,11 @@ int instance_create(Engine &E, int slot, int M, const double *r, double eta, int
   if (e == hipSuccess) e = launch_init_norms(d_rho, M, d, d_A, E.stream);
   for (int b = M - 1; b >= 0 && e == hipSuccess; --b)
     e = launch_init_conv(d_rho, M, d, b, d_woff, d_w, E.stream);
-  if (e == hipSuccess) e = launch_init_select(st, d_w, d_woff, d_A, d_uv, d_uk, d_us, ucap, E.stream);
-  if (e == hipSuccess) e = launch_init_gamma(st, d_rho, d_A, E.stream);
+  if (e == hipSuccess && total_cap >= 0)
+    e = launch_init_left(d_rho, M, d, total_cap, d_V, E.stream);
+  if (e == hipSuccess)
+    e = launch_init_select(st, d_w, d_woff, d_A, d_uv, d_uk, d_us, ucap, d_V, total_cap, E.stream);
+  if (e == hipSuccess) e = launch_init_gamma(st, d_rho, d_A, d_V, total_cap, E.stream);
   if (e == hipSuccess) e = launch_entropy_all(st, E.stream);
   cleanup();
   if (e != hipSuccess) return fail(MPO_EDEVICE, hipGetErrorString(e));
@@ -548,7 +555,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
   rc = sync_and_check(E, check_instances);
   if (rc != MPO_OK) return rc;
   long long st_blk = 0, st_el = 0, st_sv = 0, st_mr = 0, st_mc = 0, st_sw = 0;
-  double st_fl = 0.0;
+  double st_fl = 0.0, st_cf = 0.0;
   for (int g = 0; g < n; ++g) {
     const GateTot &t = E.h_tot[g];
     st_blk += t.nblk;
@@ -557,12 +564,14 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     st_mr = std::max<long long>(st_mr, t.maxr);
     st_mc = std::max<long long>(st_mc, t.maxc);
     st_fl += t.svd_flops;
+    st_cf += t.contr_flops;
   }
   if (E.prof) {
     E.work[0] += st_fl;
     E.work[1] += (double)st_el;
     E.work[2] += (double)st_sv;
     E.work[3] += 1.0;
+    E.contr_flops += st_cf;
   }
   // centre-bond run tables of every gate
   long long ct = 0;
@@ -818,8 +827,8 @@ extern "C" void mpo_free(gbs_mpo *h) {
   delete h;
 }
 
-extern "C" int mpo_init_lossy_squeezed(int M, const double *r, double eta, int d, int chi,
-                                       int precision, void *hip_stream, gbs_mpo **out) {
+static int init_handle(int M, const double *r, double eta, int d, int chi, int precision,
+                       void *hip_stream, gbs_mpo **out, int total_cap) {
   if (!out) return fail(MPO_EINVAL, "out is NULL");
   *out = nullptr;
   int rc = validate_args(M, r, eta, d, chi, precision);
@@ -836,7 +845,7 @@ extern "C" int mpo_init_lossy_squeezed(int M, const double *r, double eta, int d
     h->slot = engine_reserve_slot(h->eng);
     if (h->slot < 0) rc = fail(MPO_ENOMEM, "state table allocation failed");
   }
-  if (rc == MPO_OK) rc = instance_create(h->eng, h->slot, M, r, eta, d, chi);
+  if (rc == MPO_OK) rc = instance_create(h->eng, h->slot, M, r, eta, d, chi, total_cap);
   if (rc == MPO_OK) rc = upload_states(h->eng);
   if (rc == MPO_OK) rc = sync_and_check(h->eng);
   if (rc != MPO_OK) {
@@ -847,6 +856,17 @@ extern "C" int mpo_init_lossy_squeezed(int M, const double *r, double eta, int d
   h->eng.committed += h->eng.inst[h->slot].bytes;
   *out = h;
   return MPO_OK;
+}
+
+extern "C" int mpo_init_lossy_squeezed(int M, const double *r, double eta, int d, int chi,
+                                       int precision, void *hip_stream, gbs_mpo **out) {
+  return init_handle(M, r, eta, d, chi, precision, hip_stream, out, -1);
+}
+
+extern "C" int mpo_init_lossy_squeezed_total_cap(int M, const double *r, double eta, int d,
+                                                 int chi, int precision, void *hip_stream,
+                                                 gbs_mpo **out) {
+  return init_handle(M, r, eta, d, chi, precision, hip_stream, out, d - 1);
 }
 
 extern "C" int mpo_apply_bs_layer(gbs_mpo *h, int n_gates, const int *left_site,
@@ -1059,6 +1079,7 @@ static int set_profiling(Engine &E, int enable) {
     E.ph_n[p] = 0;
   }
   for (double &x : E.work) x = 0.0;
+  E.contr_flops = 0.0;
   return MPO_OK;
 }
 
@@ -1071,6 +1092,14 @@ static int get_profile(Engine &E, double *phase_ms, long long *phase_launches, d
   }
   if (work)
     for (int i = 0; i < 4; ++i) work[i] = E.work[i];
+  return MPO_OK;
+}
+
+extern "C" int mpo_get_contraction_work(gbs_mpo *h, double *flops) {
+  if (!h || !flops) return fail(MPO_EINVAL, "NULL argument");
+  int rc = sync_and_check(h->eng);
+  if (rc != MPO_OK) return rc;
+  *flops = h->eng.contr_flops;
   return MPO_OK;
 }
 

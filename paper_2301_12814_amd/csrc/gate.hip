@@ -303,13 +303,39 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
     }
   }
   if (!FILL) {
+    // algorithmic contraction work of the gate: 8 flops per (a, alpha, b)
+    // term of the centre-charge sums (c_a - c_alpha and c_alpha - c_b valid
+    // local pairs), plus the Fock weights applied factorised per (a, b):
+    // m_ket m_bra (m_ket + m_bra) complex MACs, m = valid splits of the
+    // two-mode photon number
+    double cf = 0.0;
+    {
+      const int DC = st.dim[j + 1];
+      const int *cC = st.chg + (size_t)(j + 1) * chi;
+      for (int al = threadIdx.x; al < DC; al += blockDim.x) {
+        const int p0 = charge_n(cC[al]), p1 = charge_np(cC[al]);
+        int nl = 0, nr = 0;
+        for (int n = p0; n <= p0 + d - 1; ++n) nl += count_window(cL, DL, n, p1, p1 + d - 1);
+        for (int n = max(p0 - d + 1, 0); n <= p0; ++n)
+          nr += count_window(cR, DR, n, p1 - d + 1, p1);
+        cf += 8.0 * nl * (double)nr;
+      }
+      for (long long idx = threadIdx.x; idx < (long long)DL * DR; idx += blockDim.x) {
+        const int a = (int)(idx / DR), b = (int)(idx % DR);
+        const int n0 = charge_n(cL[a]) - charge_n(cR[b]);
+        const int n1 = charge_np(cL[a]) - charge_np(cR[b]);
+        if (n0 < 0 || n1 < 0 || n0 > 2 * d - 2 || n1 > 2 * d - 2) continue;
+        const int mk = min(n0, 2 * d - 2 - n0) + 1, mb = min(n1, 2 * d - 2 - n1) + 1;
+        cf += 8.0 * mk * mb * (double)(mk + mb);
+      }
+    }
     // block-wide totals
     __shared__ long long s_nb, s_eb, s_re;
     __shared__ int s_sv, s_rb, s_cb, s_bg, s_mr, s_mc, s_pp;
-    __shared__ double s_fl;
+    __shared__ double s_fl, s_cf;
     if (threadIdx.x == 0) {
       s_nb = 0; s_eb = 0; s_re = 0; s_sv = 0; s_rb = 0; s_cb = 0; s_bg = 0; s_mr = 0; s_mc = 0;
-      s_pp = 0; s_fl = 0.0;
+      s_pp = 0; s_fl = 0.0; s_cf = 0.0;
     }
     __syncthreads();
     atomicAdd((unsigned long long *)&s_nb, (unsigned long long)nb);
@@ -323,6 +349,7 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
     atomicMax(&s_mc, maxc);
     atomicMax(&s_pp, maxpp);
     atomicAdd(&s_fl, fl);
+    atomicAdd(&s_cf, cf);
     __syncthreads();
     if (threadIdx.x == 0) {
       tot.nblk = (int)s_nb;
@@ -336,6 +363,7 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
       tot.nbig = s_bg;
       tot.maxpp = s_pp;
       tot.svd_flops = s_fl;
+      tot.contr_flops = s_cf;
       ly.tot[g] = tot;
     }
     return;

@@ -13,6 +13,14 @@
 //   w_b = |rho_b|^2 (*) w_{b+1}   (2-D convolution, w_M = delta_0),
 //   Gamma_j[q', q] = rho_j[q' - q] A_j / (A_{j+1} lam_j[q']).
 // Every bond keeps its top-chi charges under the mirror-pair rule.
+//
+// Total photon cap K (App. A reading in which the cutoff bounds the total
+// photon number): the state is projected onto at most K photons in ket and
+// in bra, i.e. the aux charge Q = p + q (p: photons left of the bond, q: right)
+// stays <= K.  The left factor A_b^2 becomes V_b(q) = sum_{p <= K - q} u_b(p),
+// u_b the 2-D convolution of |rho_j|^2 over j < b (u_0 = delta_0), so
+//   lam_b[q] = sqrt(w_b(q) V_b(q))  (q <= K),
+//   Gamma_j[q', q] = rho_j[q' - q] sqrt(V_j(q')) / (sqrt(V_{j+1}(q)) lam_j[q']).
 #include "blockops.h"
 #include "internal.h"
 
@@ -115,19 +123,78 @@ hipError_t launch_init_conv(const double *rho, int M, int d, int b, const long l
   return hipGetLastError();
 }
 
+// Left weights of the total cap K: V[b][x0][x1] = sum_{p <= (K - x0, K - x1)}
+// u_b(p) for every bond b, on the (K+1)^2 grid (indexed by x = K - q).  One
+// workgroup walks the bonds; each canonical cell (x0 <= x1) is computed once
+// and copied to its mirror, so mirror charges get bitwise equal values.
+__global__ __launch_bounds__(256) void k_init_left(const double *rho, int M, int d, int K,
+                                                   double *V) {
+  const int W = K + 1;
+  __shared__ double s_u[2][16 * 16];
+  for (int c = threadIdx.x; c < W * W; c += blockDim.x) s_u[0][c] = c == 0 ? 1.0 : 0.0;
+  __syncthreads();
+  for (int b = 0; b <= M; ++b) {
+    const double *u = s_u[b & 1];
+    double *Vb = V + (size_t)b * W * W;
+    for (int c = threadIdx.x; c < W * W; c += blockDim.x) {
+      const int x0 = c / W, x1 = c % W;
+      if (x0 > x1) continue;
+      // q = (K - x0, K - x1); admissible left charges p <= (x0, x1)
+      double acc = 0.0;
+      for (int p0 = 0; p0 <= x0; ++p0)
+        for (int p1 = 0; p1 <= x1; ++p1) acc += u[p0 * W + p1];
+      Vb[x0 * W + x1] = acc;
+      Vb[x1 * W + x0] = acc;
+    }
+    if (b == M) break;
+    double *un = s_u[(b + 1) & 1];
+    const double *rb = rho + (size_t)b * d * d;
+    for (int c = threadIdx.x; c < W * W; c += blockDim.x) {
+      const int p0 = c / W, p1 = c % W;
+      if (p0 > p1) continue;
+      double acc = 0.0;
+      for (int m = 0; m < d && m <= p0; ++m)
+        for (int mp = 0; mp < d && mp <= p1; ++mp) {
+          const double x = rb[m * d + mp];
+          acc = fma(u[(p0 - m) * W + (p1 - mp)], x * x, acc);
+        }
+      un[p0 * W + p1] = acc;
+      un[p1 * W + p0] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_init_left(const double *rho, int M, int d, int K, double *V, hipStream_t s) {
+  if (K < 0 || K > 15) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_init_left, dim3(1), dim3(256), 0, s, rho, M, d, K, V);
+  return hipGetLastError();
+}
+
+// Schmidt value of cell c = (q0, q1) of bond b: A_b sqrt(w_b(q)) without a
+// cap, sqrt(w_b(q) V_b(q)) with the total cap K (0 above the cap).
+__device__ inline double init_value(const double *wb, long long c, int Wb, double Ab,
+                                    const double *Vb, int K) {
+  if (K < 0) return Ab * sqrt(wb[c]);
+  const int q0 = (int)(c / Wb), q1 = (int)(c % Wb);
+  if (q0 > K || q1 > K) return 0.0;
+  return sqrt(wb[c] * Vb[(K - q0) * (K + 1) + (K - q1)]);
+}
+
 // One workgroup per bond: keep the top-chi charges (mirror-pair rule) and
 // write the sorted bond.  Units are the canonical cells q0 <= q1.
 __global__ __launch_bounds__(1024) void k_init_select(State st, const double *w,
                                                       const long long *woff, const double *A,
                                                       unsigned long long *uval,
                                                       unsigned long long *ukey, int *usize,
-                                                      long long ucap) {
+                                                      long long ucap, const double *V, int K) {
   const int b = blockIdx.x;
   const int M = st.M, d = st.d, chi = st.chi;
   const int Wb = (M - b) * (d - 1) + 1;
   const long long ncell = (long long)Wb * Wb;
   const double *wb = w + woff[b];
   const double Ab = A[b];
+  const double *Vb = K >= 0 ? V + (size_t)b * (K + 1) * (K + 1) : nullptr;
   unsigned long long *uv = uval + (long long)b * ucap;
   unsigned long long *uk = ukey + (long long)b * ucap;
   int *us = usize + (long long)b * ucap;
@@ -135,8 +202,8 @@ __global__ __launch_bounds__(1024) void k_init_select(State st, const double *w,
   __shared__ long long s_scan[17];
   // largest Schmidt value of the bond
   double lmax = 0.0;
-  for (long long c = threadIdx.x; c < ncell; c += blockDim.x) lmax = fmax(lmax, wb[c]);
-  lmax = Ab * sqrt(lmax);
+  for (long long c = threadIdx.x; c < ncell; c += blockDim.x)
+    lmax = fmax(lmax, init_value(wb, c, Wb, Ab, Vb, K));
   if (threadIdx.x == 0) s_max = 0.0;
   __syncthreads();
   atomicMax((unsigned long long *)&s_max, (unsigned long long)__double_as_longlong(lmax));
@@ -153,8 +220,8 @@ __global__ __launch_bounds__(1024) void k_init_select(State st, const double *w,
       q0 = (int)(c / Wb);
       q1 = (int)(c % Wb);
       if (q0 <= q1) {
-        vq = Ab * sqrt(wb[c]);
-        vm = Ab * sqrt(wb[(long long)q1 * Wb + q0]);
+        vq = init_value(wb, c, Wb, Ab, Vb, K);
+        vm = init_value(wb, (long long)q1 * Wb + q0, Wb, Ab, Vb, K);
         const int sz = (vq >= cut && vq > 0.0) + ((q0 != q1) && vm >= cut && vm > 0.0);
         flag = sz > 0;
       }
@@ -186,10 +253,10 @@ __global__ __launch_bounds__(1024) void k_init_select(State st, const double *w,
     if (c < ncell) {
       q0 = (int)(c / Wb);
       q1 = (int)(c % Wb);
-      v = Ab * sqrt(wb[c]);
+      v = init_value(wb, c, Wb, Ab, Vb, K);
       if (v >= cut && v > 0.0) {
         const int c0m = min(q0, q1), c1m = max(q0, q1);
-        const double vo = Ab * sqrt(wb[(long long)q1 * Wb + q0]);
+        const double vo = init_value(wb, (long long)q1 * Wb + q0, Wb, Ab, Vb, K);
         const bool oko = (q0 != q1) && vo >= cut && vo > 0.0;
         const double uvv = fmax(v, oko ? vo : 0.0);
         const unsigned long long key = ((unsigned long long)(pack_charge(c0m, c1m) + 1) << 20);
@@ -215,15 +282,17 @@ __global__ __launch_bounds__(1024) void k_init_select(State st, const double *w,
 
 hipError_t launch_init_select(State st, const double *w, const long long *woff, const double *A,
                               unsigned long long *uval, unsigned long long *ukey, int *usize,
-                              long long ucap, hipStream_t s) {
+                              long long ucap, const double *V, int K, hipStream_t s) {
   hipLaunchKernelGGL(k_init_select, dim3(st.M + 1), dim3(1024), 0, s, st, w, woff, A, uval, ukey,
-                     usize, ucap);
+                     usize, ucap, V, K);
   return hipGetLastError();
 }
 
 // Gamma_j[a][b] = rho_j[c_a - c_b] A_j / (A_{j+1} lam_j[a]) when the charge
-// difference is a valid local pair, else 0 (padding included).
-__global__ void k_init_gamma(State st, const double *rho, const double *A) {
+// difference is a valid local pair, else 0 (padding included); with the total
+// cap K the factor A_j / A_{j+1} is sqrt(V_j(c_a)) / sqrt(V_{j+1}(c_b)).
+__global__ void k_init_gamma(State st, const double *rho, const double *A, const double *V,
+                             int K) {
   const int j = blockIdx.y;
   const int chi = st.chi, d = st.d;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -237,16 +306,25 @@ __global__ void k_init_gamma(State st, const double *rho, const double *A) {
     if (m >= 0 && m < d && mp >= 0 && mp < d) {
       const double x = rho[(size_t)j * d * d + m * d + mp];
       const double la = st.lam[(size_t)j * chi + a];
-      v.re = x * A[j] / (A[j + 1] * la);
+      if (K < 0) {
+        v.re = x * A[j] / (A[j + 1] * la);
+      } else {
+        const int W = K + 1;
+        const double va = V[(size_t)j * W * W + (K - charge_n(ca)) * W + (K - charge_np(ca))];
+        const double vb =
+            V[(size_t)(j + 1) * W * W + (K - charge_n(cb)) * W + (K - charge_np(cb))];
+        v.re = x * sqrt(va) / (sqrt(vb) * la);
+      }
     }
   }
   st.gam[(size_t)j * chi * chi + idx] = v;
 }
 
-hipError_t launch_init_gamma(State st, const double *rho, const double *A, hipStream_t s) {
+hipError_t launch_init_gamma(State st, const double *rho, const double *A, const double *V, int K,
+                             hipStream_t s) {
   const long long n = (long long)st.chi * st.chi;
   hipLaunchKernelGGL(k_init_gamma, dim3((unsigned)((n + 255) / 256), st.M), dim3(256), 0, s, st,
-                     rho, A);
+                     rho, A, V, K);
   return hipGetLastError();
 }
 

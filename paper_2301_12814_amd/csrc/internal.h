@@ -62,6 +62,8 @@ struct GateTot {
   long long relems;   // R factors of the QR'd blocks (sum of n^2)
   int c0lo, c0hi, c1hi;  // centre bond: range of n, largest n' (-1: empty bond)
   double svd_flops;   // sum over blocks of 16 m n^2 + 36 n^3 (complex SVD convention)
+  double contr_flops; // algorithmic Theta contraction flops of the gate (no padding,
+                      // no mirror saving): centre-charge sums + factorised Fock weights
 };
 
 // Per-gate global offsets (host -> device).
@@ -134,11 +136,14 @@ hipError_t launch_init_rho(const double *r, const int *nint, double eta, int M, 
 hipError_t launch_init_norms(const double *rho, int M, int d, double *A, hipStream_t s);
 hipError_t launch_init_conv(const double *rho, int M, int d, int b, const long long *woff,
                             double *w, hipStream_t s);
+// total photon cap K >= 0 (K < 0: none): left weights V (M+1) x (K+1)^2
+hipError_t launch_init_left(const double *rho, int M, int d, int K, double *V, hipStream_t s);
 hipError_t launch_init_select(State st, const double *w, const long long *woff,
                               const double *A, unsigned long long *uval,
                               unsigned long long *ukey, int *usize, long long ucap,
-                              hipStream_t s);
-hipError_t launch_init_gamma(State st, const double *rho, const double *A, hipStream_t s);
+                              const double *V, int K, hipStream_t s);
+hipError_t launch_init_gamma(State st, const double *rho, const double *A, const double *V, int K,
+                             hipStream_t s);
 
 // one batched layer (chunk)
 hipError_t launch_fock(Layer ly, hipStream_t s);

@@ -40,6 +40,7 @@ def lib() -> ctypes.CDLL:
         pll = ctypes.POINTER(ctypes.c_longlong)
         L.mpo_init_lossy_squeezed.argtypes = [c_int, pd, c_double, c_int, c_int, c_int, c_void_p,
                                               ctypes.POINTER(c_void_p)]
+        L.mpo_init_lossy_squeezed_total_cap.argtypes = L.mpo_init_lossy_squeezed.argtypes
         L.mpo_apply_bs_layer.argtypes = [c_void_p, c_int, pi, pd, pd]
         L.mpo_apply_phases.argtypes = [c_void_p, pd]
         L.mpo_entropy.argtypes = [c_void_p, pd, pd]
@@ -63,6 +64,7 @@ def lib() -> ctypes.CDLL:
         L.mpo_set_profiling.argtypes = [c_void_p, c_int]
         L.mpo_get_profile.argtypes = [c_void_p, pd, pll, pd]
         L.mpo_layer_blocks.argtypes = [c_void_p, c_int, pi]
+        L.mpo_get_contraction_work.argtypes = [c_void_p, pd]
         L.gbs_device_memory.argtypes = [pll, pll]
         L.gbs_device_memory.restype = c_int
         L.gbs_set_svd_route.argtypes = [c_int, c_int]
@@ -85,10 +87,11 @@ def lib() -> ctypes.CDLL:
                      "mpo_engine_set_profiling",
                      "mpo_engine_get_profile"):
             getattr(L, name).restype = c_int
-        for name in ("mpo_layer_blocks", "mpo_set_profiling", "mpo_get_profile", "mpo_init_lossy_squeezed", "mpo_apply_bs_layer", "mpo_apply_phases",
+        for name in ("mpo_layer_blocks", "mpo_set_profiling", "mpo_get_profile", "mpo_init_lossy_squeezed",
+                     "mpo_init_lossy_squeezed_total_cap", "mpo_apply_bs_layer", "mpo_apply_phases",
                      "mpo_entropy", "mpo_photon_marginals", "mpo_photon_marginals_noalloc",
                      "mpo_sync", "mpo_get_bond", "mpo_renyi", "gbs_asymptotic_ee",
-                     "gbs_run_until_saturation", "gbs_chi_search",
+                     "gbs_run_until_saturation", "gbs_chi_search", "mpo_get_contraction_work",
                      "mpo_get_site", "mpo_layer_stats", "gbs_clements_decompose"):
             getattr(L, name).restype = c_int
         _lib = L
@@ -142,12 +145,14 @@ def clements(U: np.ndarray):
 class MPO:
     """One simulation: lossy squeezed product state evolved by beam-splitter layers."""
 
-    def __init__(self, M, r, eta, d, chi, precision=MPO_FP64, stream=None):
+    def __init__(self, M, r, eta, d, chi, precision=MPO_FP64, stream=None, total_cap=False):
+        """total_cap: d bounds the total photon number (mpo_init_lossy_squeezed_total_cap)."""
         L = lib()
         r = np.ascontiguousarray(np.broadcast_to(np.asarray(r, dtype=float), (M,)))
         h = ctypes.c_void_p()
-        _check(L.mpo_init_lossy_squeezed(int(M), _dp(r), float(eta), int(d), int(chi),
-                                         int(precision), _stream_handle(stream), ctypes.byref(h)))
+        init = L.mpo_init_lossy_squeezed_total_cap if total_cap else L.mpo_init_lossy_squeezed
+        _check(init(int(M), _dp(r), float(eta), int(d), int(chi), int(precision),
+                    _stream_handle(stream), ctypes.byref(h)))
         self._h = h
         self.M, self.d, self.chi = int(M), int(d), int(chi)
 
@@ -227,6 +232,12 @@ class MPO:
 
     def sync(self):
         _check(lib().mpo_sync(self._h))
+
+    def contraction_flops(self):
+        """Algorithmic Theta-contraction flops since profiling was enabled."""
+        f = ctypes.c_double()
+        _check(lib().mpo_get_contraction_work(self._h, ctypes.byref(f)))
+        return f.value
 
     def layer_blocks(self):
         """Sector histogram of the last layer: int array [nblocks, 8] with

@@ -46,6 +46,15 @@ def workload(name: str) -> Workload:
         return Workload("medium", 32, [0.8] * 32, eta_sqrt_scaling(32, 0.8), 8, 256, 2)
     if name == "large":          # M=64, r=0.9, eta=0.3, d=8, chi=1024 (2016 gates)
         return Workload("large", 64, [0.9] * 64, 0.3, 8, 1024, 3)
+    if name.startswith("table1"):
+        # the shape of the paper's timing table (Sec. III.A): 12 modes, 10
+        # squeezed inputs, photon loss 0.55 (transmission 0.45), d = 15 read as
+        # a cap on the total photon number; r = 0.88 (about one photon per
+        # squeezed mode, Sec. III.B) and the first 10 modes squeezed are
+        # assumptions (the table states neither); "table1-<chi>" sets chi
+        chi = int(name.split("-")[1]) if "-" in name else 1024
+        return Workload(name, 12, [0.88] * 10 + [0.0] * 2, 0.45, 15, chi, 12,
+                        extra={"total_cap": True})
     raise KeyError(name)
 
 

