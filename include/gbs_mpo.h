@@ -34,10 +34,10 @@
  *
  * Errors.  Every call returns MPO_OK or a negative code and sets a
  * thread-local message (mpo_last_error).  Argument errors leave the state
- * unchanged.  mpo_apply_bs_layer only enqueues device work; a numerical
- * failure found on the device (non-converged SVD, non-finite values,
- * workspace overflow) is latched and returned by the next synchronising call
- * (mpo_entropy, mpo_photon_marginals, mpo_sync, mpo_get_bond).
+ * unchanged.  A numerical failure found on the device (non-converged SVD,
+ * non-finite values, workspace overflow) is latched and returned by the next
+ * synchronising call (mpo_entropy, mpo_photon_marginals, mpo_sync,
+ * mpo_get_bond) or by the next layer.
  */
 #ifndef GBS_MPO_H
 #define GBS_MPO_H
@@ -99,8 +99,13 @@ int mpo_init_lossy_squeezed_total_cap(int M, const double *r, double eta, int d,
  * update with charge-blocked Theta(c), Eq. theta; per-sector SVD truncated to
  * chi; App. D.5 block SVD).  Gates must be disjoint: no two share a mode.
  *   left_site[g] in [0, M-2]; theta[g], phi[g] as in T(theta, phi).
- * Enqueues device work only.  Also updates the operator EE of each updated
- * bond and the running maximum.
+ * Also updates the operator EE of each updated bond and the running maximum.
+ * Host waits: the sector sizes are data dependent, so the call waits for the
+ * device once after the planner's count pass (to size the workspaces) and,
+ * while large sectors are still in their panel Jacobi rounds, once every 16
+ * rounds (to compact the still-rotating sectors); everything else is enqueued
+ * on the handle's stream.  Every workspace is sized before the first new
+ * tensor is written, so an EINVAL / ENOMEM return leaves the state unchanged.
  */
 int mpo_apply_bs_layer(gbs_mpo *h, int n_gates, const int *left_site,
                        const double *theta, const double *phi);

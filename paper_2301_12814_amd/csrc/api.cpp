@@ -132,7 +132,7 @@ struct Engine {
   DBuf<double> d_sv;
   DBuf<unsigned long long> d_uval, d_ukey;
   DBuf<cd> d_A, d_A0, d_R, d_U, d_V, d_tau;
-  DBuf<int> d_rotf, d_tasks;
+  DBuf<int> d_rotf, d_tasks, d_qord;
   DBuf<int> d_active;
   DBuf<int> d_eng_err;
   int *h_small = nullptr;          // pinned: [1] engine error word, [2..3] rotating blocks / tasks
@@ -148,8 +148,11 @@ struct Engine {
   double work[4] = {};
   double contr_flops = 0.0;        // algorithmic contraction flops while profiling
   long long stats[6] = {0, 0, 0, 0, 0, -1};
-  std::vector<BlkDesc> last_blk;   // sector histogram of the last layer (single chunk)
-  std::vector<int> last_blk_gate;
+  // sector histogram of the last layer, read from d_blk only when asked for
+  // (valid while the layer ran as one chunk and no later layer overwrote it)
+  bool last_blk_valid = false;
+  std::vector<long long> last_blk0;   // per gate: first descriptor in d_blk
+  std::vector<int> last_nblk;         // per gate: descriptors
 };
 
 struct gbs_mpo {
@@ -278,6 +281,7 @@ void engine_destroy(Engine &E) {
   E.d_tau.release();
   E.d_rotf.release();
   E.d_tasks.release();
+  E.d_qord.release();
   E.d_active.release();
   E.d_eng_err.release();
   if (E.h_errs) hipHostFree(E.h_errs);
@@ -554,7 +558,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
                         E.stream));
   rc = sync_and_check(E, check_instances);
   if (rc != MPO_OK) return rc;
-  long long st_blk = 0, st_el = 0, st_sv = 0, st_mr = 0, st_mc = 0, st_sw = 0;
+  long long st_blk = 0, st_el = 0, st_sv = 0, st_mr = 0, st_mc = 0;
   double st_fl = 0.0, st_cf = 0.0;
   for (int g = 0; g < n; ++g) {
     const GateTot &t = E.h_tot[g];
@@ -585,54 +589,76 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
                         E.stream));
   L.ctab = E.d_ctab.p;
   HIPCHK(launch_ctab(L, E.stream));
-  E.last_blk.clear();
-  E.last_blk_gate.clear();
-  int c0 = 0;
-  while (c0 < n) {
+  E.last_blk_valid = false;
+  // Every chunk is planned and every pool sized before the first chunk's
+  // kernels run, so that a size limit or an allocation failure returns with
+  // the state untouched (no chunk has scattered new tensors yet).
+  struct Chunk {
+    int c0, c1, blkb, bigb, maxpp;
+    long long blk0, lst0, e, re;
+  };
+  std::vector<Chunk> chunks;
+  std::vector<GateBase> bases(n);
+  Chunk need{0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int c0 = 0; c0 < n;) {
     int c1 = c0;
     long long el = 0;
     while (c1 < n && (c1 == c0 || el + E.h_tot[c1].elems + E.h_tot[c1].relems <= E.pool_budget)) {
       el += E.h_tot[c1].elems + E.h_tot[c1].relems;
       ++c1;
     }
-    const int ng = c1 - c0;
-    long long e = 0, blk0 = 0, lst0 = 0, re = 0;
-    int blkb = 0, bigb = 0, maxpp = 0;
+    Chunk ch{c0, c1, 0, 0, 0, 0, 0, 0, 0};
     for (int g = c0; g < c1; ++g) {
       const GateTot &t = E.h_tot[g];
       GateParam &gp = E.h_gates[g];
-      gp.blk0 = blk0;
-      gp.lst0 = lst0;
-      blk0 += std::max(t.nblk, 1);
-      lst0 += std::max(std::max(t.rows, t.cols), std::max(t.sv, 1));
-      E.h_base[g - c0] = GateBase{e, blkb, bigb, re};
-      e += t.elems;
-      re += t.relems;
-      blkb += t.nblk;
-      bigb += t.nbig;
-      maxpp = std::max(maxpp, t.maxpp);
+      gp.blk0 = ch.blk0;
+      gp.lst0 = ch.lst0;
+      ch.blk0 += std::max(t.nblk, 1);
+      ch.lst0 += std::max(std::max(t.rows, t.cols), std::max(t.sv, 1));
+      bases[g] = GateBase{ch.e, ch.blkb, ch.bigb, ch.re};
+      ch.e += t.elems;
+      ch.re += t.relems;
+      ch.blkb += t.nblk;
+      ch.bigb += t.nbig;
+      ch.maxpp = std::max(ch.maxpp, t.maxpp);
     }
-    HIPCHK(E.d_blk.ensure(blk0));
-    HIPCHK(E.d_runs.ensure((size_t)blk0 * 64));
-    HIPCHK(E.d_rows.ensure(lst0));
-    HIPCHK(E.d_cols.ensure(lst0));
-    HIPCHK(E.d_bigl.ensure(lst0));
-    HIPCHK(E.d_perm.ensure(lst0));
-    HIPCHK(E.d_usize.ensure(lst0));
-    HIPCHK(E.d_sv.ensure(lst0));
-    HIPCHK(E.d_uval.ensure(lst0));
-    HIPCHK(E.d_ukey.ensure(lst0));
-    HIPCHK(E.d_A.ensure(std::max(e, 1LL), (size_t)E.pool_budget));
-    HIPCHK(E.d_A0.ensure(std::max(e, 1LL), (size_t)E.pool_budget));
-    HIPCHK(E.d_U.ensure(std::max(e, 1LL), (size_t)E.pool_budget));
-    HIPCHK(E.d_R.ensure(std::max(re, 1LL), (size_t)E.pool_budget));
-    HIPCHK(E.d_V.ensure(std::max(re, 1LL), (size_t)E.pool_budget));
-    HIPCHK(E.d_tau.ensure(lst0));
-    HIPCHK(E.d_piv.ensure(lst0));
-    HIPCHK(E.d_rotf.ensure((size_t)4 * std::max(bigb, 1)));
-    HIPCHK(E.d_tasks.ensure((size_t)2 * std::max(bigb, 1) + 1));
-    if (bigb > 65535 || maxpp / 2 > 65535)
+    if (ch.bigb > 65535 || ch.maxpp / 2 > 65535)
       return fail(MPO_EINVAL, "too many large sectors in one layer chunk");
+    need.blk0 = std::max(need.blk0, ch.blk0);
+    need.lst0 = std::max(need.lst0, ch.lst0);
+    need.e = std::max(need.e, ch.e);
+    need.re = std::max(need.re, ch.re);
+    need.bigb = std::max(need.bigb, ch.bigb);
+    chunks.push_back(ch);
+    c0 = c1;
+  }
+  HIPCHK(E.d_blk.ensure(need.blk0));
+  HIPCHK(E.d_runs.ensure((size_t)need.blk0 * 64));
+  HIPCHK(E.d_rows.ensure(need.lst0));
+  HIPCHK(E.d_cols.ensure(need.lst0));
+  HIPCHK(E.d_bigl.ensure(need.lst0));
+  HIPCHK(E.d_perm.ensure(need.lst0));
+  HIPCHK(E.d_usize.ensure(need.lst0));
+  HIPCHK(E.d_sv.ensure(need.lst0));
+  HIPCHK(E.d_uval.ensure(need.lst0));
+  HIPCHK(E.d_ukey.ensure(need.lst0));
+  HIPCHK(E.d_A.ensure(std::max(need.e, 1LL), (size_t)E.pool_budget));
+  HIPCHK(E.d_A0.ensure(std::max(need.e, 1LL), (size_t)E.pool_budget));
+  HIPCHK(E.d_U.ensure(std::max(need.e, 1LL), (size_t)E.pool_budget));
+  HIPCHK(E.d_R.ensure(std::max(need.re, 1LL), (size_t)E.pool_budget));
+  HIPCHK(E.d_V.ensure(std::max(need.re, 1LL), (size_t)E.pool_budget));
+  HIPCHK(E.d_tau.ensure(need.lst0));
+  HIPCHK(E.d_piv.ensure(need.lst0));
+  HIPCHK(E.d_rotf.ensure((size_t)4 * std::max(need.bigb, 1)));
+  HIPCHK(E.d_tasks.ensure((size_t)2 * std::max(need.bigb, 1) + 1));
+  long long max_blkb = 1;
+  for (const Chunk &chk : chunks) max_blkb = std::max<long long>(max_blkb, chk.blkb);
+  HIPCHK(E.d_qord.ensure((size_t)max_blkb));
+  for (const Chunk &chk : chunks) {
+    const int c0 = chk.c0, c1 = chk.c1, ng = c1 - c0;
+    const long long blk0 = chk.blk0;
+    const int blkb = chk.blkb, bigb = chk.bigb, maxpp = chk.maxpp;
+    for (int g = c0; g < c1; ++g) E.h_base[g - c0] = bases[g];
     HIPCHK(hipMemcpyAsync(E.d_gates.p + c0, E.h_gates + c0, sizeof(GateParam) * ng,
                           hipMemcpyHostToDevice, E.stream));
     HIPCHK(hipMemcpyAsync(E.d_base.p, E.h_base, sizeof(GateBase) * ng, hipMemcpyHostToDevice,
@@ -659,6 +685,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     C.V = E.d_V.p;
     C.tau = E.d_tau.p;
     C.piv = E.d_piv.p;
+    C.qr_order = E.d_qord.p;
     C.rotf = E.d_rotf.p;
     C.active = E.d_active.p;
     C.task_blk = E.d_tasks.p;
@@ -725,27 +752,24 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
       HIPCHK(launch_entropy_layer(C, E.stream));
     }
     if (c0 == 0 && c1 == n) {
-      // keep the sector histogram of a single-chunk layer
-      std::vector<BlkDesc> tmp((size_t)blk0);
-      HIPCHK(hipMemcpyAsync(tmp.data(), E.d_blk.p, sizeof(BlkDesc) * blk0, hipMemcpyDeviceToHost,
-                            E.stream));
-      HIPCHK(hipStreamSynchronize(E.stream));
-      for (int g = 0; g < n; ++g)
-        for (int b = 0; b < E.h_tot[g].nblk; ++b) {
-          const BlkDesc &B = tmp[E.h_gates[g].blk0 + b];
-          E.last_blk.push_back(B);
-          E.last_blk_gate.push_back(g);
-          if (B.comp) st_sw = std::max<long long>(st_sw, B.sweeps);
-        }
+      // the sector histogram of a single-chunk layer stays in d_blk; it is
+      // copied to the host only by mpo_layer_blocks / mpo_layer_stats
+      E.last_blk_valid = true;
+      E.last_blk0.assign(n, 0);
+      E.last_nblk.assign(n, 0);
+      for (int g = 0; g < n; ++g) {
+        E.last_blk0[g] = E.h_gates[g].blk0;
+        E.last_nblk[g] = E.h_tot[g].nblk;
+      }
+      (void)blk0;
     }
-    c0 = c1;
   }
   E.stats[0] = st_blk;
   E.stats[1] = st_el;
   E.stats[2] = st_sv;
   E.stats[3] = st_mr;
   E.stats[4] = st_mc;
-  E.stats[5] = st_sw;
+  E.stats[5] = -1;              // slowest block's sweeps: read lazily from d_blk
   return MPO_OK;
 }
 
@@ -1041,11 +1065,42 @@ extern "C" int mpo_get_site(gbs_mpo *h, int j, double *G) {
   return MPO_OK;
 }
 
+// Sector histogram of the last layer (descriptors in layer order), copied
+// from the device on demand; empty when the layer ran in several chunks.
+static int last_blocks(Engine &E, std::vector<BlkDesc> &blk, std::vector<int> &gate) {
+  blk.clear();
+  gate.clear();
+  if (!E.last_blk_valid) return MPO_OK;
+  long long total = 0;
+  for (size_t g = 0; g < E.last_blk0.size(); ++g)
+    total = std::max(total, E.last_blk0[g] + std::max(E.last_nblk[g], 1));
+  std::vector<BlkDesc> tmp((size_t)total);
+  if (total > 0) {
+    HIPCHK(hipMemcpyAsync(tmp.data(), E.d_blk.p, sizeof(BlkDesc) * total, hipMemcpyDeviceToHost,
+                          E.stream));
+    HIPCHK(hipStreamSynchronize(E.stream));
+  }
+  for (size_t g = 0; g < E.last_blk0.size(); ++g)
+    for (int b = 0; b < E.last_nblk[g]; ++b) {
+      blk.push_back(tmp[E.last_blk0[g] + b]);
+      gate.push_back((int)g);
+    }
+  return MPO_OK;
+}
+
 extern "C" int mpo_layer_stats(gbs_mpo *h, long long *stats) {
   if (!h || !stats) return fail(MPO_EINVAL, "NULL argument");
   int rc = sync_and_check(h->eng);
   if (rc != MPO_OK) return rc;
-  for (int i = 0; i < 6; ++i) stats[i] = h->eng.stats[i];
+  std::vector<BlkDesc> blk;
+  std::vector<int> gate;
+  rc = last_blocks(h->eng, blk, gate);
+  if (rc != MPO_OK) return rc;
+  long long sw = blk.empty() ? -1 : 0;
+  for (const BlkDesc &B : blk)
+    if (B.comp) sw = std::max<long long>(sw, B.sweeps);
+  for (int i = 0; i < 5; ++i) stats[i] = h->eng.stats[i];
+  stats[5] = sw;
   return MPO_OK;
 }
 
@@ -1053,12 +1108,15 @@ extern "C" int mpo_layer_blocks(gbs_mpo *h, int max_blocks, int *out) {
   if (!h || max_blocks < 0 || (max_blocks > 0 && !out)) return fail(MPO_EINVAL, "bad argument");
   int rc = sync_and_check(h->eng, false);   // diagnostics stay readable after a numeric error
   if (rc != MPO_OK) return rc;
-  const Engine &E = h->eng;
-  const int total = (int)E.last_blk.size();
+  std::vector<BlkDesc> blk;
+  std::vector<int> gate;
+  rc = last_blocks(h->eng, blk, gate);
+  if (rc != MPO_OK) return rc;
+  const int total = (int)blk.size();
   for (int i = 0; i < total && i < max_blocks; ++i) {
-    const BlkDesc &B = E.last_blk[i];
+    const BlkDesc &B = blk[i];
     int *o = out + (size_t)8 * i;
-    o[0] = E.last_blk_gate[i];
+    o[0] = gate[i];
     o[1] = charge_n(B.q);
     o[2] = charge_np(B.q);
     o[3] = B.r;

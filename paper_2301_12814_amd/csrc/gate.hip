@@ -320,13 +320,17 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
           nr += count_window(cR, DR, n, p1 - d + 1, p1);
         cf += 8.0 * nl * (double)nr;
       }
-      for (long long idx = threadIdx.x; idx < (long long)DL * DR; idx += blockDim.x) {
-        const int a = (int)(idx / DR), b = (int)(idx % DR);
-        const int n0 = charge_n(cL[a]) - charge_n(cR[b]);
-        const int n1 = charge_np(cL[a]) - charge_np(cR[b]);
-        if (n0 < 0 || n1 < 0 || n0 > 2 * d - 2 || n1 > 2 * d - 2) continue;
-        const int mk = min(n0, 2 * d - 2 - n0) + 1, mb = min(n1, 2 * d - 2 - n1) + 1;
-        cf += 8.0 * mk * mb * (double)(mk + mb);
+      for (int a = threadIdx.x; a < DL; a += blockDim.x) {
+        // right indices with 0 <= c_a0 - c_b0 <= 2d - 2: one range of the sorted bond
+        const int ca0 = charge_n(cL[a]), ca1 = charge_np(cL[a]);
+        const int b0 = lower_bound(cR, DR, pack_charge(max(ca0 - 2 * d + 2, 0), 0));
+        const int b1 = lower_bound(cR, DR, pack_charge(ca0 + 1, 0));
+        for (int b = b0; b < b1; ++b) {
+          const int n0 = ca0 - charge_n(cR[b]), n1 = ca1 - charge_np(cR[b]);
+          if (n1 < 0 || n1 > 2 * d - 2) continue;
+          const int mk = min(n0, 2 * d - 2 - n0) + 1, mb = min(n1, 2 * d - 2 - n1) + 1;
+          cf += 8.0 * mk * mb * (double)(mk + mb);
+        }
       }
     }
     // block-wide totals
@@ -1120,6 +1124,39 @@ __device__ void qr_blocked(cd *A, int m, int n, cd *tau, int *piv, int nb, doubl
   }
 }
 
+// Launch order of the QR workgroups: the QR'd blocks by decreasing work
+// (m n^2, in quarter-octave buckets), then every other block (they exit at
+// once).  A block's QR is one long chain on one workgroup, so starting the
+// largest first shortens the launch's tail; the order changes no arithmetic.
+constexpr int QR_ORDER_BUCKETS = 256;
+
+__global__ __launch_bounds__(1024) void k_qr_order(Layer ly) {
+  __shared__ int s_cnt[QR_ORDER_BUCKETS + 1];
+  __shared__ int s_off[QR_ORDER_BUCKETS + 1];
+  for (int i = threadIdx.x; i <= QR_ORDER_BUCKETS; i += blockDim.x) s_cnt[i] = 0;
+  __syncthreads();
+  auto bucket = [&](int flat) -> int {
+    const int g = find_gate_blk(ly.base, ly.ngates, flat);
+    const BlkDesc &B = ly.blk[ly.gates[g].blk0 + (flat - ly.base[g].blk)];
+    if (!B.comp || !B.qr) return QR_ORDER_BUCKETS;          // last
+    const double w = (double)B.m * B.n * B.n;
+    const int k = (int)(4.0 * log2(fmax(w, 1.0)));
+    return QR_ORDER_BUCKETS - 1 - min(k, QR_ORDER_BUCKETS - 1);   // heavy first
+  };
+  for (int f = threadIdx.x; f < ly.total_blocks; f += blockDim.x) atomicAdd(&s_cnt[bucket(f)], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int b = 0; b <= QR_ORDER_BUCKETS; ++b) {
+      s_off[b] = acc;
+      acc += s_cnt[b];
+    }
+  }
+  __syncthreads();
+  for (int f = threadIdx.x; f < ly.total_blocks; f += blockDim.x)
+    ly.qr_order[atomicAdd(&s_off[bucket(f)], 1)] = f;
+}
+
 // QR of every block whose panel of F fits in LDS (the others: k_qr).
 // Two workgroups of 512 threads share a CU (each with half of its LDS): the
 // factorisation is a chain of short dependent steps, and the second
@@ -1127,7 +1164,7 @@ __device__ void qr_blocked(cd *A, int m, int n, cd *tau, int *piv, int nb, doubl
 constexpr int QRP_THREADS = 512;
 
 __global__ __launch_bounds__(QRP_THREADS, 4) void k_qr_panel(Layer ly, int lds_bytes) {
-  const int flat = blockIdx.x;
+  const int flat = ly.qr_order[blockIdx.x];
   const int g = find_gate_blk(ly.base, ly.ngates, flat);
   const GateBase gb = ly.base[g];
   const GateParam gp = ly.gates[g];
@@ -1144,7 +1181,7 @@ __global__ __launch_bounds__(QRP_THREADS, 4) void k_qr_panel(Layer ly, int lds_b
 }
 
 __global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly, int lds_bytes) {
-  const int flat = blockIdx.x;
+  const int flat = ly.qr_order[blockIdx.x];
   const int g = find_gate_blk(ly.base, ly.ngates, flat);
   const GateBase gb = ly.base[g];
   const GateParam gp = ly.gates[g];
@@ -1307,9 +1344,12 @@ hipError_t launch_qr(Layer ly, int max_chi, hipStream_t s) {
   (void)max_chi;
   const int lb = svd_lds_bytes();
   const int half = svd_panel_half(lb);
+  hipLaunchKernelGGL(k_qr_order, dim3(1), dim3(1024), 0, s, ly);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_qr_panel, dim3(ly.total_blocks), dim3(QRP_THREADS), (size_t)half, s, ly,
                      half);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_qr, dim3(ly.total_blocks), dim3(QR_THREADS), (size_t)lb, s, ly, lb);
   return hipGetLastError();
@@ -1536,6 +1576,99 @@ __device__ __forceinline__ void cross_pass_l(T *sA, double *nrm, int m, int w, i
     }
     __syncthreads();
   }
+}
+
+// The same cross pairs when every pair takes a whole wavefront and the
+// columns fit in registers (m <= 64 CE): column t of the first panel stays
+// with wave t for all w sub-rounds, so only the second panel's columns pass
+// through LDS.  Every rotation is computed exactly as jacobi_pair<64> does
+// (same operands, same operation order), so the result is bitwise the same;
+// only the first panel's LDS loads and stores per sub-round are saved.
+template <typename T>
+__device__ __forceinline__ void cross_pass_stationary(T *sA, double *nrm, int m, int w, int wI,
+                                                      int wJ, double tol, double tiny, int &rot) {
+  using R = typename real_of<T>::type;
+  const int gl = threadIdx.x & 63, t = threadIdx.x >> 6;
+  const bool own = t < wI;
+  T rx[CE];
+  double nx = 0.0;
+  if (own) {
+#pragma unroll
+    for (int k = 0; k < CE; ++k) {
+      const int i = gl + 64 * k;
+      rx[k] = i < m ? sA[(size_t)t * m + i] : T{0, 0};
+    }
+    nx = nrm[t];
+  }
+  for (int sr = 0; sr < w; ++sr) {
+    const int u = own ? (t + sr) % w : 0;
+    if (own && u < wJ) {
+      T *yq = sA + (size_t)(wI + u) * m;
+      double *ny = nrm + wI + u;
+      const double al = nx, be = *ny;
+      if (fmin(al, be) > tiny) {
+        R gr = 0, gi = 0;
+        T ry[CE];
+#pragma unroll
+        for (int k = 0; k < CE; ++k) {
+          const int i = gl + 64 * k;
+          ry[k] = i < m ? yq[i] : T{0, 0};
+          gr = fma(rx[k].re, ry[k].re, fma(rx[k].im, ry[k].im, gr));
+          gi = fma(rx[k].re, ry[k].im, fma(-rx[k].im, ry[k].re, gi));
+        }
+        const double grd = group_sum<64>(gr), gid = group_sum<64>(gi);
+        const double ga2 = grd * grd + gid * gid;
+        if ((ga2 > tol * tol * (al * be)) && (ga2 > 1e-300)) {
+          const double rga = rsqrt(ga2), ga = ga2 * rga;
+          const double zeta = (be - al) * (0.5 * rga);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cd_ = rsqrt(1.0 + tt * tt);
+          const double er = grd * rga, ei = -gid * rga;
+          const R c = (R)cd_, s = (R)(cd_ * tt);
+          const R ser = (R)(cd_ * tt * er), sei = (R)(cd_ * tt * ei);
+          const R cer = (R)(cd_ * er), cei = (R)(cd_ * ei);
+          double al2 = al - tt * ga, be2 = be + tt * ga;
+          const bool exact = !(al2 >= 0.5 * al) || !(be2 >= 0.5 * be);
+          R na = 0, nb = 0;
+#pragma unroll
+          for (int k = 0; k < CE; ++k) {
+            const int i = gl + 64 * k;
+            if (i < m) {
+              const T x = rx[k], y = ry[k];
+              T x2, y2;
+              x2.re = fma(-ser, y.re, fma(sei, y.im, c * x.re));
+              x2.im = fma(-ser, y.im, fma(-sei, y.re, c * x.im));
+              y2.re = fma(cer, y.re, fma(-cei, y.im, s * x.re));
+              y2.im = fma(cer, y.im, fma(cei, y.re, s * x.im));
+              rx[k] = x2;
+              yq[i] = y2;
+              if (exact) {
+                na += cabs2(x2);
+                nb += cabs2(y2);
+              }
+            }
+          }
+          if (exact) {
+            al2 = group_sum<64>(na);
+            be2 = group_sum<64>(nb);
+          }
+          nx = al2;
+          if (gl == 0) *ny = be2;
+          rot = 1;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (own) {
+#pragma unroll
+    for (int k = 0; k < CE; ++k) {
+      const int i = gl + 64 * k;
+      if (i < m) sA[(size_t)t * m + i] = rx[k];
+    }
+    if (gl == 0) nrm[t] = nx;
+  }
+  __syncthreads();
 }
 
 __device__ __forceinline__ double block_sum(double v, double *s_red) {
@@ -1795,6 +1928,8 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
   if (w * 64 <= (int)blockDim.x && GBS_PANEL_WIDE) {
     if (round == 0)
       round_robin_pass_l<64>(sA, s_nrm, m, nc, tol, tiny, rot);
+    else if (m <= 64 * CE)
+      cross_pass_stationary(sA, s_nrm, m, w, wI, wJ, tol, tiny, rot);
     else
       cross_pass_l<64>(sA, s_nrm, m, w, wI, wJ, tol, tiny, rot);
   } else if (round == 0) {

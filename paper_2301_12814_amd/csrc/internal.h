@@ -115,6 +115,7 @@ struct Layer {
   int *active;       // [0] big blocks still rotating at the latest check, [1] their tasks
   int *task_blk;     // flat indices of the still-rotating big blocks
   int *task_pre;     // first panel task of each (task_pre[nact] = all tasks)
+  int *qr_order;     // total_blocks: launch order of the QR workgroups (largest first)
   int nact, ntask;   // host copies of active[0], active[1] for the panel launches
   int total_big;     // big blocks in the layer
   int maxpp;         // largest even panel count in the layer
