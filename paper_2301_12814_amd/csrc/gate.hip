@@ -1029,6 +1029,23 @@ __device__ void qr_blocked(cd *A, int m, int n, cd *tau, int *piv, int nb, doubl
         const cd *a = A + (size_t)col * m + k;
         double wr = 0.0, wi = 0.0;
         int y = lane;
+        // eight loads in flight per lane: one wave streams the whole trailing
+        // column, so the loads in flight set the rate of the factorisation's
+        // longest chain (the largest block's QR)
+        for (; y + 448 < len; y += 512) {
+          cd av[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) av[u] = a[y + 64 * u];
+          double pr[8], pi[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const cd q = cmulc(av[u], v[y + 64 * u]);
+            pr[u] = q.re;
+            pi[u] = q.im;
+          }
+          wr += ((pr[0] + pr[1]) + (pr[2] + pr[3])) + ((pr[4] + pr[5]) + (pr[6] + pr[7]));
+          wi += ((pi[0] + pi[1]) + (pi[2] + pi[3])) + ((pi[4] + pi[5]) + (pi[6] + pi[7]));
+        }
         for (; y + 192 < len; y += 256) {
           const cd a0 = a[y], a1 = a[y + 64], a2 = a[y + 128], a3 = a[y + 192];
           const cd q0 = cmulc(a0, v[y]), q1 = cmulc(a1, v[y + 64]);
@@ -1840,6 +1857,12 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly, int lo, int
   }
 }
 
+// Blocks with at most PANEL_VERSION_MAX panels (after rounding up to even)
+// keep panel versions and per-pair verification records (see k_panel):
+// PVER_STRIDE ints per big block, versions first, then the pair table.
+constexpr int PANEL_VERSION_MAX = 64;
+constexpr int PVER_STRIDE = PANEL_VERSION_MAX + PANEL_VERSION_MAX * PANEL_VERSION_MAX;
+
 // Big blocks: squared Frobenius norm and cleared convergence flags.
 // rotf[4k + (s % 3)]: a rotation happened in sweep s; rotf[4k + 3]: converged
 // at that sweep (0 while running).
@@ -1858,11 +1881,15 @@ __global__ __launch_bounds__(256) void k_big_prep(Layer ly) {
     int *rf = ly.rotf + 4 * (size_t)blockIdx.x;
     rf[0] = rf[1] = rf[2] = rf[3] = 0;
   }
+  // panel versions 0, no pair verified yet
+  int *pv = ly.pver + (size_t)blockIdx.x * PVER_STRIDE;
+  for (int i = threadIdx.x; i < PVER_STRIDE; i += blockDim.x) pv[i] = i < PANEL_VERSION_MAX ? 0 : -1;
 }
 
 #ifndef GBS_PANEL_THREADS
 #define GBS_PANEL_THREADS 1024
 #endif
+
 constexpr int PANEL_THREADS = GBS_PANEL_THREADS;
 
 // Launch t of the panel rounds: every big block runs its own sequence of
@@ -1907,6 +1934,17 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
   const bool hasI = I < P, hasJ = J < P;
   if (!(hasI && hasJ) && round != 0) return;     // a lone panel only rotates in round 0
   if (!hasI && !hasJ) return;
+  // Panel versions (count of write-backs) and, per panel pair, the versions
+  // at which the pair was last found orthogonal (no rotation in its task).
+  // A cross round whose two panels have not changed since then would find
+  // the same columns, compute the same dot products and rotate nothing, so it
+  // is skipped; results are bitwise those of running it.
+  const bool versioned = Pp <= PANEL_VERSION_MAX;
+  int *pv = ly.pver + (size_t)kbig * PVER_STRIDE;
+  int *prec = pv + PANEL_VERSION_MAX;
+  const int plo = min(I, J), phi = max(I, J);
+  const bool track = versioned && hasI && hasJ && round != 0;
+  if (track && prec[plo * PANEL_VERSION_MAX + phi] == ((pv[plo] << 16) | pv[phi])) return;
   const int i0 = hasI ? I * w : 0, wI = hasI ? min(w, n - I * w) : 0;
   const int j0 = hasJ ? J * w : 0, wJ = hasJ ? min(w, n - J * w) : 0;
   const int nc = wI + wJ;
@@ -1945,9 +1983,17 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
     s_any = 1;
   }
   __syncthreads();
-  if (!s_any) return;          // nothing rotated: the panels in memory are unchanged
+  if (!s_any) {                // nothing rotated: the panels in memory are unchanged
+    if (track && threadIdx.x == 0)
+      prec[plo * PANEL_VERSION_MAX + phi] = (pv[plo] << 16) | pv[phi];
+    return;
+  }
   copy_out(A + (size_t)i0 * m, sA, wI * m, 1.0 / sc);
   copy_out(A + (size_t)j0 * m, sA + (size_t)wI * m, wJ * m, 1.0 / sc);
+  if (versioned && threadIdx.x == 0) {
+    if (hasI) ++pv[I];
+    if (hasJ) ++pv[J];
+  }
 }
 
 // Big blocks not yet converged, compacted into the task list of the next
@@ -2100,6 +2146,8 @@ hipError_t launch_svd_panel_step(Layer ly, int step, hipStream_t s) {
     hipLaunchKernelGGL(k_panel<cd>, dim3(ly.ntask), dim3(thr), (size_t)ly.panel_lds, s, ly, step);
   return hipGetLastError();
 }
+
+int panel_version_ints() { return PVER_STRIDE; }
 
 int svd_max_steps(Layer ly) { return MAX_SWEEPS * (ly.maxpp > 1 ? ly.maxpp - 1 : 1) + 1; }
 

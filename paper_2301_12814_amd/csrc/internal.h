@@ -116,6 +116,8 @@ struct Layer {
   int *task_blk;     // flat indices of the still-rotating big blocks
   int *task_pre;     // first panel task of each (task_pre[nact] = all tasks)
   int *qr_order;     // total_blocks: launch order of the QR workgroups (largest first)
+  int *pver;         // per big block: panel versions and pair verification records
+                     // (panel_version_ints() each)
   int nact, ntask;   // host copies of active[0], active[1] for the panel launches
   int total_big;     // big blocks in the layer
   int maxpp;         // largest even panel count in the layer
@@ -158,6 +160,7 @@ hipError_t launch_svd_small(Layer ly, hipStream_t s);
 hipError_t launch_svd_big_prep(Layer ly, hipStream_t s);
 hipError_t launch_svd_panel_step(Layer ly, int step, hipStream_t s);
 int svd_max_steps(Layer ly);
+int panel_version_ints();
 int panel_lds_bytes(int max_chi);
 hipError_t launch_svd_count(Layer ly, int last, int next_step, hipStream_t s);
 hipError_t launch_svd_big_finish(Layer ly, int sweeps_run, int max_chi, hipStream_t s);
