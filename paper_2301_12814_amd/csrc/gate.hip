@@ -757,6 +757,17 @@ constexpr int QC = 16;   // column elements per lane kept in registers (m - k <=
 
 __device__ __forceinline__ double block_sum(double v, double *s_red);
 
+// Workgroup sum without the trailing barrier of block_sum: for callers whose
+// next write of s_red comes after another barrier.
+__device__ __forceinline__ double block_sum_keep(double v, double *s_red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += s_red[w];
+  return t;
+}
+
 // Largest value over the 64 lanes of a wave with, among equal values, the
 // lowest index; the same pair in every lane.  Each step merges a lane with
 // its partner under one total order, so both end with the same pair.
@@ -929,8 +940,8 @@ __device__ void qr_blocked(cd *A, int m, int n, cd *tau, int *piv, int nb, doubl
   __shared__ double s_red[16];
   __shared__ double s_bv[16];
   __shared__ int s_bi[16];
-  __shared__ cd s_tau, s_scale, s_aux[QR_NB];
-  __shared__ int s_skip, s_piv, s_flag;
+  __shared__ cd s_aux[QR_NB];
+  __shared__ int s_flag;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int c = wave; c < n; c += nw) {
     double acc = 0.0;
@@ -955,15 +966,16 @@ __device__ void qr_blocked(cd *A, int m, int n, cd *tau, int *piv, int nb, doubl
       wave_argmax(bv, bi);
       if (lane == 0) { s_bv[wave] = bv; s_bi[wave] = bi; }
       __syncthreads();
-      if (threadIdx.x == 0) {
+      // every thread merges the waves' candidates in the same order (no
+      // second barrier; s_bv / s_bi are next written after several more)
+      int p;
+      {
         double b = s_bv[0];
-        int p = s_bi[0];
+        int pp = s_bi[0];
         for (int w2 = 1; w2 < nw; ++w2)
-          if (s_bv[w2] > b || (s_bv[w2] == b && s_bi[w2] < p)) { b = s_bv[w2]; p = s_bi[w2]; }
-        s_piv = p < n ? p : k;
+          if (s_bv[w2] > b || (s_bv[w2] == b && s_bi[w2] < pp)) { b = s_bv[w2]; pp = s_bi[w2]; }
+        p = pp < n ? pp : k;
       }
-      __syncthreads();
-      const int p = s_piv;
       if (p != k) {
         for (int y = threadIdx.x; y < m; y += blockDim.x) {
           const cd t = A[(size_t)k * m + y];
@@ -993,36 +1005,26 @@ __device__ void qr_blocked(cd *A, int m, int n, cd *tau, int *piv, int nb, doubl
         if (i > 0) x[y] = a;
         if (y >= 1) s2 += cabs2(a);
       }
-      s2 = block_sum(s2, s_red);
+      s2 = block_sum_keep(s2, s_red);
+      // every thread forms the same reflector from x[0] and s2 (no barrier);
+      // thread 0 stores tau and the new diagonal after the next barrier, as
+      // nothing reads x[0] before the following column
+      cd h_tau, h_scale;
+      double h_beta;
+      const bool skip = !householder(x[0], s2, h_tau, h_scale, h_beta);
+      for (int y = 1 + threadIdx.x; y < len; y += blockDim.x) {
+        const cd t = skip ? x[y] : cmul(x[y], h_scale);
+        if (!skip) x[y] = t;
+        v[y] = t;
+      }
+      if (threadIdx.x == 0) v[0] = cmk(1.0, 0.0);
+      __syncthreads();
       if (threadIdx.x == 0) {
-        cd t, sc;
-        double beta;
-        if (!householder(x[0], s2, t, sc, beta)) {
-          s_skip = 1;
-          s_tau = cmk(0.0, 0.0);
-          tau[k] = cmk(0.0, 0.0);
-        } else {
-          s_tau = t;
-          s_scale = sc;
-          tau[k] = t;
-          x[0] = cmk(beta, 0.0);
-          s_skip = 0;
-        }
+        tau[k] = skip ? cmk(0.0, 0.0) : h_tau;
+        if (!skip) x[0] = cmk(h_beta, 0.0);
       }
-      __syncthreads();
-      const bool skip = s_skip != 0;
-      {
-        const cd sc = s_scale;
-        for (int y = 1 + threadIdx.x; y < len; y += blockDim.x) {
-          const cd t = skip ? x[y] : cmul(x[y], sc);
-          if (!skip) x[y] = t;
-          v[y] = t;
-        }
-        if (threadIdx.x == 0) v[0] = cmk(1.0, 0.0);
-      }
-      __syncthreads();
       // F[j, i] = tau_k A[k:, j]^H v (trailing j > k) and s_aux[c] = -tau_k V[k:, c]^H v
-      const cd tk = s_tau;
+      const cd tk = skip ? cmk(0.0, 0.0) : h_tau;
       const int ntr = n - k - 1;
       for (int t = wave; t < ntr + i; t += nw) {
         const int col = t < ntr ? k + 1 + t : k0 + (t - ntr);
@@ -2296,6 +2298,69 @@ hipError_t launch_select(Layer ly, hipStream_t s) {
 constexpr int LV_CHUNK = 8;    // kept vectors per pass over the pristine sector
 constexpr int LV_XCHUNK = 256; // vector entries staged in LDS at a time
 
+// U[:, c] = A0 v_c / sigma_c for the kept vectors of a QR'd block as a dense
+// complex product on the FP64 matrix cores: v_mfma_f64_16x16x4_f64 takes a
+// 16 x 4 tile of A (one double per lane: row lane % 16, k = lane / 16), a
+// 4 x 16 tile of B (k = lane / 16, column lane % 16) and accumulates a 16 x 16
+// tile of D (lane holds rows 4 r + lane / 16, r < 4, column lane % 16).  The
+// complex product uses four real products, (Ar Br - Ai Bi) + i (Ar Bi + Ai Br),
+// with two accumulator pairs (even and odd k steps) to keep the matrix pipe
+// busy.  Rows of U are tiled by 16 (one tile per wavefront at a time), the kept
+// vectors by 16, and the vectors are staged in LDS LVM_X entries at a time.
+typedef double lv_d4 __attribute__((ext_vector_type(4)));
+constexpr int LVM_X = 64;
+
+__device__ void leftvec_mfma(const cd *A0, int m, int n, const cd *V, const double *sv, int kq,
+                             cd *U, cd *sW) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ntile = (m + 15) / 16;
+  for (int c0 = 0; c0 < kq; c0 += 16) {
+    const int nc = min(16, kq - c0);
+    for (int t0 = 0; t0 < ntile; t0 += nw) {
+      const int t = t0 + wave;                  // this wave's row tile (may be past the end)
+      const int yr = 16 * t + li;               // A row of this lane
+      lv_d4 cr0 = {0, 0, 0, 0}, ci0 = {0, 0, 0, 0}, cr1 = {0, 0, 0, 0}, ci1 = {0, 0, 0, 0};
+      for (int x0 = 0; x0 < n; x0 += LVM_X) {
+        const int nx = min(LVM_X, n - x0);
+        __syncthreads();
+        // sW[x][c] = v_c[x0 + x] = conj of the stored (conjugated) vector
+        for (int idx = threadIdx.x; idx < LVM_X * 16; idx += blockDim.x) {
+          const int x = idx >> 4, c = idx & 15;
+          sW[idx] = (x < nx && c < nc) ? cconj(V[(size_t)(c0 + c) * n + x0 + x]) : cmk(0.0, 0.0);
+        }
+        __syncthreads();
+        if (t < ntile) {
+          for (int k4 = 0; k4 < nx; k4 += 8) {
+            // two k steps of 4 per iteration, one per accumulator pair
+            const int xa = k4 + lk, xb = k4 + 4 + lk;
+            const cd a = (yr < m && xa < nx) ? A0[(size_t)(x0 + xa) * m + yr] : cmk(0.0, 0.0);
+            const cd b = sW[xa * 16 + li];
+            const cd a2 = (yr < m && xb < nx) ? A0[(size_t)(x0 + xb) * m + yr] : cmk(0.0, 0.0);
+            const cd b2 = xb < LVM_X ? sW[xb * 16 + li] : cmk(0.0, 0.0);
+            cr0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, cr0, 0, 0, 0);
+            ci0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.im, ci0, 0, 0, 0);
+            cr1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2.re, b2.re, cr1, 0, 0, 0);
+            ci1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2.re, b2.im, ci1, 0, 0, 0);
+            cr0 = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, b.im, cr0, 0, 0, 0);
+            ci0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.re, ci0, 0, 0, 0);
+            cr1 = __builtin_amdgcn_mfma_f64_16x16x4f64(-a2.im, b2.im, cr1, 0, 0, 0);
+            ci1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a2.im, b2.re, ci1, 0, 0, 0);
+          }
+        }
+      }
+      if (t < ntile && li < nc) {
+        const double s1 = 1.0 / sv[c0 + li];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int y = 16 * t + 4 * r + lk;
+          if (y < m) U[(size_t)(c0 + li) * m + y] = cmk((cr0[r] + cr1[r]) * s1, (ci0[r] + ci1[r]) * s1);
+        }
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_leftvec(Layer ly, int nchunk) {
   const int flat = blockIdx.x;
   const int g = find_gate_blk(ly.base, ly.ngates, flat);
@@ -2362,6 +2427,10 @@ __global__ __launch_bounds__(256) void k_leftvec(Layer ly, int nchunk) {
       for (int x = lane; x < n; x += 64) v[x] = cmul(v[x], f);
     }
     __syncthreads();
+  }
+  if (!ly.mixed) {
+    leftvec_mfma(A0, m, n, V, sv, B.kq, U, sV);
+    return;
   }
   // 2. U = A0 V, LV_CHUNK vectors per pass over A0 (A0 read once per pass);
   // the vectors are staged in LDS LV_XCHUNK entries at a time, so that the
