@@ -20,7 +20,7 @@ SOURCES = ["init.hip", "gate.hip", "readout.hip", "asymptotic.hip", "api.cpp", "
            "clements.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+FLAGS = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
 
@@ -30,7 +30,7 @@ def _compile(src: str, obj_dir: str = OBJ, defines=()) -> str:
     cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-x", "hip", "-c",
            os.path.join(CSRC, src), "-o", out]
     if src == "clements.cpp":
-        cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, src), "-o", out]
+        cmd = [HIPCC, "-O3", "-std=c++20", "-fPIC", "-c", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -1411,21 +1411,26 @@ constexpr int CE = GBS_CE;   // elements per lane kept in registers (m <= L * CE
 // T is the complex type of the LDS operand (cd: FP64; cf: the FP32 Jacobi of
 // the mixed-precision path); dot products and rotations run in its precision,
 // the tracked norms and the rotation parameters in FP64.
-template <int L, typename T>
+// NC: row chunks of L per lane when the columns are cached in registers.  With
+// NC = ceil(m / L) (the dispatched form) every chunk but the last is full and
+// is loaded without a bound check; the default NC = CE serves any m <= L CE.
+template <int L, typename T, int NC = CE>
 __device__ __forceinline__ void jacobi_pair(T *xp, T *xq, double *nx, double *ny, int m,
                                             int gl, double tol, double tiny, int &rot) {
   using R = typename real_of<T>::type;
   const double al = *nx, be = *ny;
   if (fmin(al, be) <= tiny) return;
   R gr = 0, gi = 0;
-  const bool cached = m <= L * CE;
-  T rx[CE], ry[CE];
+  const bool exact = m > L * (NC - 1);
+  const bool cached = m <= L * NC;
+  T rx[NC], ry[NC];
   if (cached) {
 #pragma unroll
-    for (int k = 0; k < CE; ++k) {
+    for (int k = 0; k < NC; ++k) {
       const int i = gl + L * k;
-      rx[k] = i < m ? xp[i] : T{0, 0};
-      ry[k] = i < m ? xq[i] : T{0, 0};
+      const bool in = (exact && k < NC - 1) || i < m;
+      rx[k] = in ? xp[i] : T{0, 0};
+      ry[k] = in ? xq[i] : T{0, 0};
       gr = fma(rx[k].re, ry[k].re, fma(rx[k].im, ry[k].im, gr));
       gi = fma(rx[k].re, ry[k].im, fma(-rx[k].im, ry[k].re, gi));
     }
@@ -1451,7 +1456,7 @@ __device__ __forceinline__ void jacobi_pair(T *xp, T *xq, double *nx, double *ny
   double al2 = al - t * ga, be2 = be + t * ga;
   // the tracked norms lose accuracy when a column loses more than half of
   // its weight; then both are summed afresh from the rotated columns
-  const bool exact = !(al2 >= 0.5 * al) || !(be2 >= 0.5 * be);
+  const bool renorm = !(al2 >= 0.5 * al) || !(be2 >= 0.5 * be);
   R na = 0, nb = 0;
   auto rotate = [&](const T x, const T y, T &x2, T &y2) {
     x2.re = fma(-ser, y.re, fma(sei, y.im, c * x.re));
@@ -1461,14 +1466,14 @@ __device__ __forceinline__ void jacobi_pair(T *xp, T *xq, double *nx, double *ny
   };
   if (cached) {
 #pragma unroll
-    for (int k = 0; k < CE; ++k) {
+    for (int k = 0; k < NC; ++k) {
       const int i = gl + L * k;
-      if (i < m) {
+      if ((exact && k < NC - 1) || i < m) {
         T x2, y2;
         rotate(rx[k], ry[k], x2, y2);
         xp[i] = x2;
         xq[i] = y2;
-        if (exact) {
+        if (renorm) {
           na += cabs2(x2);
           nb += cabs2(y2);
         }
@@ -1480,13 +1485,13 @@ __device__ __forceinline__ void jacobi_pair(T *xp, T *xq, double *nx, double *ny
       rotate(xp[i], xq[i], x2, y2);
       xp[i] = x2;
       xq[i] = y2;
-      if (exact) {
+      if (renorm) {
         na += cabs2(x2);
         nb += cabs2(y2);
       }
     }
   }
-  if (exact) {               // uniform over the group
+  if (renorm) {              // uniform over the group
     al2 = group_sum<L>(na);
     be2 = group_sum<L>(nb);
   }
@@ -1543,7 +1548,7 @@ __device__ __forceinline__ cd *jacobi_operand(const Layer &ly, const GateBase &g
 
 // One round-robin pass over all pairs of the nc columns at A (column stride m,
 // squared norms in nrm), L lanes per pair.
-template <int L, typename T>
+template <int L, typename T, int NC = CE>
 __device__ __forceinline__ void round_robin_pass_l(T *A, double *nrm, int m, int nc, double tol,
                                                    double tiny, int &rot) {
   const int gl = threadIdx.x & (L - 1), slot = threadIdx.x / L;
@@ -1560,8 +1565,8 @@ __device__ __forceinline__ void round_robin_pass_l(T *A, double *nrm, int m, int
         q = (round - k + np - 1) % (np - 1);
       }
       if (p >= nc || q >= nc) continue;
-      jacobi_pair<L>(A + (size_t)p * m, A + (size_t)q * m, nrm + p, nrm + q, m, gl, tol, tiny,
-                     rot);
+      jacobi_pair<L, T, NC>(A + (size_t)p * m, A + (size_t)q * m, nrm + p, nrm + q, m, gl, tol,
+                            tiny, rot);
     }
     __syncthreads();
   }
@@ -1603,35 +1608,37 @@ __device__ __forceinline__ void cross_pass_l(T *sA, double *nrm, int m, int w, i
 // through LDS.  Every rotation is computed exactly as jacobi_pair<64> does
 // (same operands, same operation order), so the result is bitwise the same;
 // only the first panel's LDS loads and stores per sub-round are saved.
-template <typename T>
+// NC = ceil(m / 64) row chunks per lane (m <= 64 NC): all but the last are
+// full and carry no bound check.
+template <typename T, int NC>
 __device__ __forceinline__ void cross_pass_stationary(T *sA, double *nrm, int m, int w, int wI,
                                                       int wJ, double tol, double tiny, int &rot) {
   using R = typename real_of<T>::type;
   const int gl = threadIdx.x & 63, t = threadIdx.x >> 6;
   const bool own = t < wI;
-  T rx[CE];
+  T rx[NC];
   double nx = 0.0;
   if (own) {
 #pragma unroll
-    for (int k = 0; k < CE; ++k) {
+    for (int k = 0; k < NC; ++k) {
       const int i = gl + 64 * k;
-      rx[k] = i < m ? sA[(size_t)t * m + i] : T{0, 0};
+      rx[k] = (k < NC - 1 || i < m) ? sA[(size_t)t * m + i] : T{0, 0};
     }
     nx = nrm[t];
   }
-  for (int sr = 0; sr < w; ++sr) {
-    const int u = own ? (t + sr) % w : 0;
+  int u = t;                   // (t + sr) mod w, stepped per sub-round
+  for (int sr = 0; sr < w; ++sr, u = (u + 1 == w) ? 0 : u + 1) {
     if (own && u < wJ) {
       T *yq = sA + (size_t)(wI + u) * m;
       double *ny = nrm + wI + u;
       const double al = nx, be = *ny;
       if (fmin(al, be) > tiny) {
         R gr = 0, gi = 0;
-        T ry[CE];
+        T ry[NC];
 #pragma unroll
-        for (int k = 0; k < CE; ++k) {
+        for (int k = 0; k < NC; ++k) {
           const int i = gl + 64 * k;
-          ry[k] = i < m ? yq[i] : T{0, 0};
+          ry[k] = (k < NC - 1 || i < m) ? yq[i] : T{0, 0};
           gr = fma(rx[k].re, ry[k].re, fma(rx[k].im, ry[k].im, gr));
           gi = fma(rx[k].re, ry[k].im, fma(-rx[k].im, ry[k].re, gi));
         }
@@ -1647,12 +1654,12 @@ __device__ __forceinline__ void cross_pass_stationary(T *sA, double *nrm, int m,
           const R ser = (R)(cd_ * tt * er), sei = (R)(cd_ * tt * ei);
           const R cer = (R)(cd_ * er), cei = (R)(cd_ * ei);
           double al2 = al - tt * ga, be2 = be + tt * ga;
-          const bool exact = !(al2 >= 0.5 * al) || !(be2 >= 0.5 * be);
+          const bool renorm = !(al2 >= 0.5 * al) || !(be2 >= 0.5 * be);
           R na = 0, nb = 0;
 #pragma unroll
-          for (int k = 0; k < CE; ++k) {
+          for (int k = 0; k < NC; ++k) {
             const int i = gl + 64 * k;
-            if (i < m) {
+            if (k < NC - 1 || i < m) {
               const T x = rx[k], y = ry[k];
               T x2, y2;
               x2.re = fma(-ser, y.re, fma(sei, y.im, c * x.re));
@@ -1661,13 +1668,13 @@ __device__ __forceinline__ void cross_pass_stationary(T *sA, double *nrm, int m,
               y2.im = fma(cer, y.im, fma(cei, y.re, s * x.im));
               rx[k] = x2;
               yq[i] = y2;
-              if (exact) {
+              if (renorm) {
                 na += cabs2(x2);
                 nb += cabs2(y2);
               }
             }
           }
-          if (exact) {
+          if (renorm) {
             al2 = group_sum<64>(na);
             be2 = group_sum<64>(nb);
           }
@@ -1681,13 +1688,30 @@ __device__ __forceinline__ void cross_pass_stationary(T *sA, double *nrm, int m,
   }
   if (own) {
 #pragma unroll
-    for (int k = 0; k < CE; ++k) {
+    for (int k = 0; k < NC; ++k) {
       const int i = gl + 64 * k;
-      if (i < m) sA[(size_t)t * m + i] = rx[k];
+      if (k < NC - 1 || i < m) sA[(size_t)t * m + i] = rx[k];
     }
     if (gl == 0) nrm[t] = nx;
   }
   __syncthreads();
+}
+
+// Calls F.template operator()<NC>() with NC = ceil(m / L) for m <= L CE
+// (register-cached columns, exact chunk count), else with NC = CE.
+template <int L, typename F>
+__device__ __forceinline__ void with_chunks(int m, F &&f) {
+  static_assert(CE == 8, "chunk dispatch written for eight chunks");
+  switch ((m + L - 1) / L) {
+    case 1: f.template operator()<1>(); break;
+    case 2: f.template operator()<2>(); break;
+    case 3: f.template operator()<3>(); break;
+    case 4: f.template operator()<4>(); break;
+    case 5: f.template operator()<5>(); break;
+    case 6: f.template operator()<6>(); break;
+    case 7: f.template operator()<7>(); break;
+    default: f.template operator()<CE>(); break;
+  }
 }
 
 __device__ __forceinline__ double block_sum(double v, double *s_red) {
@@ -1840,7 +1864,9 @@ __global__ __launch_bounds__(SVD_THREADS) void k_svd_small(Layer ly, int lo, int
       if (threadIdx.x == 0) s_rot = 0;
       column_norms(sA, m, n, sig);
       int rot = 0;
-      round_robin_pass_l<GBS_SMALL_LANES>(sA, sig, m, n, tol, tiny, rot);
+      with_chunks<GBS_SMALL_LANES>(m, [&]<int NC>() {
+        round_robin_pass_l<GBS_SMALL_LANES, T, NC>(sA, sig, m, n, tol, tiny, rot);
+      });
       if (rot) s_rot = 1;
       __syncthreads();
       const int any = s_rot;
@@ -1967,9 +1993,11 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
   // one more, cheap, lane-swap step of every reduction
   if (w * 64 <= (int)blockDim.x && GBS_PANEL_WIDE) {
     if (round == 0)
-      round_robin_pass_l<64>(sA, s_nrm, m, nc, tol, tiny, rot);
+      with_chunks<64>(m, [&]<int NC>() { round_robin_pass_l<64, T, NC>(sA, s_nrm, m, nc, tol, tiny, rot); });
     else if (m <= 64 * CE)
-      cross_pass_stationary(sA, s_nrm, m, w, wI, wJ, tol, tiny, rot);
+      with_chunks<64>(m, [&]<int NC>() {
+        cross_pass_stationary<T, NC>(sA, s_nrm, m, w, wI, wJ, tol, tiny, rot);
+      });
     else
       cross_pass_l<64>(sA, s_nrm, m, w, wI, wJ, tol, tiny, rot);
   } else if (round == 0) {
@@ -1980,11 +2008,9 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
   __shared__ int s_any;
   if (threadIdx.x == 0) s_any = 0;
   __syncthreads();
-  if (rot) {
-    rf[sweep % 3] = 1;
-    s_any = 1;
-  }
+  if (rot) s_any = 1;
   __syncthreads();
+  if (s_any && threadIdx.x == 0) rf[sweep % 3] = 1;
   if (!s_any) {                // nothing rotated: the panels in memory are unchanged
     if (track && threadIdx.x == 0)
       prec[plo * PANEL_VERSION_MAX + phi] = (pv[plo] << 16) | pv[phi];
