@@ -1177,12 +1177,16 @@ __global__ __launch_bounds__(1024) void k_qr_order(Layer ly) {
 }
 
 // QR of every block whose panel of F fits in LDS (the others: k_qr).
-// Two workgroups of 512 threads share a CU (each with half of its LDS): the
-// factorisation is a chain of short dependent steps, and the second
-// workgroup's steps fill the first one's waits.
-constexpr int QRP_THREADS = 512;
+// A block's factorisation is one long chain on one workgroup, and the
+// largest blocks' chains set the launch's length: 1024 threads per
+// workgroup (one per CU, half of its LDS) stream each trailing column with
+// twice the lanes of two 512-thread workgroups per CU.
+#ifndef GBS_QRP_THREADS
+#define GBS_QRP_THREADS 1024
+#endif
+constexpr int QRP_THREADS = GBS_QRP_THREADS;
 
-__global__ __launch_bounds__(QRP_THREADS, 4) void k_qr_panel(Layer ly, int lds_bytes) {
+__global__ __launch_bounds__(QRP_THREADS) void k_qr_panel(Layer ly, int lds_bytes) {
   const int flat = ly.qr_order[blockIdx.x];
   const int g = find_gate_blk(ly.base, ly.ngates, flat);
   const GateBase gb = ly.base[g];
