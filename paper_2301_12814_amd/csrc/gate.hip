@@ -111,6 +111,16 @@ __host__ __device__ inline int panel_width(int m, int n, int lds_bytes, int esz)
   return (n + np - 1) / np;
 }
 
+// Panel width of the FP64 panel rounds (Gram form, k_panel_gram): the columns
+// stream from global memory, so only the 32 columns of a panel pair's Gram
+// bound the width: the fewest panels of at most 16 columns (even count when
+// more than one), then the narrowest width giving that count.
+__host__ __device__ inline int gram_panel_width(int n) {
+  int np = (n + 15) / 16;
+  if (np > 1 && (np & 1)) ++np;
+  return (n + np - 1) / np;
+}
+
 // Route of a computed block's SVD.  A block with at least 16 columns, or
 // whose operand does not fit in LDS, is first reduced by a Householder QR,
 // A = Q R, and the Jacobi rotates the n x n operand X = R^H: its columns are
@@ -278,7 +288,8 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
           if (big && 2LL * mj * ly.esz > panel_lds) atomicOr(st.err, ERR_WORKSPACE);
           if (big) {
             ++bgb;
-            const int w = panel_width(mj, n, min(lds_bytes, panel_lds), ly.esz);
+            const int w = ly.mixed ? panel_width(mj, n, min(lds_bytes, panel_lds), ly.esz)
+                                   : gram_panel_width(n);
             const int np = (n + w - 1) / w;
             maxpp = max(maxpp, np + (np & 1));
           }
@@ -404,7 +415,8 @@ __global__ __launch_bounds__(1024) void k_plan(Layer ly, int lds_bytes, int qr_o
         svd_route(B.m, B.n, lds_bytes, qr_ok, ly.esz, qr, bg, mj);
         if (qr) re = (long long)B.n * B.n;
         if (bg) {
-          w = panel_width(mj, B.n, min(lds_bytes, panel_lds), ly.esz);
+          w = ly.mixed ? panel_width(mj, B.n, min(lds_bytes, panel_lds), ly.esz)
+                       : gram_panel_width(B.n);
           npan = (B.n + w - 1) / w;
         }
       }
@@ -2028,6 +2040,407 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
   }
 }
 
+// ----------------------------------------------------------------------------
+// Panel rounds in Gram form (the FP64 path).  A task's two panels (at most 16
+// columns each; padded index space of 32: panel I at 0..15, panel J at
+// 16..31) are not staged in LDS.  Their Gram matrix G = X^H X is formed on
+// the FP64 matrix cores straight from global memory; the task's rotations
+// (the same pairs, in the same order, as the column passes above) are
+// computed from G and applied to it from both sides, G <- J^H G J, while
+// their product W = J_1 J_2 ... accumulates; then the columns receive all of
+// them at once, X <- X W, again on the matrix cores.  The rotation of a pair
+// (p, q) with g = G[p][q], al = G[p][p], be = G[q][q] follows the formulas of
+// the column passes (zeta, t, c, s and e = conj(g) / |g|): column p of J is
+// c on row p and -s e on row q, column q is s on row p and c e on row q.  In
+// exact arithmetic the rotations are those of the column passes; G holds the
+// same inner products (each rounded once per update instead of recomputed),
+// and the final pass with no rotation decides convergence on a G formed
+// afresh from the columns.  LDS: G (double-buffered) and W, 49 KB, so three
+// tasks share a CU.
+// ----------------------------------------------------------------------------
+constexpr int PG_THREADS = 256;
+constexpr int PG_N = 32;
+typedef double pg_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ pg_d4 pg_mfma(double a, double b, pg_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Complex products in a fixed sequence of fused operations (every caller
+// rounds alike).
+__device__ __forceinline__ cd pg_mul(cd a, cd b) {          // a b
+  return cmk(fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re));
+}
+__device__ __forceinline__ cd pg_mulc(cd a, cd b) {         // conj(a) b
+  return cmk(fma(a.re, b.re, a.im * b.im), fma(a.re, b.im, -(a.im * b.re)));
+}
+__device__ __forceinline__ cd pg_fma(cd a, cd b, cd c) {    // a b + c
+  return cmk(fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im)));
+}
+
+// Entry (i, j), i <= j, of J^H G J for the round's coefficients: self[k] =
+// J[k][k], other[k] = J[part[k]][k], part[k] = partner of k (k itself, with
+// self 1 and other 0, when k is not rotated).  Branch-free and in one fixed
+// sequence of operations, so that the threads forming the next round's
+// rotations get the very bits the update writes.
+__device__ __forceinline__ cd pg_entry(const cd *G, int i, int j, const cd *self, const cd *other,
+                                       const int *part) {
+  const int pi = part[i], pj = part[j];
+  const cd ai = self[i], bi = other[i], aj = self[j], bj = other[j];
+  const cd t1 = pg_fma(G[i * 32 + pj], bj, pg_mul(G[i * 32 + j], aj));
+  const cd t2 = pg_fma(G[pi * 32 + pj], bj, pg_mul(G[pi * 32 + j], aj));
+  cd v = pg_mulc(ai, t1);
+  const cd u = pg_mulc(bi, t2);
+  v = cmk(v.re + u.re, v.im + u.im);
+  if (i == j) v.im = 0.0;
+  return v;
+}
+
+// Partner of padded index k in inner round rr of a task (round 0: the
+// round-robin pairs of the compact columns, I's then J's; other rounds: the
+// cross pairs (t, wI + (t + rr) mod w)); isp: k is the pair's first column.
+__device__ __forceinline__ int pg_partner(int k, int rr, bool round0, int wI, int wJ, int w,
+                                          bool &isp) {
+  isp = false;
+  const int nc = wI + wJ;
+  if (round0) {
+    const int ck = k < 16 ? (k < wI ? k : -1) : (k - 16 < wJ ? wI + (k - 16) : -1);
+    if (ck < 0 || nc < 2) return -1;
+    const int npc = nc + (nc & 1);
+    int pc;
+    if (ck == npc - 1) {
+      pc = rr;
+    } else if (ck == rr) {
+      pc = npc - 1;
+      isp = true;
+    } else {
+      const int s1 = (ck - rr + npc - 1) % (npc - 1);
+      if (s1 <= npc / 2 - 1) {
+        isp = true;
+        pc = (rr - s1 + npc - 1) % (npc - 1);
+      } else {
+        pc = (rr + (npc - 1 - s1)) % (npc - 1);
+      }
+    }
+    return pc < nc ? (pc < wI ? pc : 16 + (pc - wI)) : -1;
+  }
+  if (k < 16) {
+    if (k >= wI) return -1;
+    const int u = (k + rr) % w;
+    isp = true;
+    return u < wJ ? 16 + u : -1;
+  }
+  if (k - 16 >= wJ) return -1;
+  const int t = (k - 16 - rr % w + w) % w;
+  return t < wI ? t : -1;
+}
+
+__global__ __launch_bounds__(PG_THREADS, 3) void k_panel_gram(Layer ly, int step) {
+  const int task = blockIdx.x;
+  int lo = 0, hi = ly.nact;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ly.task_pre[mid] <= task) lo = mid; else hi = mid;
+  }
+  const int kbig = ly.task_blk[lo];
+  const int kpair = task - ly.task_pre[lo];
+  int g, bi;
+  big_block_of(ly, kbig, g, bi);
+  const BlkDesc B = ly.blk[ly.gates[g].blk0 + bi];
+  const int P = B.npan, Pp = P + (P & 1);
+  if (kpair >= Pp / 2) return;
+  const int sweep = step / (Pp - 1), round = step % (Pp - 1);
+  if (sweep >= min(MAX_SWEEPS, ly.states[ly.gates[g].inst].max_sweeps)) return;
+  int *rf = ly.rotf + 4 * (size_t)kbig;
+  if (rf[3]) return;
+  if (round == 0 && sweep > 0 && rf[(sweep - 1) % 3] == 0) {   // previous sweep: no rotation
+    if (threadIdx.x == 0) rf[3] = sweep;
+    return;
+  }
+  if (round == 0 && kpair == 0 && threadIdx.x == 0) rf[(sweep + 1) % 3] = 0;
+  int I, J;
+  if (kpair == 0) {
+    I = round;
+    J = Pp - 1;
+  } else {
+    I = (round + kpair) % (Pp - 1);
+    J = (round - kpair + Pp - 1) % (Pp - 1);
+  }
+  const int m = B.mj, n = B.n, w = B.w;
+  const bool hasI = I < P, hasJ = J < P;
+  if (!(hasI && hasJ) && round != 0) return;     // a lone panel only rotates in round 0
+  if (!hasI && !hasJ) return;
+  // panel versions and verification records, as in k_panel
+  const bool versioned = Pp <= PANEL_VERSION_MAX;
+  int *pv = ly.pver + (size_t)kbig * PVER_STRIDE;
+  int *prec = pv + PANEL_VERSION_MAX;
+  const int plo = min(I, J), phi = max(I, J);
+  const bool track = versioned && hasI && hasJ && round != 0;
+  if (track && prec[plo * PANEL_VERSION_MAX + phi] == ((pv[plo] << 16) | pv[phi])) return;
+  const int i0 = hasI ? I * w : 0, wI = hasI ? min(w, n - I * w) : 0;
+  const int j0 = hasJ ? J * w : 0, wJ = hasJ ? min(w, n - J * w) : 0;
+  const int nc = wI + wJ;
+  cd *A = jacobi_operand(ly, ly.base[g], B);
+  __shared__ cd sG[2][PG_N * PG_N];      // G[i][j] at i * PG_N + j
+  __shared__ cd sW[PG_N * PG_N];         // W[i][j] at i * PG_N + j
+  __shared__ cd s_self[2][PG_N], s_other[2][PG_N];   // J[i][i], J[partner(i)][i]
+  __shared__ int s_part[2][PG_N];        // partner of i in the round (i itself: none)
+  __shared__ int s_pp[2][PG_N / 2], s_pq[2][PG_N / 2];   // the round's rotated pairs
+  __shared__ int s_np[2];
+  __shared__ int s_any;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  // global column of padded index k, -1 when there is none
+  auto col_of = [&](int k) -> int {
+    if (k < 16) return k < wI ? i0 + k : -1;
+    return k - 16 < wJ ? j0 + (k - 16) : -1;
+  };
+  // 1. the Gram tiles (I, I), (I, J), (J, J): wave v takes rows [v R, v R +
+  // R) of all three from one set of loads (lane (lr, lk) feeds column lr of
+  // each panel at row y + lk; tile entry [i][j] = sum_y conj(X[y][P + i])
+  // X[y][Q + j] lands in lane (lr = j, lk) register r with i = 4 r + lk), the
+  // next 16 rows' loads in flight while the current ones are multiplied; the
+  // four partial Grams are then summed in wave order.
+  {
+    const int cI = col_of(lr), cJ = col_of(16 + lr);
+    const cd *xi = cI >= 0 ? A + (size_t)cI * m : nullptr;
+    const cd *xj = cJ >= 0 ? A + (size_t)cJ * m : nullptr;
+    const int R = ((m + 4 * nwv * 4 - 1) / (4 * nwv * 4)) * 16;     // rows per wave, multiple of 16
+    const int ya = min(m, wave * R), yb = min(m, ya + R);
+    pg_d4 ar = {0.0, 0.0, 0.0, 0.0}, ai = ar, br = ar, bi = ar, cr = ar, ci = ar;
+    constexpr int GB = 4;                              // 4-row steps per batch
+    cd a[GB], b[GB];
+    auto load = [&](int y0, cd *ra, cd *rb) {
+#pragma unroll
+      for (int u = 0; u < GB; ++u) {
+        const int y = y0 + 4 * u + lk;
+        ra[u] = (xi && y < yb) ? xi[y] : cmk(0.0, 0.0);
+        rb[u] = (xj && y < yb) ? xj[y] : cmk(0.0, 0.0);
+      }
+    };
+    load(ya, a, b);
+    for (int y0 = ya; y0 < yb; y0 += 4 * GB) {
+      cd a2[GB], b2[GB];
+      load(y0 + 4 * GB, a2, b2);
+#pragma unroll
+      for (int u = 0; u < GB; ++u) {
+        // (I, I): conj(a) a; (I, J): conj(a) b; (J, J): conj(b) b
+        ar = pg_mfma(a[u].re, a[u].re, ar);
+        ar = pg_mfma(a[u].im, a[u].im, ar);
+        ai = pg_mfma(a[u].re, a[u].im, ai);
+        ai = pg_mfma(-a[u].im, a[u].re, ai);
+        br = pg_mfma(a[u].re, b[u].re, br);
+        br = pg_mfma(a[u].im, b[u].im, br);
+        bi = pg_mfma(a[u].re, b[u].im, bi);
+        bi = pg_mfma(-a[u].im, b[u].re, bi);
+        cr = pg_mfma(b[u].re, b[u].re, cr);
+        cr = pg_mfma(b[u].im, b[u].im, cr);
+        ci = pg_mfma(b[u].re, b[u].im, ci);
+        ci = pg_mfma(-b[u].im, b[u].re, ci);
+      }
+#pragma unroll
+      for (int u = 0; u < GB; ++u) {
+        a[u] = a2[u];
+        b[u] = b2[u];
+      }
+    }
+    // partials of waves 1, 2 in sG[1] and sW, of wave 3 in sG[0], at the
+    // tiles' own positions (upper blocks); wave 0 adds them in wave order
+    if (wave > 0) {
+      cd *dst = wave == 1 ? sG[1] : wave == 2 ? sW : sG[0];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * r + lk, j = lr;
+        dst[i * PG_N + j] = cmk(ar[r], ai[r]);
+        dst[i * PG_N + 16 + j] = cmk(br[r], bi[r]);
+        dst[(16 + i) * PG_N + 16 + j] = cmk(cr[r], ci[r]);
+      }
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * r + lk, j = lr;
+        const int pos[3] = {i * PG_N + j, i * PG_N + 16 + j, (16 + i) * PG_N + 16 + j};
+        const double vr0[3] = {ar[r], br[r], cr[r]}, vi0[3] = {ai[r], bi[r], ci[r]};
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const cd p1 = sG[1][pos[t]], p2 = sW[pos[t]], p3 = sG[0][pos[t]];
+          const double vr = ((vr0[t] + p1.re) + p2.re) + p3.re;
+          double vi = ((vi0[t] + p1.im) + p2.im) + p3.im;
+          const int ri = t == 2 ? 16 + i : i, cj = t == 0 ? j : 16 + j;
+          if (t == 1) {
+            sG[0][ri * PG_N + cj] = cmk(vr, vi);
+            sG[0][cj * PG_N + ri] = cmk(vr, -vi);
+          } else if (i <= j) {            // Hermitian: upper triangle, mirrored
+            if (i == j) vi = 0.0;
+            sG[0][ri * PG_N + cj] = cmk(vr, vi);
+            sG[0][cj * PG_N + ri] = cmk(vr, -vi);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < PG_N * PG_N; e += blockDim.x)
+    sW[e] = cmk(e / PG_N == e % PG_N ? 1.0 : 0.0, 0.0);
+  if (threadIdx.x == 0) s_any = 0;
+  const double tol = jacobi_tol(m), tiny = jacobi_floor(m, B.fro2);
+  // 2. the task's rotations on G, accumulated into W.  Round rr applies the
+  // coefficients in slot rr & 1; meanwhile threads 0..31 form the next
+  // round's (from the entries of J^H G J they need, computed as the update
+  // computes them), so that each round takes one barrier.
+  const int npc = nc + (nc & 1);
+  const int nrounds = round == 0 ? npc - 1 : w;
+  // rotation of padded index k in round rr from the current G (entries via
+  // get(i, j)); writes slot sl
+  auto form = [&](int rr, int sl, auto get) {
+    const int k = threadIdx.x;
+    bool isp;
+    const int part = pg_partner(k, rr, round == 0, wI, wJ, w, isp);
+    cd self = cmk(1.0, 0.0), other = cmk(0.0, 0.0);
+    int pj = k;
+    bool act = false;
+    if (part >= 0) {
+      const int p = isp ? k : part, q = isp ? part : k;
+      const double al = get(p, p).re, be = get(q, q).re;
+      const cd gq = get(p, q);
+      const double ga2 = gq.re * gq.re + gq.im * gq.im;
+      if (fmin(al, be) > tiny && (ga2 > tol * tol * (al * be)) && (ga2 > 1e-300)) {
+        const double rga = rsqrt(ga2);
+        const double zeta = (be - al) * (0.5 * rga);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = rsqrt(1.0 + t * t), sn = c * t;
+        const double er = gq.re * rga, ei = -gq.im * rga;      // e = conj(g) / |g|
+        if (isp) {
+          self = cmk(c, 0.0);
+          other = cmk(-sn * er, -sn * ei);                  // J[q][p] = -s e
+        } else {
+          self = cmk(c * er, c * ei);                       // J[q][q] = c e
+          other = cmk(sn, 0.0);                             // J[p][q] = s
+        }
+        pj = part;
+        act = true;
+        s_any = 1;
+      }
+    }
+    s_self[sl][k] = self;
+    s_other[sl][k] = other;
+    s_part[sl][k] = pj;
+    // compact list of the rotated pairs, in order of their first column
+    const unsigned long long bal = __ballot(act && isp);
+    if (act && isp) {
+      const int at = __popcll(bal & ((1ull << k) - 1ull));
+      s_pp[sl][at] = k;
+      s_pq[sl][at] = part;
+    }
+    if (k == 0) s_np[sl] = __popcll(bal);
+  };
+  if (threadIdx.x < PG_N && nrounds > 0)
+    form(0, 0, [&](int i, int j) { return sG[0][i * PG_N + j]; });
+  int cur = 0;
+  for (int rr = 0; rr < nrounds; ++rr) {
+    __syncthreads();
+    const int sl = rr & 1;
+    const cd *G0 = sG[cur];
+    cd *G1 = sG[cur ^ 1];
+    const cd *cs = s_self[sl], *co = s_other[sl];
+    const int *cp = s_part[sl];
+    if (threadIdx.x < PG_N && rr + 1 < nrounds)
+      form(rr + 1, sl ^ 1, [&](int i, int j) {
+        return i <= j ? pg_entry(G0, i, j, cs, co, cp) : cconj(pg_entry(G0, j, i, cs, co, cp));
+      });
+    // G' = J^H G J (upper triangle, mirrored), W' = W J: waves 1.. (wave 0
+    // forms the next round's rotations meanwhile).  The upper triangle is
+    // enumerated as 16 row pairs (i, 31 - i) of 33 entries each.
+    const int ut = (int)threadIdx.x - 64, nut = (int)blockDim.x - 64;
+    if (ut >= 0) {
+#pragma unroll
+      for (int it = 0; it < 3; ++it) {
+        const int e = ut + it * nut;
+        if (e < 528) {
+          const int rp = e / 33, c = e - 33 * rp;
+          const int i = c < 32 - rp ? rp : 31 - rp;
+          const int j = c < 32 - rp ? rp + c : i + (c - (32 - rp));
+          const cd v = pg_entry(G0, i, j, cs, co, cp);
+          G1[i * PG_N + j] = v;
+          G1[j * PG_N + i] = cconj(v);
+        }
+      }
+      const int np = s_np[sl];
+#pragma unroll
+      for (int it = 0; it < 3; ++it) {
+        const int e = ut + it * nut;
+        if (e < PG_N * np) {
+          const int k = e % np, i = e / np;
+          const int pp = s_pp[sl][k], pq = s_pq[sl][k];
+          const cd wp = sW[i * PG_N + pp], wq = sW[i * PG_N + pq];
+          sW[i * PG_N + pp] = pg_fma(wq, co[pp], pg_mul(wp, cs[pp]));
+          sW[i * PG_N + pq] = pg_fma(wp, co[pq], pg_mul(wq, cs[pq]));
+        }
+      }
+    }
+    cur ^= 1;
+  }
+  __syncthreads();
+  if (s_any && threadIdx.x == 0) rf[sweep % 3] = 1;
+  if (!s_any) {                // nothing rotated: the panels in memory are unchanged
+    if (track && threadIdx.x == 0)
+      prec[plo * PANEL_VERSION_MAX + phi] = (pv[plo] << 16) | pv[phi];
+    return;
+  }
+  // 3. X <- X W by 16-row tiles: D[y][j] = sum_k X[y][k] W[k][j]; lane (lr,
+  // lk) feeds row y0 + lr of column k0 + lk and W[k0 + lk][16 jt + lr], and
+  // holds D rows 4 r + lk, column lr of each column tile jt.  A wave reads
+  // every column of its rows before it writes them.
+  cd x[PG_N / 4];
+  int xoff[PG_N / 4];                    // element offset of column 4 s8 + lk, -1: none
+#pragma unroll
+  for (int s8 = 0; s8 < PG_N / 4; ++s8) {
+    const int c = col_of(4 * s8 + lk);
+    xoff[s8] = c >= 0 ? c * m : -1;
+  }
+  auto load_tile = [&](int t0, cd *rx) {
+    const int y = 16 * t0 + lr;
+#pragma unroll
+    for (int s8 = 0; s8 < PG_N / 4; ++s8)
+      rx[s8] = (xoff[s8] >= 0 && y < m) ? A[(unsigned)(xoff[s8] + y)] : cmk(0.0, 0.0);
+  };
+  load_tile(wave, x);
+  const int c0 = col_of(lr), c1 = col_of(16 + lr);
+  for (int t0 = wave; 16 * t0 < m; t0 += nwv) {
+    const int y0 = 16 * t0;
+    cd xn[PG_N / 4];
+    load_tile(t0 + nwv, xn);             // next tile's rows, in flight meanwhile
+    // one column tile at a time (its accumulators and W operands live only
+    // for its own products)
+#pragma unroll 1
+    for (int jt = 0; jt < 2; ++jt) {
+      pg_d4 dr = {0.0, 0.0, 0.0, 0.0}, di = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s8 = 0; s8 < PG_N / 4; ++s8) {
+        const cd wv = sW[(4 * s8 + lk) * PG_N + 16 * jt + lr];
+        dr = pg_mfma(x[s8].re, wv.re, dr);
+        dr = pg_mfma(-x[s8].im, wv.im, dr);
+        di = pg_mfma(x[s8].re, wv.im, di);
+        di = pg_mfma(x[s8].im, wv.re, di);
+      }
+      const int c = jt == 0 ? c0 : c1;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int yo = y0 + 4 * r + lk;
+        if (yo < m && c >= 0) A[(size_t)c * m + yo] = cmk(dr[r], di[r]);
+      }
+    }
+#pragma unroll
+    for (int s8 = 0; s8 < PG_N / 4; ++s8) x[s8] = xn[s8];
+  }
+  if (versioned && threadIdx.x == 0) {
+    if (hasI) ++pv[I];
+    if (hasJ) ++pv[J];
+  }
+}
+
 // Big blocks not yet converged, compacted into the task list of the next
 // panel launches: task_blk[i] = flat index of the i-th still-rotating block,
 // task_pre[i] = its first task (Pp / 2 panel pairs each), task_pre[n] = all
@@ -2175,7 +2588,7 @@ hipError_t launch_svd_panel_step(Layer ly, int step, hipStream_t s) {
   if (ly.mixed)
     hipLaunchKernelGGL(k_panel<cf>, dim3(ly.ntask), dim3(thr), (size_t)ly.panel_lds, s, ly, step);
   else
-    hipLaunchKernelGGL(k_panel<cd>, dim3(ly.ntask), dim3(thr), (size_t)ly.panel_lds, s, ly, step);
+    hipLaunchKernelGGL(k_panel_gram, dim3(ly.ntask), dim3(PG_THREADS), 0, s, ly, step);
   return hipGetLastError();
 }
 
