@@ -2114,24 +2114,29 @@ __device__ __forceinline__ int pg_partner(int k, int rr, bool round0, int wI, in
       pc = npc - 1;
       isp = true;
     } else {
-      const int s1 = (ck - rr + npc - 1) % (npc - 1);
+      // ck, rr < npc - 1: every sum below lies in [0, 2 (npc - 1))
+      const int mod = npc - 1;
+      int s1 = ck - rr + mod;
+      if (s1 >= mod) s1 -= mod;
       if (s1 <= npc / 2 - 1) {
         isp = true;
-        pc = (rr - s1 + npc - 1) % (npc - 1);
+        pc = rr - s1 + mod;
       } else {
-        pc = (rr + (npc - 1 - s1)) % (npc - 1);
+        pc = rr + (mod - s1);
       }
+      if (pc >= mod) pc -= mod;
     }
     return pc < nc ? (pc < wI ? pc : 16 + (pc - wI)) : -1;
   }
+  // k - 16, rr < w here
   if (k < 16) {
     if (k >= wI) return -1;
-    const int u = (k + rr) % w;
+    const int u = k + rr >= w ? k + rr - w : k + rr;
     isp = true;
     return u < wJ ? 16 + u : -1;
   }
   if (k - 16 >= wJ) return -1;
-  const int t = (k - 16 - rr % w + w) % w;
+  const int t = k - 16 - rr < 0 ? k - 16 - rr + w : k - 16 - rr;
   return t < wI ? t : -1;
 }
 
