@@ -133,6 +133,13 @@ __host__ __device__ inline int gram_panel_width(int n) {
 #endif
 constexpr int QR_MIN_COLS = GBS_QR_MIN_COLS;
 
+// In FP64 (esz 16) a block of at least GBS_GRAM_MIN_COLS columns also takes
+// the panel rounds (in Gram form) even when it would fit the one-workgroup
+// Jacobi: its many dependent rounds on one workgroup would otherwise form a
+// chain of their own beside the panel rounds that run anyway.
+#ifndef GBS_GRAM_MIN_COLS
+#define GBS_GRAM_MIN_COLS 48
+#endif
 __host__ __device__ inline void svd_route(int m, int n, int lds_bytes, int qr_ok, int esz,
                                           int &qr, int &big, int &mj) {
   qr = 0;
@@ -141,7 +148,8 @@ __host__ __device__ inline void svd_route(int m, int n, int lds_bytes, int qr_ok
     qr = 1;
     mj = n;
   }
-  big = svd_small_need(mj, n, esz) > (size_t)lds_bytes ? 1 : 0;
+  big = (svd_small_need(mj, n, esz) > (size_t)lds_bytes || (esz == 16 && n >= GBS_GRAM_MIN_COLS))
+            ? 1 : 0;
 }
 
 // Two passes over the charge box of every gate.  The count pass (FILL =
