@@ -414,12 +414,14 @@ def main():
     avg_ms = phase_ms[dom] / launches
     if dom == "svd":
         # one "launch" = the SVD stage of one layer: k_qr_panel and k_qr, the
-        # k_svd_small size classes, k_big_prep, the k_panel steps with their
-        # k_big_count checks and k_big_finish, timed by HIP events on the
-        # library's stream
+        # k_svd_small size classes, k_big_prep, the panel steps (k_panel_gram
+        # in FP64, k_panel in the mixed mode) with their k_big_count checks
+        # and k_big_finish, timed by HIP events on the library's stream.  The
+        # stage runs on the vector ALUs and the FP64 matrix cores, whose dense
+        # peaks are the same 78.6 TFLOP/s
         per_launch = work["svd_flops"] / launches
         achieved = per_launch / (avg_ms * 1e-3) / 1e12
-        roof = {"kernel": "svd stage per layer (k_qr_panel + k_qr + k_svd_small + k_panel steps + k_big_*)",
+        roof = {"kernel": "svd stage per layer (k_qr_panel + k_qr + k_svd_small + panel steps + k_big_*)",
                 "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFS,
                 "traffic": stage_traffic(w.name, args.precision, len(layers)),
