@@ -277,7 +277,8 @@ int mpo_layer_blocks(gbs_mpo *h, int max_blocks, int *out);
  * SVD'd; these knobs only choose which kernels do it, the results agree to
  * rounding).  lds_limit_bytes > 0 lowers the LDS budget below the device's:
  * a block whose Jacobi operand exceeds it takes the multi-workgroup panel
- * rounds.  With qr_enable != 0 a block exceeding it, or with at least 16
+ * rounds (in FP64 so does every block of at least 48 columns).  With
+ * qr_enable != 0 a block exceeding it, or with at least 16
  * columns, is first reduced by a Householder QR with column pivoting;
  * qr_enable = 0 runs every Jacobi on the block itself.  lds_limit_bytes = 0
  * restores the device budget.  Affects layers planned after the call; not

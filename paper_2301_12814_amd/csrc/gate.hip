@@ -14,7 +14,8 @@
 //
 // Kernels, in launch order: k_fock (Fock tables), k_plan (sector planning),
 // k_ctab + k_contract (Theta blocks), k_qr_panel / k_qr (pivoted QR),
-// k_svd_small and the k_panel rounds (one-sided Jacobi), k_big_finish,
+// k_svd_small and the panel rounds (one-sided Jacobi: k_panel_gram in FP64,
+// k_panel in the mixed mode), k_big_finish,
 // k_select (truncation), k_leftvec (kept vectors of QR'd blocks), k_zero +
 // k_scatter (new tensors), k_entropy_layer (EE of the new bonds).
 #include <math.h>
@@ -1206,7 +1207,20 @@ __global__ __launch_bounds__(1024) void k_qr_order(Layer ly) {
 #endif
 constexpr int QRP_THREADS = GBS_QRP_THREADS;
 
-__global__ __launch_bounds__(QRP_THREADS) void k_qr_panel(Layer ly, int lds_bytes) {
+// Blocks of the sketch-pivoted QR (defined below): one thread per column and
+// the panel's reflectors in LDS beside the W tiles.
+#ifndef GBS_QR_SKETCH
+#define GBS_QR_SKETCH 0
+#endif
+constexpr int QS_NB = 8;             // panel width
+constexpr int QS_THREADS = 1024;     // one thread per block column (n <= 1024)
+constexpr int QS_WBYTES = 16 * 16 * QS_NB * 16;   // per-wave W tiles (16 waves)
+__host__ __device__ inline bool qs_fits(int m, int n, int lds_bytes) {
+  return GBS_QR_SKETCH && n >= QS_NB + 4 && n <= QS_THREADS &&
+         (long long)m * QS_NB * 16 + QS_WBYTES <= lds_bytes;
+}
+
+__global__ __launch_bounds__(QRP_THREADS) void k_qr_panel(Layer ly, int lds_bytes, int qs_lds) {
   const int flat = ly.qr_order[blockIdx.x];
   const int g = find_gate_blk(ly.base, ly.ngates, flat);
   const GateBase gb = ly.base[g];
@@ -1214,6 +1228,7 @@ __global__ __launch_bounds__(QRP_THREADS) void k_qr_panel(Layer ly, int lds_byte
   const BlkDesc B = ly.blk[gp.blk0 + (flat - gb.blk)];
   if (!B.comp || !B.qr) return;
   const int m = B.m, n = B.n;
+  if (qs_fits(m, n, qs_lds)) return;                 // k_qr_sketch's block
   const int nb = qr_panel_width(m, n, lds_bytes);
   if (nb < 2) return;
   cd *A = ly.A + gb.e + B.eoff;
@@ -1223,7 +1238,7 @@ __global__ __launch_bounds__(QRP_THREADS) void k_qr_panel(Layer ly, int lds_byte
   qr_write_x(ly.R + gb.r + B.joff, A, m, n);
 }
 
-__global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly, int lds_bytes) {
+__global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly, int lds_bytes, int qs_lds) {
   const int flat = ly.qr_order[blockIdx.x];
   const int g = find_gate_blk(ly.base, ly.ngates, flat);
   const GateBase gb = ly.base[g];
@@ -1236,6 +1251,7 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly, int lds_bytes) {
   int *piv = ly.piv + gp.lst0 + B.svoff;
   extern __shared__ __attribute__((aligned(16))) double s_dyn[];
   if (qr_panel_width(m, n, svd_panel_half(lds_bytes)) >= 2) return;   // k_qr_panel's block
+  if (qs_fits(m, n, qs_lds)) return;                                   // k_qr_sketch's block
   // one column at a time (operands too large for a panel of F in LDS)
   cd *v = reinterpret_cast<cd *>(s_dyn);             // current reflector, m - k entries
   double *cn = reinterpret_cast<double *>(v + m);    // remaining column norms^2
@@ -1382,6 +1398,331 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly, int lds_bytes) {
   qr_write_x(ly.R + gb.r + B.joff, A, m, n);
 }
 
+// ----------------------------------------------------------------------------
+// Householder QR with sketch pivoting, by panels of QS_NB columns (in place of
+// the column pivoting above when GBS_QR_SKETCH is set).  A panel's pivots are
+// the columns a column-pivoted QR of a small random sketch picks: the sketch
+// S = Omega A[k0:, k0:] has QS_P = QS_NB + 4 rows of independent signs (a
+// hash of the matrix row, the sketch row and the panel), and each of its
+// column norms estimates the norm of the remaining column, so that the panel
+// takes the columns of largest remaining norm without a pass over the
+// trailing matrix per column.  The panel is then factored alone (unpivoted
+// Householder: H = I - tau v v^H, v[0] = 1, H^H x = beta e_1 as above), its
+// reflectors are gathered as Q = I - V T V^H (T upper triangular, forward
+// accumulation) and the trailing columns receive Q^H in one step,
+//   A_t <- A_t - V T^H (V^H A_t),
+// computed on the FP64 matrix cores by tiles of 16 columns: the complex
+// products run as real ones with the panel's 8 complex reflectors embedded
+// as 16 real rows (W = V^H A_t: rows Re W, Im W; A_t -= V W': rows (y, re),
+// (y, im)).  The trailing matrix is read three times and written once per
+// panel (sketch, W, update) instead of read once per column.  One workgroup
+// of 1024 threads per block, thread t holding the sketch column of column t.
+// ----------------------------------------------------------------------------
+constexpr int QS_P = QS_NB + 4;      // sketch rows
+
+__device__ __forceinline__ uint32_t qs_mix(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+// sign bits of the sketch drawn for the panel at column k0, for matrix row y:
+// bit r set = entry (r, y) is -1
+__device__ __forceinline__ uint32_t qs_signs(int y, int k0) {
+  return qs_mix((uint32_t)y * 0x9e3779b9u + qs_mix((uint32_t)k0 + 0x632be5abu));
+}
+
+typedef double qs_d4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ qs_d4 qs_mfma(double a, double b, qs_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(QS_THREADS) void k_qr_sketch(Layer ly, int lds_bytes) {
+  const int flat = ly.qr_order[blockIdx.x];
+  const int g = find_gate_blk(ly.base, ly.ngates, flat);
+  const GateBase gb = ly.base[g];
+  const GateParam gp = ly.gates[g];
+  const BlkDesc B = ly.blk[gp.blk0 + (flat - gb.blk)];
+  if (!B.comp || !B.qr) return;
+  const int m = B.m, n = B.n;
+  if (!qs_fits(m, n, lds_bytes)) return;
+  cd *A = ly.A + gb.e + B.eoff;
+  cd *tau = ly.tau + gp.lst0 + B.svoff;
+  int *piv = ly.piv + gp.lst0 + B.svoff;
+  cd *S = ly.R + gb.r + B.joff;            // sketch (QS_P x n) in the block's R region
+  extern __shared__ __attribute__((aligned(16))) double s_dyn[];
+  cd *sW = reinterpret_cast<cd *>(s_dyn);               // [wave][16 columns][QS_NB]
+  cd *sV = sW + 16 * 16 * QS_NB;                        // [row - k0][QS_NB]
+  __shared__ cd s_T[QS_NB * QS_NB], s_vv[QS_NB * QS_NB];
+  __shared__ cd s_x[QS_P], s_y[QS_P];
+  __shared__ double s_bv[16], s_red[16];
+  __shared__ int s_bi[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  if (tid < n) piv[tid] = tid;
+  for (int k0 = 0; k0 < n; k0 += QS_NB) {
+    const int b = min(QS_NB, n - k0), len0 = m - k0;
+    // 0. sketch of the columns [k0, n) over rows [k0, m): S[r][j] = sum_y
+    // Omega[r][y] A[y][j], by tiles of 16 columns (sketch rows in the real
+    // A operand, the real and imaginary parts of A in two products)
+    for (int j0 = k0 + 16 * wave; j0 < n; j0 += 16 * nw) {
+      qs_d4 sr = {0.0, 0.0, 0.0, 0.0}, si = sr;
+      const int j = j0 + lr;
+      const cd *col = A + (size_t)min(j, n - 1) * m;
+      for (int y0 = k0; y0 < m; y0 += 4) {
+        const int y = y0 + lk;
+        const bool in = y < m;
+        const double om = (in && lr < QS_P) ? (((qs_signs(y, k0) >> lr) & 1u) ? -1.0 : 1.0) : 0.0;
+        const cd a = (in && j < n) ? col[y] : cmk(0.0, 0.0);
+        sr = qs_mfma(om, a.re, sr);
+        si = qs_mfma(om, a.im, si);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 4 * q + lk;
+        if (r < QS_P && j < n) S[r + (size_t)QS_P * j] = cmk(sr[q], si[q]);
+      }
+    }
+    __syncthreads();
+    // 1. the panel's pivots: column-pivoted QR of the sketch columns [k0, n),
+    // thread j holding column j
+    cd sk[QS_P];
+#pragma unroll
+    for (int r = 0; r < QS_P; ++r)
+      sk[r] = (tid >= k0 && tid < n) ? S[r + (size_t)QS_P * tid] : cmk(0.0, 0.0);
+    for (int i = 0; i < b; ++i) {
+      const int k = k0 + i;
+      double bv = -1.0;
+      int bi = n;
+      if (tid >= k && tid < n) {
+        double s2 = 0.0;
+#pragma unroll
+        for (int r = 0; r < QS_P; ++r)
+          if (r >= i) s2 += cabs2(sk[r]);
+        bv = s2;
+        bi = tid;
+      }
+      wave_argmax(bv, bi);
+      if (lane == 0) { s_bv[wave] = bv; s_bi[wave] = bi; }
+      __syncthreads();
+      int p;
+      {
+        double bb = s_bv[0];
+        int pp = s_bi[0];
+        for (int w2 = 1; w2 < nw; ++w2)
+          if (s_bv[w2] > bb || (s_bv[w2] == bb && s_bi[w2] < pp)) { bb = s_bv[w2]; pp = s_bi[w2]; }
+        p = pp < n ? pp : k;
+      }
+      if (p != k) {
+        for (int y = tid; y < m; y += blockDim.x) {
+          const cd t = A[(size_t)k * m + y];
+          A[(size_t)k * m + y] = A[(size_t)p * m + y];
+          A[(size_t)p * m + y] = t;
+        }
+        if (tid == p) {
+#pragma unroll
+          for (int r = 0; r < QS_P; ++r) s_x[r] = sk[r];
+        }
+        if (tid == k) {
+#pragma unroll
+          for (int r = 0; r < QS_P; ++r) s_y[r] = sk[r];
+        }
+        if (tid == 0) {
+          const int t = piv[k];
+          piv[k] = piv[p];
+          piv[p] = t;
+        }
+        __syncthreads();
+        if (tid == k) {
+#pragma unroll
+          for (int r = 0; r < QS_P; ++r) sk[r] = s_x[r];
+        }
+        if (tid == p) {
+#pragma unroll
+          for (int r = 0; r < QS_P; ++r) sk[r] = s_y[r];
+        }
+        __syncthreads();
+      }
+      if (tid == k) {
+#pragma unroll
+        for (int r = 0; r < QS_P; ++r) s_x[r] = sk[r];
+      }
+      __syncthreads();
+      // reflector of the sketch column's rows i.. (every thread alike), applied
+      // to the later sketch columns
+      double s2 = 0.0;
+#pragma unroll
+      for (int r = 0; r < QS_P; ++r)
+        if (r > i) s2 += cabs2(s_x[r]);
+      cd ht, hs;
+      double hb;
+      const bool skip = !householder(s_x[i], s2, ht, hs, hb);
+      if (!skip && tid > k && tid < n) {
+        cd dv = sk[i];
+#pragma unroll
+        for (int r = 0; r < QS_P; ++r)
+          if (r > i) cfma(dv, cconj(cmul(s_x[r], hs)), sk[r]);
+        const cd f = cmul(cconj(ht), dv);             // conj(tau) v^H s
+        sk[i] = csub(sk[i], f);
+#pragma unroll
+        for (int r = 0; r < QS_P; ++r)
+          if (r > i) sk[r] = csub(sk[r], cmul(cmul(s_x[r], hs), f));
+      }
+      __syncthreads();
+    }
+    // 2. the panel: unpivoted Householder QR of A[k0:, k0:k0 + b]
+    for (int i = 0; i < b; ++i) {
+      const int k = k0 + i, len = m - k;
+      cd *x = A + (size_t)k * m + k;
+      double s2 = 0.0;
+      for (int y = 1 + tid; y < len; y += blockDim.x) s2 += cabs2(x[y]);
+      s2 = block_sum_keep(s2, s_red);
+      cd h_tau, h_scale;
+      double h_beta;
+      const bool skip = !householder(x[0], s2, h_tau, h_scale, h_beta);
+      if (!skip)
+        for (int y = 1 + tid; y < len; y += blockDim.x) x[y] = cmul(x[y], h_scale);
+      __syncthreads();
+      if (tid == 0) {
+        tau[k] = skip ? cmk(0.0, 0.0) : h_tau;
+        if (!skip) x[0] = cmk(h_beta, 0.0);
+      }
+      const int c = k + 1 + wave;                     // one later panel column per wave
+      if (!skip && c < k0 + b) {
+        cd *a = A + (size_t)c * m + k;
+        double dr = 0.0, di = 0.0;
+        for (int y = lane; y < len; y += 64) {
+          const cd v = y == 0 ? cmk(1.0, 0.0) : x[y];
+          const cd q = cmulc(v, a[y]);
+          dr += q.re;
+          di += q.im;
+        }
+        dr = group_sum<64>(dr);
+        di = group_sum<64>(di);
+        const cd f = cmul(cconj(h_tau), cmk(dr, di));    // conj(tau) v^H a
+        for (int y = lane; y < len; y += 64) {
+          const cd v = y == 0 ? cmk(1.0, 0.0) : x[y];
+          a[y] = csub(a[y], cmul(v, f));
+        }
+      }
+      __syncthreads();
+    }
+    if (k0 + b >= n) break;
+    // 3. V (rows k0.. of the panel's reflectors) into LDS, V^H V and T
+    for (int idx = tid; idx < len0 * QS_NB; idx += blockDim.x) {
+      const int yy = idx / QS_NB, c = idx - QS_NB * yy;
+      cd v = cmk(0.0, 0.0);
+      if (c < b) v = yy > c ? A[(size_t)(k0 + c) * m + k0 + yy] : (yy == c ? cmk(1.0, 0.0) : v);
+      sV[idx] = v;
+    }
+    __syncthreads();
+    for (int pi = wave; pi < b * (b - 1) / 2; pi += nw) {
+      int c1 = 0, rem = pi;
+      while (rem >= b - 1 - c1) { rem -= b - 1 - c1; ++c1; }
+      const int c2 = c1 + 1 + rem;
+      double vr = 0.0, vi = 0.0;
+      for (int yy = c2 + lane; yy < len0; yy += 64) {
+        const cd q = cmulc(sV[yy * QS_NB + c1], sV[yy * QS_NB + c2]);
+        vr += q.re;
+        vi += q.im;
+      }
+      vr = group_sum<64>(vr);
+      vi = group_sum<64>(vi);
+      if (lane == 0) s_vv[c1 * QS_NB + c2] = cmk(vr, vi);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int c = 0; c < QS_NB; ++c)
+        for (int r = 0; r < QS_NB; ++r) s_T[r * QS_NB + c] = cmk(0.0, 0.0);
+      for (int c = 0; c < b; ++c) {
+        const cd tc = tau[k0 + c];
+        for (int r = 0; r < c; ++r) {
+          cd acc = cmk(0.0, 0.0);
+          for (int q = r; q < c; ++q) cfma(acc, s_T[r * QS_NB + q], s_vv[q * QS_NB + c]);
+          s_T[r * QS_NB + c] = cmk(-(tc.re * acc.re - tc.im * acc.im), -(tc.re * acc.im + tc.im * acc.re));
+        }
+        s_T[c * QS_NB + c] = tc;
+      }
+    }
+    __syncthreads();
+    // 4. the trailing columns [k0 + b, n) by tiles of 16 (one wave each)
+    cd *wt = sW + (size_t)wave * 16 * QS_NB;
+    for (int j0 = k0 + b + 16 * wave; j0 < n; j0 += 16 * nw) {
+      const int j = j0 + lr;
+      const bool cj = j < n;
+      cd *col = A + (size_t)min(j, n - 1) * m + k0;
+      // W = V^H A_t: rows c (Re W[c]) and 8 + c (Im W[c]); a step takes rows
+      // yy = y0, y0 + 1 (k = lk: row y0 + lk / 2, real part when lk is even)
+      qs_d4 wd = {0.0, 0.0, 0.0, 0.0};
+      const int cv = lr & 7;
+      const bool imrow = lr >= 8;
+      for (int y0 = 0; y0 < len0; y0 += 2) {
+        const int yy = y0 + (lk >> 1);
+        const bool part = lk & 1;
+        const bool in = yy < len0;
+        const cd v = in ? sV[yy * QS_NB + cv] : cmk(0.0, 0.0);
+        const double av = !imrow ? (part ? v.im : v.re) : (part ? v.re : -v.im);
+        const cd a = (in && cj) ? col[yy] : cmk(0.0, 0.0);
+        wd = qs_mfma(av, part ? a.im : a.re, wd);
+      }
+      // lane (lr, lk) holds Re W[lk], Re W[4 + lk], Im W[lk], Im W[4 + lk] of
+      // column j; W' = T^H W per column through the wave's LDS tile
+      wt[lr * QS_NB + lk] = cmk(wd[0], wd[2]);
+      wt[lr * QS_NB + 4 + lk] = cmk(wd[1], wd[3]);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // the wave's LDS writes before its reads
+      cd w2[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = lk + 4 * h;
+        cd acc = cmk(0.0, 0.0);
+        for (int c2 = 0; c2 <= c; ++c2) cfma(acc, cconj(s_T[c2 * QS_NB + c]), wt[lr * QS_NB + c2]);
+        w2[h] = acc;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      wt[lr * QS_NB + lk] = w2[0];
+      wt[lr * QS_NB + 4 + lk] = w2[1];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      // A_t -= V W' by 8-row tiles: output row R = 2 (yy - yb) + part; step s
+      // takes reflectors 2 s, 2 s + 1 (k = lk: reflector 2 s + lk / 2, the
+      // real part of W' when lk is even)
+      for (int yb = 0; yb < len0; yb += 8) {
+        qs_d4 d;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int R = 4 * q + lk, yy = yb + (R >> 1);
+          const cd a = (yy < len0 && cj) ? col[yy] : cmk(0.0, 0.0);
+          d[q] = (R & 1) ? a.im : a.re;
+        }
+        const int yy = yb + (lr >> 1);
+        const bool opart = lr & 1;
+#pragma unroll
+        for (int s4 = 0; s4 < QS_NB / 2; ++s4) {
+          const int c = 2 * s4 + (lk >> 1);
+          const bool wpart = lk & 1;
+          const cd v = yy < len0 ? sV[yy * QS_NB + c] : cmk(0.0, 0.0);
+          // coefficient of W'[c].(wpart) in output (yy, opart), negated
+          const double av = !opart ? (!wpart ? -v.re : v.im) : (!wpart ? -v.im : -v.re);
+          const cd wv = wt[lr * QS_NB + c];             // B operand: W'[c][column lr]
+          d = qs_mfma(av, wpart ? wv.im : wv.re, d);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int R = 4 * q + lk, yo = yb + (R >> 1);
+          if (yo < len0 && cj) {
+            double *dst = reinterpret_cast<double *>(col + yo);
+            dst[R & 1] = d[q];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  qr_write_x(ly.R + gb.r + B.joff, A, m, n);
+}
+
 hipError_t launch_qr(Layer ly, int max_chi, hipStream_t s) {
   if (ly.total_blocks == 0) return hipSuccess;
   (void)max_chi;
@@ -1390,11 +1731,18 @@ hipError_t launch_qr(Layer ly, int max_chi, hipStream_t s) {
   hipLaunchKernelGGL(k_qr_order, dim3(1), dim3(1024), 0, s, ly);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  const int qs_lds = lb - 2048;                       // beside k_qr_sketch's static LDS
+  if (GBS_QR_SKETCH) {
+    hipLaunchKernelGGL(k_qr_sketch, dim3(ly.total_blocks), dim3(QS_THREADS), (size_t)qs_lds, s, ly,
+                       qs_lds);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_qr_panel, dim3(ly.total_blocks), dim3(QRP_THREADS), (size_t)half, s, ly,
-                     half);
+                     half, qs_lds);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_qr, dim3(ly.total_blocks), dim3(QR_THREADS), (size_t)lb, s, ly, lb);
+  hipLaunchKernelGGL(k_qr, dim3(ly.total_blocks), dim3(QR_THREADS), (size_t)lb, s, ly, lb, qs_lds);
   return hipGetLastError();
 }
 
@@ -2533,6 +2881,8 @@ int svd_lds_bytes() {
     hipFuncSetAttribute((const void *)k_panel<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_panel<cf>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_qr, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    // k_qr_sketch's static LDS exceeds the 2 KB the others leave, so it takes 2 KB less
+    hipFuncSetAttribute((const void *)k_qr_sketch, hipFuncAttributeMaxDynamicSharedMemorySize, b - 2048);
     hipFuncSetAttribute((const void *)k_qr_panel, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_leftvec, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_scatter, hipFuncAttributeMaxDynamicSharedMemorySize, b);
