@@ -1213,13 +1213,18 @@ constexpr int QRP_THREADS = GBS_QRP_THREADS;
 #define GBS_QR_SKETCH 0
 #endif
 constexpr int QS_NB = 8;             // panel width
-constexpr int QS_THREADS = 1024;     // one thread per block column (n <= 1024)
+constexpr int QS_THREADS = QRP_THREADS;   // one thread per block column (n <= 1024)
+static_assert(QS_THREADS == 1024, "the sketch path holds one column per thread");
 constexpr int QS_WBYTES = 16 * 16 * QS_NB * 16;   // per-wave W tiles (16 waves)
 __host__ __device__ inline bool qs_fits(int m, int n, int lds_bytes) {
   return GBS_QR_SKETCH && n >= QS_NB + 4 && n <= QS_THREADS &&
          (long long)m * QS_NB * 16 + QS_WBYTES <= lds_bytes;
 }
 
+__device__ void qr_sketch(cd *A, int m, int n, cd *tau, int *piv, cd *S, double *s_dyn);
+
+// lds_bytes: the column-pivoted path's budget; qs_lds: the sketch path's
+// (the launch provides the larger of the two)
 __global__ __launch_bounds__(QRP_THREADS) void k_qr_panel(Layer ly, int lds_bytes, int qs_lds) {
   const int flat = ly.qr_order[blockIdx.x];
   const int g = find_gate_blk(ly.base, ly.ngates, flat);
@@ -1228,12 +1233,17 @@ __global__ __launch_bounds__(QRP_THREADS) void k_qr_panel(Layer ly, int lds_byte
   const BlkDesc B = ly.blk[gp.blk0 + (flat - gb.blk)];
   if (!B.comp || !B.qr) return;
   const int m = B.m, n = B.n;
-  if (qs_fits(m, n, qs_lds)) return;                 // k_qr_sketch's block
-  const int nb = qr_panel_width(m, n, lds_bytes);
-  if (nb < 2) return;
   cd *A = ly.A + gb.e + B.eoff;
+  cd *tau = ly.tau + gp.lst0 + B.svoff;
+  int *piv = ly.piv + gp.lst0 + B.svoff;
   extern __shared__ __attribute__((aligned(16))) double s_dyn[];
-  qr_blocked(A, m, n, ly.tau + gp.lst0 + B.svoff, ly.piv + gp.lst0 + B.svoff, nb, s_dyn);
+  if (qs_fits(m, n, qs_lds)) {
+    qr_sketch(A, m, n, tau, piv, ly.R + gb.r + B.joff, s_dyn);
+  } else {
+    const int nb = qr_panel_width(m, n, lds_bytes);
+    if (nb < 2) return;
+    qr_blocked(A, m, n, tau, piv, nb, s_dyn);
+  }
   __syncthreads();
   qr_write_x(ly.R + gb.r + B.joff, A, m, n);
 }
@@ -1251,7 +1261,7 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr(Layer ly, int lds_bytes, int 
   int *piv = ly.piv + gp.lst0 + B.svoff;
   extern __shared__ __attribute__((aligned(16))) double s_dyn[];
   if (qr_panel_width(m, n, svd_panel_half(lds_bytes)) >= 2) return;   // k_qr_panel's block
-  if (qs_fits(m, n, qs_lds)) return;                                   // k_qr_sketch's block
+  if (qs_fits(m, n, qs_lds)) return;                                   // sketch-pivoted in k_qr_panel
   // one column at a time (operands too large for a panel of F in LDS)
   cd *v = reinterpret_cast<cd *>(s_dyn);             // current reflector, m - k entries
   double *cn = reinterpret_cast<double *>(v + m);    // remaining column norms^2
@@ -1439,20 +1449,8 @@ __device__ __forceinline__ qs_d4 qs_mfma(double a, double b, qs_d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-__global__ __launch_bounds__(QS_THREADS) void k_qr_sketch(Layer ly, int lds_bytes) {
-  const int flat = ly.qr_order[blockIdx.x];
-  const int g = find_gate_blk(ly.base, ly.ngates, flat);
-  const GateBase gb = ly.base[g];
-  const GateParam gp = ly.gates[g];
-  const BlkDesc B = ly.blk[gp.blk0 + (flat - gb.blk)];
-  if (!B.comp || !B.qr) return;
-  const int m = B.m, n = B.n;
-  if (!qs_fits(m, n, lds_bytes)) return;
-  cd *A = ly.A + gb.e + B.eoff;
-  cd *tau = ly.tau + gp.lst0 + B.svoff;
-  int *piv = ly.piv + gp.lst0 + B.svoff;
-  cd *S = ly.R + gb.r + B.joff;            // sketch (QS_P x n) in the block's R region
-  extern __shared__ __attribute__((aligned(16))) double s_dyn[];
+__device__ void qr_sketch(cd *A, int m, int n, cd *tau, int *piv, cd *S, double *s_dyn) {
+  // S: the sketch (QS_P x n), in the block's R region
   cd *sW = reinterpret_cast<cd *>(s_dyn);               // [wave][16 columns][QS_NB]
   cd *sV = sW + 16 * 16 * QS_NB;                        // [row - k0][QS_NB]
   __shared__ cd s_T[QS_NB * QS_NB], s_vv[QS_NB * QS_NB];
@@ -1719,8 +1717,6 @@ __global__ __launch_bounds__(QS_THREADS) void k_qr_sketch(Layer ly, int lds_byte
     }
     __syncthreads();
   }
-  __syncthreads();
-  qr_write_x(ly.R + gb.r + B.joff, A, m, n);
 }
 
 hipError_t launch_qr(Layer ly, int max_chi, hipStream_t s) {
@@ -1731,15 +1727,10 @@ hipError_t launch_qr(Layer ly, int max_chi, hipStream_t s) {
   hipLaunchKernelGGL(k_qr_order, dim3(1), dim3(1024), 0, s, ly);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int qs_lds = lb - 2048;                       // beside k_qr_sketch's static LDS
-  if (GBS_QR_SKETCH) {
-    hipLaunchKernelGGL(k_qr_sketch, dim3(ly.total_blocks), dim3(QS_THREADS), (size_t)qs_lds, s, ly,
-                       qs_lds);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k_qr_panel, dim3(ly.total_blocks), dim3(QRP_THREADS), (size_t)half, s, ly,
-                     half, qs_lds);
+  // the sketch path's static LDS exceeds the 2 KB the others leave
+  const int qs_lds = lb - 2048;
+  hipLaunchKernelGGL(k_qr_panel, dim3(ly.total_blocks), dim3(QRP_THREADS),
+                     (size_t)(GBS_QR_SKETCH ? qs_lds : half), s, ly, half, qs_lds);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_qr, dim3(ly.total_blocks), dim3(QR_THREADS), (size_t)lb, s, ly, lb, qs_lds);
@@ -2411,11 +2402,13 @@ __global__ __launch_bounds__(PANEL_THREADS) void k_panel(Layer ly, int step) {
 // exact arithmetic the rotations are those of the column passes; G holds the
 // same inner products (each rounded once per update instead of recomputed),
 // and the final pass with no rotation decides convergence on a G formed
-// afresh from the columns.  LDS: G (double-buffered) and W, 49 KB, so three
-// tasks share a CU.
+// afresh from the columns.  LDS: G double-buffered, 33 KB; W lives in the
+// registers of the three updating waves during the rotations and passes
+// through LDS once before the product, so four tasks share a CU.
 // ----------------------------------------------------------------------------
-constexpr int PG_THREADS = 256;
+constexpr int PG_THREADS = 256;     // wave 0 forms rotations, waves 1..3 update
 constexpr int PG_N = 32;
+constexpr int PG_WROWS = 6;         // rows of W per updating half-wave (6 x 6 >= 32)
 typedef double pg_d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ pg_d4 pg_mfma(double a, double b, pg_d4 c) {
@@ -2496,7 +2489,7 @@ __device__ __forceinline__ int pg_partner(int k, int rr, bool round0, int wI, in
   return t < wI ? t : -1;
 }
 
-__global__ __launch_bounds__(PG_THREADS, 3) void k_panel_gram(Layer ly, int step) {
+__global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step) {
   const int task = blockIdx.x;
   int lo = 0, hi = ly.nact;
   while (hi - lo > 1) {
@@ -2542,12 +2535,9 @@ __global__ __launch_bounds__(PG_THREADS, 3) void k_panel_gram(Layer ly, int step
   const int j0 = hasJ ? J * w : 0, wJ = hasJ ? min(w, n - J * w) : 0;
   const int nc = wI + wJ;
   cd *A = jacobi_operand(ly, ly.base[g], B);
-  __shared__ cd sG[2][PG_N * PG_N];      // G[i][j] at i * PG_N + j
-  __shared__ cd sW[PG_N * PG_N];         // W[i][j] at i * PG_N + j
+  __shared__ cd sG[2][PG_N * PG_N];      // G[i][j] at i * PG_N + j; W before the product
   __shared__ cd s_self[2][PG_N], s_other[2][PG_N];   // J[i][i], J[partner(i)][i]
   __shared__ int s_part[2][PG_N];        // partner of i in the round (i itself: none)
-  __shared__ int s_pp[2][PG_N / 2], s_pq[2][PG_N / 2];   // the round's rotated pairs
-  __shared__ int s_np[2];
   __shared__ int s_any;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -2605,10 +2595,10 @@ __global__ __launch_bounds__(PG_THREADS, 3) void k_panel_gram(Layer ly, int step
         b[u] = b2[u];
       }
     }
-    // partials of waves 1, 2 in sG[1] and sW, of wave 3 in sG[0], at the
-    // tiles' own positions (upper blocks); wave 0 adds them in wave order
-    if (wave > 0) {
-      cd *dst = wave == 1 ? sG[1] : wave == 2 ? sW : sG[0];
+    // the four partial Grams at the tiles' own positions (upper blocks):
+    // G = (v0 + v1) + (v2 + v3), waves 1 and 3 through sG[1] and sG[0],
+    // then wave 2's sum through sG[1]
+    auto put = [&](cd *dst) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 4 * r + lk, j = lr;
@@ -2616,19 +2606,39 @@ __global__ __launch_bounds__(PG_THREADS, 3) void k_panel_gram(Layer ly, int step
         dst[i * PG_N + 16 + j] = cmk(br[r], bi[r]);
         dst[(16 + i) * PG_N + 16 + j] = cmk(cr[r], ci[r]);
       }
-    }
-    __syncthreads();
-    if (wave == 0) {
+    };
+    auto add = [&](const cd *src) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 4 * r + lk, j = lr;
-        const int pos[3] = {i * PG_N + j, i * PG_N + 16 + j, (16 + i) * PG_N + 16 + j};
+        const cd pa = src[i * PG_N + j], pb = src[i * PG_N + 16 + j],
+                 pc = src[(16 + i) * PG_N + 16 + j];
+        ar[r] += pa.re;
+        ai[r] += pa.im;
+        br[r] += pb.re;
+        bi[r] += pb.im;
+        cr[r] += pc.re;
+        ci[r] += pc.im;
+      }
+    };
+    if (wave == 1) put(sG[1]);
+    if (wave == 3) put(sG[0]);
+    __syncthreads();
+    if (wave == 0) add(sG[1]);
+    if (wave == 2) add(sG[0]);
+    __syncthreads();
+    if (wave == 2) put(sG[1]);
+    __syncthreads();
+    if (wave == 0) {
+      add(sG[1]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * r + lk, j = lr;
         const double vr0[3] = {ar[r], br[r], cr[r]}, vi0[3] = {ai[r], bi[r], ci[r]};
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
-          const cd p1 = sG[1][pos[t]], p2 = sW[pos[t]], p3 = sG[0][pos[t]];
-          const double vr = ((vr0[t] + p1.re) + p2.re) + p3.re;
-          double vi = ((vi0[t] + p1.im) + p2.im) + p3.im;
+          const double vr = vr0[t];
+          double vi = vi0[t];
           const int ri = t == 2 ? 16 + i : i, cj = t == 0 ? j : 16 + j;
           if (t == 1) {
             sG[0][ri * PG_N + cj] = cmk(vr, vi);
@@ -2643,8 +2653,15 @@ __global__ __launch_bounds__(PG_THREADS, 3) void k_panel_gram(Layer ly, int step
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < PG_N * PG_N; e += blockDim.x)
-    sW[e] = cmk(e / PG_N == e % PG_N ? 1.0 : 0.0, 0.0);
+  // W = J_1 J_2 ... in registers: updating half-wave h = (thread - 64) / 32
+  // holds rows h + 6 jr (jr < PG_WROWS; rows past 31 stay zero) of column
+  // thread % 32
+  static_assert(PG_THREADS == 256, "three updating waves hold W");
+  const int ut = (int)threadIdx.x - 64;
+  const int wh = ut >= 0 ? ut >> 5 : 0, wk = threadIdx.x & 31;
+  cd wreg[PG_WROWS];
+#pragma unroll
+  for (int jr = 0; jr < PG_WROWS; ++jr) wreg[jr] = cmk(wh + 6 * jr == wk ? 1.0 : 0.0, 0.0);
   if (threadIdx.x == 0) s_any = 0;
   const double tol = jacobi_tol(m), tiny = jacobi_floor(m, B.fro2);
   // 2. the task's rotations on G, accumulated into W.  Round rr applies the
@@ -2661,7 +2678,6 @@ __global__ __launch_bounds__(PG_THREADS, 3) void k_panel_gram(Layer ly, int step
     const int part = pg_partner(k, rr, round == 0, wI, wJ, w, isp);
     cd self = cmk(1.0, 0.0), other = cmk(0.0, 0.0);
     int pj = k;
-    bool act = false;
     if (part >= 0) {
       const int p = isp ? k : part, q = isp ? part : k;
       const double al = get(p, p).re, be = get(q, q).re;
@@ -2681,21 +2697,12 @@ __global__ __launch_bounds__(PG_THREADS, 3) void k_panel_gram(Layer ly, int step
           other = cmk(sn, 0.0);                             // J[p][q] = s
         }
         pj = part;
-        act = true;
         s_any = 1;
       }
     }
     s_self[sl][k] = self;
     s_other[sl][k] = other;
     s_part[sl][k] = pj;
-    // compact list of the rotated pairs, in order of their first column
-    const unsigned long long bal = __ballot(act && isp);
-    if (act && isp) {
-      const int at = __popcll(bal & ((1ull << k) - 1ull));
-      s_pp[sl][at] = k;
-      s_pq[sl][at] = part;
-    }
-    if (k == 0) s_np[sl] = __popcll(bal);
   };
   if (threadIdx.x < PG_N && nrounds > 0)
     form(0, 0, [&](int i, int j) { return sG[0][i * PG_N + j]; });
@@ -2714,7 +2721,7 @@ __global__ __launch_bounds__(PG_THREADS, 3) void k_panel_gram(Layer ly, int step
     // G' = J^H G J (upper triangle, mirrored), W' = W J: waves 1.. (wave 0
     // forms the next round's rotations meanwhile).  The upper triangle is
     // enumerated as 16 row pairs (i, 31 - i) of 33 entries each.
-    const int ut = (int)threadIdx.x - 64, nut = (int)blockDim.x - 64;
+    const int nut = (int)blockDim.x - 64;
     if (ut >= 0) {
 #pragma unroll
       for (int it = 0; it < 3; ++it) {
@@ -2728,17 +2735,15 @@ __global__ __launch_bounds__(PG_THREADS, 3) void k_panel_gram(Layer ly, int step
           G1[j * PG_N + i] = cconj(v);
         }
       }
-      const int np = s_np[sl];
+      // column wk of W: W[i][wk] self[wk] + W[i][partner] other[wk], the
+      // partner's entry from the lane holding it (same half-wave, same row)
+      const int pk = cp[wk];
+      const cd sk = cs[wk], ok = co[wk];
+      const int src = (threadIdx.x & 32) | pk;
 #pragma unroll
-      for (int it = 0; it < 3; ++it) {
-        const int e = ut + it * nut;
-        if (e < PG_N * np) {
-          const int k = e % np, i = e / np;
-          const int pp = s_pp[sl][k], pq = s_pq[sl][k];
-          const cd wp = sW[i * PG_N + pp], wq = sW[i * PG_N + pq];
-          sW[i * PG_N + pp] = pg_fma(wq, co[pp], pg_mul(wp, cs[pp]));
-          sW[i * PG_N + pq] = pg_fma(wp, co[pq], pg_mul(wq, cs[pq]));
-        }
+      for (int jr = 0; jr < PG_WROWS; ++jr) {
+        const cd wq = cmk(__shfl(wreg[jr].re, src), __shfl(wreg[jr].im, src));
+        if (pk != wk) wreg[jr] = pg_fma(wq, ok, pg_mul(wreg[jr], sk));
       }
     }
     cur ^= 1;
@@ -2750,6 +2755,13 @@ __global__ __launch_bounds__(PG_THREADS, 3) void k_panel_gram(Layer ly, int step
       prec[plo * PANEL_VERSION_MAX + phi] = (pv[plo] << 16) | pv[phi];
     return;
   }
+  cd *sW = sG[0];              // W[i][j] at i * PG_N + j (G is no longer needed)
+  if (ut >= 0) {
+#pragma unroll
+    for (int jr = 0; jr < PG_WROWS; ++jr)
+      if (wh + 6 * jr < PG_N) sW[(wh + 6 * jr) * PG_N + wk] = wreg[jr];
+  }
+  __syncthreads();
   // 3. X <- X W by 16-row tiles: D[y][j] = sum_k X[y][k] W[k][j]; lane (lr,
   // lk) feeds row y0 + lr of column k0 + lk and W[k0 + lk][16 jt + lr], and
   // holds D rows 4 r + lk, column lr of each column tile jt.  A wave reads
@@ -2881,9 +2893,8 @@ int svd_lds_bytes() {
     hipFuncSetAttribute((const void *)k_panel<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_panel<cf>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_qr, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    // k_qr_sketch's static LDS exceeds the 2 KB the others leave, so it takes 2 KB less
-    hipFuncSetAttribute((const void *)k_qr_sketch, hipFuncAttributeMaxDynamicSharedMemorySize, b - 2048);
-    hipFuncSetAttribute((const void *)k_qr_panel, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    // k_qr_panel's sketch path has more static LDS than the 2 KB the others leave
+    hipFuncSetAttribute((const void *)k_qr_panel, hipFuncAttributeMaxDynamicSharedMemorySize, b - 2048);
     hipFuncSetAttribute((const void *)k_leftvec, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_scatter, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     hipFuncSetAttribute((const void *)k_big_finish, hipFuncAttributeMaxDynamicSharedMemorySize, b);
