@@ -132,7 +132,7 @@ struct Engine {
   DBuf<double> d_sv;
   DBuf<unsigned long long> d_uval, d_ukey;
   DBuf<cd> d_A, d_A0, d_R, d_U, d_V, d_tau;
-  DBuf<int> d_rotf, d_tasks, d_qord, d_pver;
+  DBuf<int> d_rotf, d_tasks, d_qord, d_bord, d_pver;
   DBuf<int> d_active;
   DBuf<int> d_eng_err;
   int *h_small = nullptr;          // pinned: [1] engine error word, [2..3] rotating blocks / tasks
@@ -282,6 +282,7 @@ void engine_destroy(Engine &E) {
   E.d_rotf.release();
   E.d_tasks.release();
   E.d_qord.release();
+  E.d_bord.release();
   E.d_pver.release();
   E.d_active.release();
   E.d_eng_err.release();
@@ -655,6 +656,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
   long long max_blkb = 1;
   for (const Chunk &chk : chunks) max_blkb = std::max<long long>(max_blkb, chk.blkb);
   HIPCHK(E.d_qord.ensure((size_t)max_blkb));
+  HIPCHK(E.d_bord.ensure((size_t)std::max(need.bigb, 1)));
   HIPCHK(E.d_pver.ensure((size_t)panel_version_ints() * std::max(need.bigb, 1)));
   for (const Chunk &chk : chunks) {
     const int c0 = chk.c0, c1 = chk.c1, ng = c1 - c0;
@@ -688,6 +690,7 @@ int engine_apply(Engine &E, const std::vector<GateParam> &gates, bool check_inst
     C.tau = E.d_tau.p;
     C.piv = E.d_piv.p;
     C.qr_order = E.d_qord.p;
+    C.big_order = E.d_bord.p;
     C.pver = E.d_pver.p;
     C.rotf = E.d_rotf.p;
     C.active = E.d_active.p;

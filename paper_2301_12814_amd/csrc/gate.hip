@@ -2538,6 +2538,7 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
   __shared__ cd sG[2][PG_N * PG_N];      // G[i][j] at i * PG_N + j; W before the product
   __shared__ cd s_self[2][PG_N], s_other[2][PG_N];   // J[i][i], J[partner(i)][i]
   __shared__ int s_part[2][PG_N];        // partner of i in the round (i itself: none)
+  __shared__ int s_rot[2];               // the round rotates some pair
   __shared__ int s_any;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -2703,6 +2704,8 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
     s_self[sl][k] = self;
     s_other[sl][k] = other;
     s_part[sl][k] = pj;
+    const unsigned long long bal = __ballot(pj != k);
+    if (k == 0) s_rot[sl] = bal != 0ull;
   };
   if (threadIdx.x < PG_N && nrounds > 0)
     form(0, 0, [&](int i, int j) { return sG[0][i * PG_N + j]; });
@@ -2720,9 +2723,12 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
       });
     // G' = J^H G J (upper triangle, mirrored), W' = W J: waves 1.. (wave 0
     // forms the next round's rotations meanwhile).  The upper triangle is
-    // enumerated as 16 row pairs (i, 31 - i) of 33 entries each.
+    // enumerated as 16 row pairs (i, 31 - i) of 33 entries each.  A round
+    // without a rotation leaves G and W as they are (J = I: the update would
+    // copy them exactly), and G stays in its buffer.
     const int nut = (int)blockDim.x - 64;
-    if (ut >= 0) {
+    const bool rot = s_rot[sl] != 0;
+    if (ut >= 0 && rot) {
 #pragma unroll
       for (int it = 0; it < 3; ++it) {
         const int e = ut + it * nut;
@@ -2746,7 +2752,7 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
         if (pk != wk) wreg[jr] = pg_fma(wq, ok, pg_mul(wreg[jr], sk));
       }
     }
-    cur ^= 1;
+    if (rot) cur ^= 1;
   }
   __syncthreads();
   if (s_any && threadIdx.x == 0) rf[sweep % 3] = 1;
@@ -2814,6 +2820,35 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
   }
 }
 
+// Big blocks by operand rows, largest first (bucketed by log2 of the rows):
+// the panel launches lay their tasks out in this order, so the longest tasks
+// start first and the short ones fill the launch's tail.  A block's results
+// do not depend on where its tasks sit in a launch.
+__global__ __launch_bounds__(1024) void k_big_order(Layer ly) {
+  __shared__ int s_cnt[QR_ORDER_BUCKETS], s_off[QR_ORDER_BUCKETS];
+  for (int i = threadIdx.x; i < QR_ORDER_BUCKETS; i += blockDim.x) s_cnt[i] = 0;
+  __syncthreads();
+  auto bucket = [&](int k) -> int {
+    int g, bi;
+    big_block_of(ly, k, g, bi);
+    const BlkDesc &B = ly.blk[ly.gates[g].blk0 + bi];
+    const int b = (int)(8.0 * log2(fmax((double)B.mj, 1.0)));
+    return QR_ORDER_BUCKETS - 1 - min(b, QR_ORDER_BUCKETS - 1);
+  };
+  for (int k = threadIdx.x; k < ly.total_big; k += blockDim.x) atomicAdd(&s_cnt[bucket(k)], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int b = 0; b < QR_ORDER_BUCKETS; ++b) {
+      s_off[b] = acc;
+      acc += s_cnt[b];
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < ly.total_big; k += blockDim.x)
+    ly.big_order[atomicAdd(&s_off[bucket(k)], 1)] = k;
+}
+
 // Big blocks not yet converged, compacted into the task list of the next
 // panel launches: task_blk[i] = flat index of the i-th still-rotating block,
 // task_pre[i] = its first task (Pp / 2 panel pairs each), task_pre[n] = all
@@ -2825,9 +2860,9 @@ __global__ __launch_bounds__(1024) void k_big_count(Layer ly, int last, int next
   __shared__ int s_iscan[17];
   int nb = 0, nt = 0;
   for (int b0 = 0; b0 < ly.total_big; b0 += blockDim.x) {
-    const int k = b0 + threadIdx.x;
+    const int k = b0 + threadIdx.x < ly.total_big ? ly.big_order[b0 + threadIdx.x] : -1;
     int act = 0, tasks = 0;
-    if (k < ly.total_big && !ly.rotf[4 * (size_t)k + 3]) {
+    if (k >= 0 && !ly.rotf[4 * (size_t)k + 3]) {
       int g, bi;
       big_block_of(ly, k, g, bi);
       const BlkDesc &B = ly.blk[ly.gates[g].blk0 + bi];
@@ -2932,6 +2967,9 @@ hipError_t launch_svd_small(Layer ly, hipStream_t s) {
 hipError_t launch_svd_big_prep(Layer ly, hipStream_t s) {
   if (ly.total_big == 0) return hipSuccess;
   hipLaunchKernelGGL(k_big_prep, dim3(ly.total_big), dim3(256), 0, s, ly);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_big_order, dim3(1), dim3(1024), 0, s, ly);
   return hipGetLastError();
 }
 

@@ -116,6 +116,7 @@ struct Layer {
   int *task_blk;     // flat indices of the still-rotating big blocks
   int *task_pre;     // first panel task of each (task_pre[nact] = all tasks)
   int *qr_order;     // total_blocks: launch order of the QR workgroups (largest first)
+  int *big_order;    // total_big: big blocks by operand rows, largest first (panel tasks)
   int *pver;         // per big block: panel versions and pair verification records
                      // (panel_version_ints() each)
   int nact, ntask;   // host copies of active[0], active[1] for the panel launches
