@@ -2576,11 +2576,12 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
       load(y0 + 4 * GB, a2, b2);
 #pragma unroll
       for (int u = 0; u < GB; ++u) {
-        // (I, I): conj(a) a; (I, J): conj(a) b; (J, J): conj(b) b
+        // (I, I): conj(a) a; (I, J): conj(a) b; (J, J): conj(b) b.  The
+        // diagonal blocks' imaginary parts are M - M^T with M = Re^T Im, so
+        // ai and ci accumulate M alone (ten products per step, not twelve)
         ar = pg_mfma(a[u].re, a[u].re, ar);
         ar = pg_mfma(a[u].im, a[u].im, ar);
         ai = pg_mfma(a[u].re, a[u].im, ai);
-        ai = pg_mfma(-a[u].im, a[u].re, ai);
         br = pg_mfma(a[u].re, b[u].re, br);
         br = pg_mfma(a[u].im, b[u].im, br);
         bi = pg_mfma(a[u].re, b[u].im, bi);
@@ -2588,7 +2589,6 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
         cr = pg_mfma(b[u].re, b[u].re, cr);
         cr = pg_mfma(b[u].im, b[u].im, cr);
         ci = pg_mfma(b[u].re, b[u].im, ci);
-        ci = pg_mfma(-b[u].im, b[u].re, ci);
       }
 #pragma unroll
       for (int u = 0; u < GB; ++u) {
@@ -2632,10 +2632,21 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
     __syncthreads();
     if (wave == 0) {
       add(sG[1]);
+      // M of the two diagonal blocks through sG[1] (read above by this wave
+      // only): their imaginary parts are M[i][j] - M[j][i]
+      double *sm = reinterpret_cast<double *>(sG[1]);      // [2][16][16]
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = 4 * r + lk, j = lr;
-        const double vr0[3] = {ar[r], br[r], cr[r]}, vi0[3] = {ai[r], bi[r], ci[r]};
+        sm[i * 16 + j] = ai[r];
+        sm[256 + i * 16 + j] = ci[r];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * r + lk, j = lr;
+        const double vr0[3] = {ar[r], br[r], cr[r]},
+                     vi0[3] = {ai[r] - sm[j * 16 + i], bi[r], ci[r] - sm[256 + j * 16 + i]};
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
           const double vr = vr0[t];
@@ -2795,20 +2806,21 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
     // for its own products)
 #pragma unroll 1
     for (int jt = 0; jt < 2; ++jt) {
-      pg_d4 dr = {0.0, 0.0, 0.0, 0.0}, di = {0.0, 0.0, 0.0, 0.0};
+      // three real products (Gauss): t1 = Re X Re W, t2 = Im X Im W,
+      // t3 = (Re X + Im X)(Re W + Im W); D = (t1 - t2) + i (t3 - t1 - t2)
+      pg_d4 t1 = {0.0, 0.0, 0.0, 0.0}, t2 = t1, t3 = t1;
 #pragma unroll
       for (int s8 = 0; s8 < PG_N / 4; ++s8) {
         const cd wv = sW[(4 * s8 + lk) * PG_N + 16 * jt + lr];
-        dr = pg_mfma(x[s8].re, wv.re, dr);
-        dr = pg_mfma(-x[s8].im, wv.im, dr);
-        di = pg_mfma(x[s8].re, wv.im, di);
-        di = pg_mfma(x[s8].im, wv.re, di);
+        t1 = pg_mfma(x[s8].re, wv.re, t1);
+        t2 = pg_mfma(x[s8].im, wv.im, t2);
+        t3 = pg_mfma(x[s8].re + x[s8].im, wv.re + wv.im, t3);
       }
       const int c = jt == 0 ? c0 : c1;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int yo = y0 + 4 * r + lk;
-        if (yo < m && c >= 0) A[(size_t)c * m + yo] = cmk(dr[r], di[r]);
+        if (yo < m && c >= 0) A[(size_t)c * m + yo] = cmk(t1[r] - t2[r], (t3[r] - t1[r]) - t2[r]);
       }
     }
 #pragma unroll
