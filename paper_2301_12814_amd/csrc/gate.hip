@@ -2539,6 +2539,7 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
   __shared__ cd s_self[2][PG_N], s_other[2][PG_N];   // J[i][i], J[partner(i)][i]
   __shared__ int s_part[2][PG_N];        // partner of i in the round (i itself: none)
   __shared__ int s_rot[2];               // the round rotates some pair
+  __shared__ unsigned s_touch;           // padded indices rotated in some round
   __shared__ int s_any;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -2674,7 +2675,10 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
   cd wreg[PG_WROWS];
 #pragma unroll
   for (int jr = 0; jr < PG_WROWS; ++jr) wreg[jr] = cmk(wh + 6 * jr == wk ? 1.0 : 0.0, 0.0);
-  if (threadIdx.x == 0) s_any = 0;
+  if (threadIdx.x == 0) {
+    s_any = 0;
+    s_touch = 0u;
+  }
   const double tol = jacobi_tol(m), tiny = jacobi_floor(m, B.fro2);
   // 2. the task's rotations on G, accumulated into W.  Round rr applies the
   // coefficients in slot rr & 1; meanwhile threads 0..31 form the next
@@ -2716,7 +2720,10 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
     s_other[sl][k] = other;
     s_part[sl][k] = pj;
     const unsigned long long bal = __ballot(pj != k);
-    if (k == 0) s_rot[sl] = bal != 0ull;
+    if (k == 0) {
+      s_rot[sl] = bal != 0ull;
+      s_touch |= (unsigned)bal;
+    }
   };
   if (threadIdx.x < PG_N && nrounds > 0)
     form(0, 0, [&](int i, int j) { return sG[0][i * PG_N + j]; });
@@ -2782,12 +2789,16 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
   // 3. X <- X W by 16-row tiles: D[y][j] = sum_k X[y][k] W[k][j]; lane (lr,
   // lk) feeds row y0 + lr of column k0 + lk and W[k0 + lk][16 jt + lr], and
   // holds D rows 4 r + lk, column lr of each column tile jt.  A wave reads
-  // every column of its rows before it writes them.
+  // every column of its rows before it writes them.  W is a product of
+  // rotations of the touched indices, so an untouched column of X is left
+  // as it is (not read, not multiplied, not written) and takes no part in
+  // the touched ones.
+  const unsigned touch = s_touch;
   cd x[PG_N / 4];
   int xoff[PG_N / 4];                    // element offset of column 4 s8 + lk, -1: none
 #pragma unroll
   for (int s8 = 0; s8 < PG_N / 4; ++s8) {
-    const int c = col_of(4 * s8 + lk);
+    const int c = ((touch >> (4 * s8 + lk)) & 1u) ? col_of(4 * s8 + lk) : -1;
     xoff[s8] = c >= 0 ? c * m : -1;
   }
   auto load_tile = [&](int t0, cd *rx) {
@@ -2797,7 +2808,8 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
       rx[s8] = (xoff[s8] >= 0 && y < m) ? A[(unsigned)(xoff[s8] + y)] : cmk(0.0, 0.0);
   };
   load_tile(wave, x);
-  const int c0 = col_of(lr), c1 = col_of(16 + lr);
+  const int c0 = ((touch >> lr) & 1u) ? col_of(lr) : -1;
+  const int c1 = ((touch >> (16 + lr)) & 1u) ? col_of(16 + lr) : -1;
   for (int t0 = wave; 16 * t0 < m; t0 += nwv) {
     const int y0 = 16 * t0;
     cd xn[PG_N / 4];
@@ -2806,11 +2818,13 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
     // for its own products)
 #pragma unroll 1
     for (int jt = 0; jt < 2; ++jt) {
+      if (((touch >> (16 * jt)) & 0xffffu) == 0u) continue;
       // three real products (Gauss): t1 = Re X Re W, t2 = Im X Im W,
       // t3 = (Re X + Im X)(Re W + Im W); D = (t1 - t2) + i (t3 - t1 - t2)
       pg_d4 t1 = {0.0, 0.0, 0.0, 0.0}, t2 = t1, t3 = t1;
 #pragma unroll
       for (int s8 = 0; s8 < PG_N / 4; ++s8) {
+        if (((touch >> (4 * s8)) & 0xfu) == 0u) continue;
         const cd wv = sW[(4 * s8 + lk) * PG_N + 16 * jt + lr];
         t1 = pg_mfma(x[s8].re, wv.re, t1);
         t2 = pg_mfma(x[s8].im, wv.im, t2);
@@ -2827,8 +2841,8 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
     for (int s8 = 0; s8 < PG_N / 4; ++s8) x[s8] = xn[s8];
   }
   if (versioned && threadIdx.x == 0) {
-    if (hasI) ++pv[I];
-    if (hasJ) ++pv[J];
+    if (hasI && (touch & 0xffffu)) ++pv[I];
+    if (hasJ && (touch >> 16)) ++pv[J];
   }
 }
 
