@@ -35,7 +35,7 @@ FP64_VECTOR_PEAK_TFS = 78.6      # 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
 FP64_MFMA_PEAK_TFS = 78.6
 
 
-def cpu_baseline(chis=(32, 48, 64), budget_s: float = 30.0):
+def cpu_baseline(chis=(48, 64, 96), budget_s: float = 30.0):
     """Dense FP64 oracle on this host: one mid-chain gate of the large
     workload's per-mode state (r=0.9, eta=0.3, d=8) on a 12-mode chain whose
     bonds are full at each chi (the dense two-site tensor is (64 chi)^2).
@@ -336,7 +336,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--layers", type=int, default=0, help="limit layers per step (debug)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-chis", default="32,48,64",
+    ap.add_argument("--cpu-chis", default="48,64,96",
                     help="bond dimensions of the oracle timing fit (cpu_baseline)")
     ap.add_argument("--batch", type=int, default=256, help="instances (workload batch)")
     ap.add_argument("--requests", type=int, default=200, help="requests (workload serve)")

@@ -2445,6 +2445,13 @@ __device__ __forceinline__ cd pg_entry(const cd *G, int i, int j, const cd *self
   return v;
 }
 
+// Whether the pair with al = |x_p|^2, be = |x_q|^2, g = x_p^H x_q rotates
+// (the tests of the column passes).
+__device__ __forceinline__ bool pg_active(double al, double be, cd gq, double tol, double tiny) {
+  const double ga2 = gq.re * gq.re + gq.im * gq.im;
+  return fmin(al, be) > tiny && (ga2 > tol * tol * (al * be)) && (ga2 > 1e-300);
+}
+
 // Partner of padded index k in inner round rr of a task (round 0: the
 // round-robin pairs of the compact columns, I's then J's; other rounds: the
 // cross pairs (t, wI + (t + rr) mod w)); isp: k is the pair's first column.
@@ -2540,9 +2547,11 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
   __shared__ int s_part[2][PG_N];        // partner of i in the round (i itself: none)
   __shared__ int s_rot[2];               // the round rotates some pair
   __shared__ unsigned s_touch;           // padded indices rotated in some round
+  __shared__ int s_pre;                  // some pair of the task passes the tests on the fresh Gram
   __shared__ int s_any;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwv = blockDim.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
+  if (threadIdx.x == 0) s_pre = 0;
   // global column of padded index k, -1 when there is none
   auto col_of = [&](int k) -> int {
     if (k < 16) return k < wI ? i0 + k : -1;
@@ -2685,7 +2694,25 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
   // round's (from the entries of J^H G J they need, computed as the update
   // computes them), so that each round takes one barrier.
   const int npc = nc + (nc & 1);
-  const int nrounds = round == 0 ? npc - 1 : w;
+  // The task's rounds pair every two real indices (round 0) or every real
+  // index of I with every real index of J (the other rounds).  If no such
+  // pair passes the tests on the fresh Gram, the first round rotates
+  // nothing, G stays as it is, and so on: no round rotates, and the rounds
+  // are skipped.
+  {
+    bool hit = false;
+    for (int e = threadIdx.x; e < PG_N * PG_N; e += blockDim.x) {
+      const int i = e >> 5, j = e & 31;
+      const bool ri = i < 16 ? i < wI : i - 16 < wJ, rj = j < 16 ? j < wI : j - 16 < wJ;
+      const bool inset = ri && rj && (round == 0 ? i < j : (i < 16 && j >= 16));
+      if (inset && pg_active(sG[0][i * PG_N + i].re, sG[0][j * PG_N + j].re, sG[0][i * PG_N + j],
+                             tol, tiny))
+        hit = true;
+    }
+    if (hit) s_pre = 1;
+    __syncthreads();
+  }
+  const int nrounds = !s_pre ? 0 : round == 0 ? npc - 1 : w;
   // rotation of padded index k in round rr from the current G (entries via
   // get(i, j)); writes slot sl
   auto form = [&](int rr, int sl, auto get) {
@@ -2698,8 +2725,8 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
       const int p = isp ? k : part, q = isp ? part : k;
       const double al = get(p, p).re, be = get(q, q).re;
       const cd gq = get(p, q);
-      const double ga2 = gq.re * gq.re + gq.im * gq.im;
-      if (fmin(al, be) > tiny && (ga2 > tol * tol * (al * be)) && (ga2 > 1e-300)) {
+      if (pg_active(al, be, gq, tol, tiny)) {
+        const double ga2 = gq.re * gq.re + gq.im * gq.im;
         const double rga = rsqrt(ga2);
         const double zeta = (be - al) * (0.5 * rga);
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
