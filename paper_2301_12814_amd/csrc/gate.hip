@@ -2560,16 +2560,17 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
   // 1. the Gram tiles (I, I), (I, J), (J, J): wave v takes rows [v R, v R +
   // R) of all three from one set of loads (lane (lr, lk) feeds column lr of
   // each panel at row y + lk; tile entry [i][j] = sum_y conj(X[y][P + i])
-  // X[y][Q + j] lands in lane (lr = j, lk) register r with i = 4 r + lk), the
-  // next 16 rows' loads in flight while the current ones are multiplied; the
-  // four partial Grams are then summed in wave order.
+  // X[y][Q + j] lands in lane (lr = j, lk) register r with i = 4 r + lk), 16
+  // rows' loads in flight together (the registers a second batch would take
+  // hold the third accumulator of the (I, J) block); the four partial Grams
+  // are then summed pairwise.
   {
     const int cI = col_of(lr), cJ = col_of(16 + lr);
     const cd *xi = cI >= 0 ? A + (size_t)cI * m : nullptr;
     const cd *xj = cJ >= 0 ? A + (size_t)cJ * m : nullptr;
     const int R = ((m + 4 * nwv * 4 - 1) / (4 * nwv * 4)) * 16;     // rows per wave, multiple of 16
     const int ya = min(m, wave * R), yb = min(m, ya + R);
-    pg_d4 ar = {0.0, 0.0, 0.0, 0.0}, ai = ar, br = ar, bi = ar, cr = ar, ci = ar;
+    pg_d4 ar = {0.0, 0.0, 0.0, 0.0}, ai = ar, br = ar, bq = ar, bi = ar, cr = ar, ci = ar;
     constexpr int GB = 4;                              // 4-row steps per batch
     cd a[GB], b[GB];
     auto load = [&](int y0, cd *ra, cd *rb) {
@@ -2580,31 +2581,31 @@ __global__ __launch_bounds__(PG_THREADS, 4) void k_panel_gram(Layer ly, int step
         rb[u] = (xj && y < yb) ? xj[y] : cmk(0.0, 0.0);
       }
     };
-    load(ya, a, b);
     for (int y0 = ya; y0 < yb; y0 += 4 * GB) {
-      cd a2[GB], b2[GB];
-      load(y0 + 4 * GB, a2, b2);
+      load(y0, a, b);
 #pragma unroll
       for (int u = 0; u < GB; ++u) {
         // (I, I): conj(a) a; (I, J): conj(a) b; (J, J): conj(b) b.  The
         // diagonal blocks' imaginary parts are M - M^T with M = Re^T Im, so
-        // ai and ci accumulate M alone (ten products per step, not twelve)
+        // ai and ci accumulate M alone; (I, J) takes three products (Gauss:
+        // P = Re Re, Q = Im Im, R = (Re a - Im a)(Re b + Im b); G = P + Q +
+        // i (R - P + Q)): nine products per step, not twelve
         ar = pg_mfma(a[u].re, a[u].re, ar);
         ar = pg_mfma(a[u].im, a[u].im, ar);
         ai = pg_mfma(a[u].re, a[u].im, ai);
         br = pg_mfma(a[u].re, b[u].re, br);
-        br = pg_mfma(a[u].im, b[u].im, br);
-        bi = pg_mfma(a[u].re, b[u].im, bi);
-        bi = pg_mfma(-a[u].im, b[u].re, bi);
+        bq = pg_mfma(a[u].im, b[u].im, bq);
+        bi = pg_mfma(a[u].re - a[u].im, b[u].re + b[u].im, bi);
         cr = pg_mfma(b[u].re, b[u].re, cr);
         cr = pg_mfma(b[u].im, b[u].im, cr);
         ci = pg_mfma(b[u].re, b[u].im, ci);
       }
+    }
 #pragma unroll
-      for (int u = 0; u < GB; ++u) {
-        a[u] = a2[u];
-        b[u] = b2[u];
-      }
+    for (int r = 0; r < 4; ++r) {          // (I, J) from P, Q, R
+      const double p = br[r], q = bq[r];
+      br[r] = p + q;
+      bi[r] = (bi[r] - p) + q;
     }
     // the four partial Grams at the tiles' own positions (upper blocks):
     // G = (v0 + v1) + (v2 + v3), waves 1 and 3 through sG[1] and sG[0],
