@@ -348,7 +348,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (no multi-GPU path); "
+        print("bench.py: the library runs a simulation on one GPU (no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
